@@ -1,0 +1,246 @@
+/*
+ * mnbab.h -- C ABI of the MI355X batched back-substitution engine for
+ * multi-neuron-constraint guided branch-and-bound (MN-BaB, Ferrari et al.,
+ * ICLR 2022, arXiv 2205.00263).
+ *
+ * The library bounds  min_{x in box} C f(x) + c0  for a ReLU network f
+ * (Section 2.1, Eq. 1; the linear property is folded into an extra affine
+ * layer) over many branch-and-bound subproblems at once, by back-substitution
+ * (Section 3.1: Eq. 2 for affine layers, Eq. 5 for ReLU layers, Eq. 6 for the
+ * input box) with optimisable ReLU slopes alpha, split multipliers beta
+ * (Eq. 4) and multi-neuron-constraint multipliers gamma (Eq. 3).
+ *
+ * Conventions
+ *  - Every call returns an int status: MNB_OK (0), MNB_PENDING (1) or a
+ *    negative error code.  mnb_last_error() gives a thread-local message.
+ *    No C++ exception crosses this boundary.
+ *  - Unless stated otherwise pointers are HOST pointers owned by the caller
+ *    and only read during the call (the library copies what it keeps).
+ *    Output arrays are caller-allocated with the documented sizes.
+ *  - Floating point data is IEEE float32, row-major; conv tensors are
+ *    (C, H, W) flattened, weights [Co][Ci][k][k].
+ *  - Device memory is allocated through the installed allocator (default:
+ *    hipMalloc) and work runs on the installed stream (default: a stream the
+ *    library creates).  Calls are synchronous with respect to the host unless
+ *    stated otherwise: they return once their results are in host memory.
+ *  - A device error, or a NaN/Inf reaching a bound, never produces a positive
+ *    (unsound) lower bound: the affected lb is reported as -INFINITY.
+ */
+#ifndef MNBAB_H
+#define MNBAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define MNB_OK 0
+#define MNB_PENDING 1
+#define MNB_EINVAL (-1)   /* invalid argument or shape; nothing was written  */
+#define MNB_ENOMEM (-2)   /* device allocation failed or capacity exhausted  */
+#define MNB_EDEVICE (-3)  /* HIP runtime / kernel error                      */
+#define MNB_ETIMEOUT (-4)
+#define MNB_ESTATE (-5)   /* call not valid in the object's current state    */
+
+const char* mnb_last_error(void);
+
+/* ------------------------------------------------------------------ device plumbing */
+/* Allocator hooks (e.g. a framework's caching allocator).  alloc(bytes, ctx)
+ * returns a device pointer or NULL; free(ptr, ctx) releases it.  Passing NULL
+ * functions restores hipMalloc/hipFree.  Install before creating objects. */
+typedef void* (*mnb_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*mnb_free_fn)(void* ptr, void* ctx);
+int mnb_set_allocator(mnb_alloc_fn alloc, mnb_free_fn free_fn, void* ctx);
+/* Stream the library launches on (a hipStream_t cast to void*); NULL restores
+ * the library's own stream.  Only default-priority streams are supported. */
+int mnb_set_stream(void* hip_stream);
+
+/* ------------------------------------------------------------------ network */
+enum { MNB_INPUT = 0, MNB_FC = 1, MNB_CONV = 2, MNB_RELU = 3, MNB_ADD = 4 };
+
+/* One node of the network DAG (Section 2.1: affine layers zhat = W z + b,
+ * ReLUs z = max(0, zhat); convolutional and residual layers as the paper's
+ * networks use them, Tables 4-5).  Nodes are topologically ordered; node 0 is
+ * MNB_INPUT with out_chw = input shape.  src (and src2 for MNB_ADD) index
+ * earlier nodes.  MNB_FC: W [dout][din], b [dout], din = size of src.
+ * MNB_CONV: W [Co][Ci][k][k], b [Co], stride, pad (zero padding), output
+ * shape derived from the input shape.  MNB_RELU follows an MNB_FC, MNB_CONV
+ * or MNB_ADD node; MNB_ADD joins two affine nodes of equal shape.  The last
+ * node must be MNB_FC (the logits). in_chw/out_chw are checked when nonzero. */
+typedef struct {
+    int kind;
+    int src;
+    int src2;
+    int in_chw[3];
+    int out_chw[3];
+    int k, stride, pad;
+    const float* W;
+    const float* b;
+} mnb_layer;
+
+typedef struct mnb_net mnb_net;
+/* Copies the weights to the device.  Returns MNB_EINVAL for an unsupported
+ * graph or inconsistent shapes. */
+int mnb_net_create(const mnb_layer* layers, int n_layers, mnb_net** out);
+void mnb_net_destroy(mnb_net* net);
+/* Number of ReLU layers and their widths (caller array of n_relu ints). */
+int mnb_net_info(const mnb_net* net, int* n_relu, int* relu_sizes, int* d_in, int* d_out);
+
+/* ------------------------------------------------------------------ multi-neuron constraints */
+/* Constraints  P z + Phat zhat <= p  over the output z and input zhat of ReLU
+ * layer `layer` (Eq. 3), e rows in CSR form over that layer's neurons:
+ * row_ptr [e+1], col [nnz], P [nnz], Phat [nnz], p [e]. */
+typedef struct {
+    int layer;
+    int e;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const float* P;
+    const float* Phat;
+    const float* p;
+} mnb_mnc;
+
+/* ------------------------------------------------------------------ problems */
+/* A problem is a device-resident pool of `capacity` subproblem slots on one
+ * network; every query added to it has n_spec spec rows.  max_mnc bounds the
+ * number of MNC rows per ReLU layer of any query (0: no MNCs). */
+typedef struct mnb_problem mnb_problem;
+int mnb_problem_create(const mnb_net* net, int n_spec, int64_t capacity, int max_mnc,
+                       mnb_problem** out);
+void mnb_problem_destroy(mnb_problem* pb);
+
+/* bound_init: add a query and bound its root with the DeepPoly pass that
+ * precedes optimisation (Section 4 setup): heuristic alpha (1 if u > -l else
+ * 0), beta = gamma = 0; ReLU layer 0 from the exact interval of the first
+ * affine layer; later layers by back-substitution of the rows +-e_j of the
+ * neurons an interval pass does not prove stable, intersected with that
+ * interval.  x_lo/x_hi [d0]: the input box (the L-infinity ball of radius eps
+ * around x0, clipped to the valid range).  C [n_spec][d_out], c0 [n_spec]:
+ * spec rows, bounded as C f(x) + c0.  mnc: n_mnc constraint sets (may be
+ * NULL), used by later bound_optimize calls through gamma.  Outputs: root
+ * subproblem id, lb [n_spec], ub [n_spec] (ub = spec at the input minimising
+ * each row's concretisation, Section 3.1 "Upper Bounding"). */
+int bound_init(mnb_problem* pb, const float* x_lo, const float* x_hi, const float* C,
+               const float* c0, const mnb_mnc* mnc, int n_mnc, int64_t* root_id, float* lb,
+               float* ub);
+
+/* branch_split: two children per (parent, ReLU layer, neuron) (Section 3.2,
+ * "Enforcing Splits"): each copies its parent's state and parameters; the
+ * split entry of S (Eq. 4) is -1 (positive phase, zhat >= 0) in the first
+ * child and +1 (negative phase) in the second, the neuron's bound is
+ * tightened to the phase, its beta is reset to 0, and ReLU layers after the
+ * split layer are marked for recomputation at the next bound_optimize.
+ * child [2n]: ids, positive child first.  Parents stay valid. */
+int branch_split(mnb_problem* pb, const int64_t* parent, const int32_t* layer,
+                 const int32_t* neuron, int n, int64_t* child);
+
+typedef struct {
+    int steps;             /* Adam updates (evaluations = steps + 1)                 */
+    float lr, beta1, beta2, eps;
+    int recompute_intermediate; /* 1: recompute layers after pending splits (Sec. 3.2) */
+    int ckpt_stride;       /* adjoint checkpoint stride over ReLU layers (>=1); 0 = auto */
+    size_t mem_budget;     /* bytes of device workspace per call; 0 = default        */
+} mnb_opt_cfg;
+void mnb_opt_cfg_default(mnb_opt_cfg* cfg);
+
+/* bound_optimize: optimise (alpha, beta, gamma) of n subproblems by projected
+ * Adam ascent (Section 3.1, last paragraphs) with the hand-written adjoint of
+ * back-substitution; one parameter set per (subproblem, objective layer,
+ * direction), shared by the rows of that objective.  Each evaluation first
+ * recomputes, in ascending order, the intermediate bounds of the ReLU layers
+ * after the subproblem's earliest pending split (rows: neurons unstable at
+ * call start; new bounds are intersected with the old), then bounds the spec
+ * rows.  lb/ub [n][n_spec]: best lb over the evaluations (and never below the
+ * subproblem's previous lb) and the spec at that evaluation's minimiser.
+ * branch_layer/branch_neuron [n] (nullable): the unstable, unsplit neuron
+ * with the largest sum over spec rows of |a'_j| * (-u_j l_j / (u_j - l_j))
+ * at the last evaluation (-1 if none). */
+int bound_optimize(mnb_problem* pb, const int64_t* ids, int n, const mnb_opt_cfg* cfg, float* lb,
+                   float* ub, int32_t* branch_layer, int32_t* branch_neuron);
+
+/* Read back a subproblem's intermediate bounds of ReLU layer `layer`
+ * (l, u [d_layer]) and split diagonal S (int8 [d_layer], may be NULL). */
+int mnb_get_bounds(mnb_problem* pb, int64_t id, int layer, float* l, float* u, int8_t* S);
+/* Read / write a parameter set of a subproblem: set 0 = spec rows, set
+ * 2m-1 / 2m = lower / upper bounds of ReLU layer m >= 1.  alpha, beta
+ * [sum of ReLU widths] (layers below the set's objective are used), gamma
+ * [n_relu * max_mnc].  Any pointer may be NULL. */
+int mnb_get_params(mnb_problem* pb, int64_t id, int set, float* alpha, float* beta, float* gamma);
+int mnb_set_params(mnb_problem* pb, int64_t id, int set, const float* alpha, const float* beta,
+                   const float* gamma);
+/* Gradient of a set's objective (sum of its rows' lower bounds) with respect
+ * to the set's alpha, beta and gamma at the subproblem's current parameters
+ * and bounds (the adjoint used by bound_optimize; l/u are not modified).
+ * lb_rows [rows of the set] (nullable), g_alpha/g_beta [sum of ReLU widths],
+ * g_gamma [n_relu * max_mnc]; each nullable.  Returns the row count in *rows. */
+int mnb_bound_grad(mnb_problem* pb, int64_t id, int set, int* rows, float* lb_rows, float* g_alpha,
+                   float* g_beta, float* g_gamma);
+/* Free subproblem slots. */
+int mnb_release(mnb_problem* pb, const int64_t* ids, int n);
+/* Slots in use / capacity. */
+int mnb_problem_usage(const mnb_problem* pb, int64_t* used, int64_t* capacity);
+
+/* ------------------------------------------------------------------ kernel-level entry points */
+/* The back-substitution products on DEVICE pointers (row-major float32),
+ * enqueued on the library stream; mnb_sync() waits for them.
+ * fc_backsub:   C[M, din] (+)= A[M, dout] W[dout, din]      (Eq. 2, W of fc node `node`)
+ * conv_backsub: C[M, Ci*Hi*Wi] (+)= transposed conv of A[M, Co*Ho*Wo] by conv node `node`
+ * fc_forward / conv_forward: C = G W^T + b / conv(G) + b (the adjoint's forward products). */
+int mnb_kernel_fc_backsub(const mnb_net* net, int node, const float* A, float* C, int M, int accumulate);
+int mnb_kernel_conv_backsub(const mnb_net* net, int node, const float* A, float* C, int M, int accumulate);
+int mnb_kernel_fc_forward(const mnb_net* net, int node, const float* G, float* C, int M);
+int mnb_kernel_conv_forward(const mnb_net* net, int node, const float* G, float* C, int M);
+int mnb_sync(void);
+
+/* ------------------------------------------------------------------ serving */
+/* A verification query for the server: box, spec and MNC sets as in
+ * bound_init, plus a per-query wall-clock budget. */
+typedef struct {
+    int net_index;         /* index into the nets the server was created with */
+    const float* x_lo;
+    const float* x_hi;
+    const float* C;
+    const float* c0;
+    int n_spec;
+    const mnb_mnc* mnc;
+    int n_mnc;
+    double timeout_s;
+} mnb_query;
+
+enum { MNB_VERIFIED = 1, MNB_FALSIFIED = 2, MNB_UNKNOWN = 3, MNB_TIMEOUT = 4 };
+
+typedef struct {
+    int verdict;           /* MNB_VERIFIED / MNB_FALSIFIED / MNB_UNKNOWN / MNB_TIMEOUT */
+    float lb;              /* min over spec rows of the root's optimised lb        */
+    int64_t subproblems;   /* subproblems bounded for this query                   */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock            */
+} mnb_result;
+
+typedef struct {
+    mnb_opt_cfg opt;       /* per-batch optimisation settings                      */
+    int max_batch;         /* subproblems per engine step                          */
+    int64_t queue_cap;     /* live subproblems per query before UNKNOWN            */
+    size_t mem_budget;     /* device bytes the admitted queries may hold           */
+} mnb_server_cfg;
+void mnb_server_cfg_default(mnb_server_cfg* cfg);
+
+typedef struct mnb_server mnb_server;
+/* Continuous-batching server: a host thread admits queries as slots and the
+ * memory budget allow, advances every live subproblem batch by one
+ * bound_optimize call per iteration, and branches or retires subproblems
+ * (lb > 0 on every spec row: verified; ub < 0: counterexample). */
+int mnb_server_create(mnb_net* const* nets, int n_nets, const mnb_server_cfg* cfg,
+                      mnb_server** out);
+void mnb_server_destroy(mnb_server* srv);
+/* Non-blocking, thread-safe. */
+int query_submit(mnb_server* srv, const mnb_query* q, uint64_t* ticket);
+/* MNB_PENDING until the query is done; then MNB_OK and *out filled. */
+int query_poll(mnb_server* srv, uint64_t ticket, mnb_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MNBAB_H */

@@ -1,0 +1,281 @@
+"""Python binding of the engine: numpy in, numpy out; every step runs in the HIP library.
+
+Names follow the C ABI (bound_init, branch_split, bound_optimize,
+query_submit, query_poll).  Arrays are converted to contiguous float32 /
+int32 / int64 and handed over as plain pointers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+__all__ = ["Net", "Problem", "use_torch_plumbing", "mnc_to_csr", "set_index"]
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def _ptr(a, ctype=C.c_float):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def set_index(key):
+    """Parameter-set index: 'final' -> 0, (m, +1) -> 2m-1 (lower bounds of ReLU layer m), (m, -1) -> 2m."""
+    if key == "final":
+        return 0
+    m, s = key
+    return 2 * m - 1 if s > 0 else 2 * m
+
+
+# --------------------------------------------------------------------------- plumbing
+_torch_hooks = {}
+
+
+def use_torch_plumbing(enable=True):
+    """Route device allocations through PyTorch's caching allocator and launch on torch's current stream."""
+    L = lib()
+    if not enable:
+        check(L.mnb_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None))
+        check(L.mnb_set_stream(None))
+        _torch_hooks.clear()
+        return
+    import torch
+    stream = torch.cuda.current_stream()
+    dev = torch.cuda.current_device()
+
+    def _alloc(nbytes, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream))
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free)
+    _torch_hooks.update(alloc=a, free=f, stream=stream)
+    check(L.mnb_set_allocator(a, f, None))
+    check(L.mnb_set_stream(C.c_void_p(stream.cuda_stream)))
+
+
+# --------------------------------------------------------------------------- network
+class Net:
+    """A network (node list in the workloads format) copied to the device."""
+
+    def __init__(self, nodes):
+        from workloads import node_shapes  # shapes only
+        shapes = node_shapes(nodes)
+        arr = (_lib.Layer * len(nodes))()
+        keep = []
+        kinds = {"input": _lib.MNB_INPUT, "fc": _lib.MNB_FC, "conv": _lib.MNB_CONV,
+                 "relu": _lib.MNB_RELU, "add": _lib.MNB_ADD}
+        for i, n in enumerate(nodes):
+            L = arr[i]
+            L.kind = kinds[n["kind"]]
+            L.src = n.get("src", -1)
+            L.src2 = n.get("src2", -1)
+            for t in range(3):
+                L.out_chw[t] = shapes[i][t]
+                if i > 0:
+                    L.in_chw[t] = shapes[n["src"]][t]
+            if n["kind"] in ("fc", "conv"):
+                W, b = _f32(n["W"]), _f32(n["b"])
+                keep += [W, b]
+                L.W, L.b = _ptr(W), _ptr(b)
+            if n["kind"] == "conv":
+                L.k = n["W"].shape[2]
+                L.stride, L.pad = n["stride"], n["pad"]
+        h = C.c_void_p()
+        check(lib().mnb_net_create(arr, len(nodes), C.byref(h)))
+        self.h = h
+        self.nodes = nodes
+        nr = C.c_int()
+        sizes = (C.c_int * 64)()
+        d_in, d_out = C.c_int(), C.c_int()
+        check(lib().mnb_net_info(h, C.byref(nr), sizes, C.byref(d_in), C.byref(d_out)))
+        self.relu_sizes = [sizes[i] for i in range(nr.value)]
+        self.d0, self.n_out = d_in.value, d_out.value
+        self.relu_nodes = [i for i, n in enumerate(nodes) if n["kind"] == "relu"]
+
+    @property
+    def n_relu(self):
+        return len(self.relu_sizes)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                lib().mnb_net_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    # kernel-level entry points (device pointers, e.g. torch tensors' data_ptr())
+    def fc_backsub(self, node, A_ptr, C_ptr, M, accumulate=False):
+        check(lib().mnb_kernel_fc_backsub(self.h, node, C.c_void_p(A_ptr), C.c_void_p(C_ptr), M, int(accumulate)))
+
+    def conv_backsub(self, node, A_ptr, C_ptr, M, accumulate=False):
+        check(lib().mnb_kernel_conv_backsub(self.h, node, C.c_void_p(A_ptr), C.c_void_p(C_ptr), M,
+                                            int(accumulate)))
+
+    def fc_forward(self, node, G_ptr, C_ptr, M):
+        check(lib().mnb_kernel_fc_forward(self.h, node, C.c_void_p(G_ptr), C.c_void_p(C_ptr), M))
+
+    def conv_forward(self, node, G_ptr, C_ptr, M):
+        check(lib().mnb_kernel_conv_forward(self.h, node, C.c_void_p(G_ptr), C.c_void_p(C_ptr), M))
+
+    @staticmethod
+    def sync():
+        check(lib().mnb_sync())
+
+
+def mnc_to_csr(P, Phat, p):
+    """Dense (P, Phat, p) of one layer -> CSR arrays over the union of their nonzeros."""
+    P = np.asarray(P, dtype=np.float64)
+    Phat = np.asarray(Phat, dtype=np.float64)
+    e = P.shape[0]
+    row_ptr = [0]
+    cols, pv, hv = [], [], []
+    for r in range(e):
+        nz = np.nonzero((P[r] != 0) | (Phat[r] != 0))[0]
+        cols += list(nz)
+        pv += list(P[r, nz])
+        hv += list(Phat[r, nz])
+        row_ptr.append(len(cols))
+    return (np.asarray(row_ptr, np.int32), np.asarray(cols, np.int32), np.asarray(pv, np.float32),
+            np.asarray(hv, np.float32), np.asarray(p, np.float32))
+
+
+class _MncPack:
+    """ctypes array of mnb_mnc plus the numpy buffers it points into."""
+
+    def __init__(self, mncs):
+        # mncs: dict relu-layer m -> (row_ptr, col, P, Phat, p)
+        self.keep = []
+        self.arr = (_lib.Mnc * max(1, len(mncs)))()
+        for t, (m, (rp, col, P, Ph, p)) in enumerate(sorted(mncs.items())):
+            rp, col = np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(col, np.int32)
+            P, Ph, p = _f32(P), _f32(Ph), _f32(p)
+            self.keep += [rp, col, P, Ph, p]
+            c = self.arr[t]
+            c.layer, c.e = int(m), int(len(p))
+            c.row_ptr, c.col = _ptr(rp, C.c_int32), _ptr(col, C.c_int32)
+            c.P, c.Phat, c.p = _ptr(P), _ptr(Ph), _ptr(p)
+        self.n = len(mncs)
+
+
+# --------------------------------------------------------------------------- problem
+class Problem:
+    """Device-resident pool of subproblems of one network."""
+
+    def __init__(self, net: Net, n_spec: int, capacity: int = 1024, max_mnc: int = 0):
+        self.net = net
+        self.S = int(n_spec)
+        self.max_mnc = int(max_mnc)
+        h = C.c_void_p()
+        check(lib().mnb_problem_create(net.h, self.S, int(capacity), self.max_mnc, C.byref(h)))
+        self.h = h
+        self.total_d = sum(net.relu_sizes)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                lib().mnb_problem_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def bound_init(self, lo, hi, Cm, c0, mncs=None):
+        lo, hi, Cm, c0 = _f32(lo), _f32(hi), _f32(Cm), _f32(c0)
+        assert Cm.shape == (self.S, self.net.n_out)
+        pack = _MncPack(mncs or {})
+        rid = C.c_int64()
+        lb = np.zeros(self.S, np.float32)
+        ub = np.zeros(self.S, np.float32)
+        check(lib().bound_init(self.h, _ptr(lo), _ptr(hi), _ptr(Cm), _ptr(c0),
+                               pack.arr if pack.n else None, pack.n, C.byref(rid), _ptr(lb), _ptr(ub)))
+        return rid.value, lb, ub
+
+    def branch_split(self, parents, layers, neurons):
+        parents = np.ascontiguousarray(parents, np.int64)
+        layers = np.ascontiguousarray(layers, np.int32)
+        neurons = np.ascontiguousarray(neurons, np.int32)
+        n = len(parents)
+        child = np.zeros(2 * n, np.int64)
+        check(lib().branch_split(self.h, _ptr(parents, C.c_int64), _ptr(layers, C.c_int32),
+                                 _ptr(neurons, C.c_int32), n, _ptr(child, C.c_int64)))
+        return child
+
+    @staticmethod
+    def opt_cfg(steps=20, lr=0.1, beta1=0.9, beta2=0.999, eps=1e-8, recompute_intermediate=True,
+                ckpt_stride=0, mem_budget=0):
+        cfg = _lib.OptCfg()
+        lib().mnb_opt_cfg_default(C.byref(cfg))
+        cfg.steps, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = steps, lr, beta1, beta2, eps
+        cfg.recompute_intermediate = int(recompute_intermediate)
+        cfg.ckpt_stride = int(ckpt_stride)
+        cfg.mem_budget = int(mem_budget)
+        return cfg
+
+    def bound_optimize(self, ids, want_branch=False, **kw):
+        ids = np.ascontiguousarray(ids, np.int64)
+        n = len(ids)
+        cfg = self.opt_cfg(**kw)
+        lb = np.zeros((n, self.S), np.float32)
+        ub = np.zeros((n, self.S), np.float32)
+        bl = np.zeros(n, np.int32) if want_branch else None
+        bn = np.zeros(n, np.int32) if want_branch else None
+        check(lib().bound_optimize(self.h, _ptr(ids, C.c_int64), n, C.byref(cfg), _ptr(lb), _ptr(ub),
+                                   _ptr(bl, C.c_int32) if want_branch else None,
+                                   _ptr(bn, C.c_int32) if want_branch else None))
+        if want_branch:
+            return lb, ub, bl, bn
+        return lb, ub
+
+    def get_bounds(self, sid, layer):
+        d = self.net.relu_sizes[layer]
+        l = np.zeros(d, np.float32)
+        u = np.zeros(d, np.float32)
+        S = np.zeros(d, np.int8)
+        check(lib().mnb_get_bounds(self.h, int(sid), int(layer), _ptr(l), _ptr(u), _ptr(S, C.c_int8)))
+        return l, u, S
+
+    def get_params(self, sid, set_idx):
+        a = np.zeros(self.total_d, np.float32)
+        b = np.zeros(self.total_d, np.float32)
+        g = np.zeros(max(1, self.net.n_relu * self.max_mnc), np.float32)
+        check(lib().mnb_get_params(self.h, int(sid), int(set_idx), _ptr(a), _ptr(b), _ptr(g)))
+        return a, b, g[: self.net.n_relu * self.max_mnc]
+
+    def set_params(self, sid, set_idx, alpha=None, beta=None, gamma=None):
+        a = _f32(alpha) if alpha is not None else None
+        b = _f32(beta) if beta is not None else None
+        g = _f32(gamma) if gamma is not None else None
+        check(lib().mnb_set_params(self.h, int(sid), int(set_idx), _ptr(a) if a is not None else None,
+                                   _ptr(b) if b is not None else None, _ptr(g) if g is not None else None))
+
+    def bound_grad(self, sid, set_idx):
+        rows = C.c_int()
+        lbr = np.zeros(max(self.S, max(self.net.relu_sizes) * 1), np.float32)
+        ga = np.zeros(self.total_d, np.float32)
+        gb = np.zeros(self.total_d, np.float32)
+        gg = np.zeros(max(1, self.net.n_relu * self.max_mnc), np.float32)
+        check(lib().mnb_bound_grad(self.h, int(sid), int(set_idx), C.byref(rows), _ptr(lbr), _ptr(ga), _ptr(gb),
+                                   _ptr(gg)))
+        return lbr[: rows.value], ga, gb, gg[: self.net.n_relu * self.max_mnc]
+
+    def release(self, ids):
+        ids = np.ascontiguousarray(ids, np.int64)
+        check(lib().mnb_release(self.h, _ptr(ids, C.c_int64), len(ids)))
+
+    def usage(self):
+        u, c = C.c_int64(), C.c_int64()
+        check(lib().mnb_problem_usage(self.h, C.byref(u), C.byref(c)))
+        return u.value, c.value

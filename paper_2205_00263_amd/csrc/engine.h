@@ -1,0 +1,105 @@
+// Host-side engine objects behind the C ABI.
+#pragma once
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mnbab.h"
+#include "kernels.h"
+
+namespace mnb {
+
+// ---------------------------------------------------------------- device memory / stream
+void* dalloc(size_t bytes);
+void dfree(void* p);
+hipStream_t stream();
+
+// Grow-only named device buffers; growing synchronises the stream first.
+struct Workspace {
+    struct Buf {
+        void* p = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Buf> bufs;
+    template <class T>
+    T* get(const std::string& name, size_t count) {
+        size_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 16;
+        Buf& b = bufs[name];
+        if (b.bytes < bytes) {
+            if (b.p) {
+                MNB_HIP(hipStreamSynchronize(stream()));
+                dfree(b.p);
+            }
+            size_t nb = bytes + bytes / 8 + 256;
+            b.p = dalloc(nb);
+            b.bytes = nb;
+        }
+        return (T*)b.p;
+    }
+    size_t total() const {
+        size_t t = 0;
+        for (auto& kv : bufs) t += kv.second.bytes;
+        return t;
+    }
+    ~Workspace() {
+        for (auto& kv : bufs)
+            if (kv.second.p) dfree(kv.second.p);
+    }
+};
+
+struct NetNode {
+    int kind = 0, src = -1, src2 = -1;
+    int C = 0, H = 0, W = 0, size = 0;
+    int k = 0, stride = 1, pad = 0;
+    float* Wd = nullptr;
+    float* bd = nullptr;
+    ConvGeom geom{};
+    int relu_m = -1;
+};
+
+}  // namespace mnb
+
+struct mnb_net {
+    std::vector<mnb::NetNode> nodes;
+    std::vector<int> relus, relu_d, relu_off;
+    std::vector<float*> relu_bias;   // effective bias of each ReLU's input node, expanded [d]
+    std::vector<void*> owned;
+    int total_d = 0, d0 = 0, n_out = 0, last = 0, max_width = 0;
+    ~mnb_net();
+};
+
+struct mnb_problem {
+    mnb_net* net = nullptr;
+    int S = 0, R = 0, n_sets = 0, e_cap = 0;
+    int64_t cap = 0;
+    long ld_state = 0, ld_param = 0, ld_gamma = 0;
+    // per-slot device arrays
+    float *l = nullptr, *u = nullptr, *alpha = nullptr, *beta = nullptr, *gamma = nullptr;
+    int8_t* S_ = nullptr;
+    int32_t* qid = nullptr;
+    float* lb = nullptr;   // [cap, S] reported lb
+    // host mirrors
+    std::vector<int> recompute_from, slot_query;
+    std::vector<char> used;
+    std::vector<int64_t> free_list;
+    int64_t n_used = 0;
+    // queries (device, growable)
+    int n_query = 0, q_cap = 0;
+    float *lo = nullptr, *hi = nullptr, *Chat = nullptr, *chat = nullptr, *C = nullptr, *c0 = nullptr;
+    // MNC per layer: arrays [q_cap][...] per layer
+    struct MncLayer {
+        int* e_of = nullptr;
+        int *colptr = nullptr, *col_e = nullptr, *rowptr = nullptr, *row_j = nullptr;
+        float *col_P = nullptr, *col_Ph = nullptr, *row_P = nullptr, *row_Ph = nullptr, *p = nullptr;
+    };
+    std::vector<MncLayer> mnc;
+    int nnz_cap = 0;
+    bool has_mnc = false;
+    std::vector<void*> owned;
+    mnb::Workspace ws;
+    std::mutex mu;
+    ~mnb_problem();
+};

@@ -1,0 +1,856 @@
+// Host engine: network and problem state on the device, the back-substitution
+// passes, their adjoint, and the C ABI of include/mnbab.h.
+#include "engine.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+
+using namespace mnb;
+
+// =====================================================================================
+// errors, allocator, stream
+// =====================================================================================
+namespace mnb {
+static thread_local std::string t_err;
+void set_error(int code, const std::string& msg) {
+    (void)code;
+    t_err = msg;
+}
+
+static mnb_alloc_fn g_alloc = nullptr;
+static mnb_free_fn g_free = nullptr;
+static void* g_ctx = nullptr;
+static hipStream_t g_user_stream = nullptr;
+static hipStream_t g_own_stream = nullptr;
+static std::mutex g_mu;
+
+void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (g_alloc) {
+        p = g_alloc(bytes, g_ctx);
+        if (!p) throw Error{MNB_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes"};
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess)
+            throw Error{MNB_ENOMEM, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e)};
+    }
+    return p;
+}
+void dfree(void* p) {
+    if (!p) return;
+    if (g_free)
+        g_free(p, g_ctx);
+    else
+        (void)hipFree(p);
+}
+hipStream_t stream() {
+    if (g_user_stream) return g_user_stream;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_own_stream) MNB_HIP(hipStreamCreateWithFlags(&g_own_stream, hipStreamNonBlocking));
+    return g_own_stream;
+}
+
+// Host-to-device copy that has completed when it returns (sources are often temporaries).
+static void h2d(void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    MNB_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream()));
+    MNB_HIP(hipStreamSynchronize(stream()));
+}
+
+template <class T>
+static T* upload(const T* h, size_t n, std::vector<void*>* owned) {
+    T* d = (T*)dalloc(std::max<size_t>(n * sizeof(T), 16));
+    if (n) h2d(d, h, n * sizeof(T));
+    if (owned) owned->push_back(d);
+    return d;
+}
+static void sync() { MNB_HIP(hipStreamSynchronize(stream())); }
+}  // namespace mnb
+
+#define API_BEGIN try {
+#define API_END                                  \
+    }                                            \
+    catch (const mnb::Error& e) {                \
+        mnb::t_err = e.msg;                      \
+        return e.code;                           \
+    }                                            \
+    catch (const std::exception& e) {            \
+        mnb::t_err = e.what();                   \
+        return MNB_EDEVICE;                      \
+    }                                            \
+    return MNB_OK;
+
+extern "C" const char* mnb_last_error(void) { return mnb::t_err.c_str(); }
+
+extern "C" int mnb_set_allocator(mnb_alloc_fn a, mnb_free_fn f, void* ctx) {
+    if ((a == nullptr) != (f == nullptr)) {
+        t_err = "allocator and free must both be set or both be NULL";
+        return MNB_EINVAL;
+    }
+    g_alloc = a;
+    g_free = f;
+    g_ctx = ctx;
+    return MNB_OK;
+}
+extern "C" int mnb_set_stream(void* s) {
+    g_user_stream = (hipStream_t)s;
+    return MNB_OK;
+}
+
+// =====================================================================================
+// network
+// =====================================================================================
+mnb_net::~mnb_net() {
+    for (void* p : owned) dfree(p);
+}
+
+static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>& Wh) {
+    const NetNode& in = net->nodes[nd.src];
+    ConvGeom& g = nd.geom;
+    g.Ci = in.C; g.Hi = in.H; g.Wi = in.W;
+    g.Co = nd.C; g.Ho = nd.H; g.Wo = nd.W;
+    g.k = nd.k; g.s = nd.stride; g.p = nd.pad;
+    g.W = nd.Wd; g.b = nd.bd;
+    const int k = g.k, s = g.s;
+    // forward gather table
+    std::vector<int2> ft(g.Ci * k * k);
+    for (int ci = 0; ci < g.Ci; ++ci)
+        for (int ky = 0; ky < k; ++ky)
+            for (int kx = 0; kx < k; ++kx)
+                ft[(ci * k + ky) * k + kx] = make_int2(ci * g.Hi * g.Wi + ky * g.Wi + kx, (ky << 16) | kx);
+    g.fwd_ktab = upload(ft.data(), ft.size(), &net->owned);
+    // stride phases of the transposed convolution
+    MNB_CHECK(s * s <= 16, MNB_EINVAL, "conv stride above 4 is not supported");
+    g.n_phase = 0;
+    for (int ry = 0; ry < s; ++ry)
+        for (int rx = 0; rx < s; ++rx) {
+            ConvPhase ph{};
+            ph.rho_y = ry; ph.rho_x = rx;
+            ph.Y0 = ((ry - g.p) % s + s) % s;
+            ph.X0 = ((rx - g.p) % s + s) % s;
+            ph.nY = ph.Y0 < g.Hi ? (g.Hi - ph.Y0 + s - 1) / s : 0;
+            ph.nX = ph.X0 < g.Wi ? (g.Wi - ph.X0 + s - 1) / s : 0;
+            ph.Ty = ry < k ? (k - ry + s - 1) / s : 0;
+            ph.Tx = rx < k ? (k - rx + s - 1) / s : 0;
+            ph.q0y = (ph.Y0 + g.p - ry) / s;
+            ph.q0x = (ph.X0 + g.p - rx) / s;
+            const int T = ph.Ty * ph.Tx;
+            if (T > 0) {
+                std::vector<float> wp((size_t)g.Co * T * g.Ci);
+                std::vector<int2> kt((size_t)g.Co * T);
+                for (int co = 0; co < g.Co; ++co)
+                    for (int ty = 0; ty < ph.Ty; ++ty)
+                        for (int tx = 0; tx < ph.Tx; ++tx) {
+                            const int kk = (co * ph.Ty + ty) * ph.Tx + tx;
+                            kt[kk] = make_int2(co * g.Ho * g.Wo - ty * g.Wo - tx, (ty << 16) | tx);
+                            for (int ci = 0; ci < g.Ci; ++ci)
+                                wp[(size_t)kk * g.Ci + ci] =
+                                    Wh[(((size_t)co * g.Ci + ci) * k + (ry + s * ty)) * k + (rx + s * tx)];
+                        }
+                ph.Wp = upload(wp.data(), wp.size(), &net->owned);
+                ph.ktab = upload(kt.data(), kt.size(), &net->owned);
+            }
+            g.ph[g.n_phase++] = ph;
+        }
+}
+
+extern "C" int mnb_net_create(const mnb_layer* L, int n, mnb_net** out) {
+    API_BEGIN
+    MNB_CHECK(L && out && n >= 2, MNB_EINVAL, "need at least an input and one layer");
+    MNB_CHECK(L[0].kind == MNB_INPUT, MNB_EINVAL, "node 0 must be MNB_INPUT");
+    auto net = new mnb_net();
+    try {
+        net->nodes.resize(n);
+        for (int i = 0; i < n; ++i) {
+            NetNode& nd = net->nodes[i];
+            const mnb_layer& l = L[i];
+            nd.kind = l.kind;
+            nd.src = l.src;
+            nd.src2 = l.src2;
+            if (i == 0) {
+                nd.C = l.out_chw[0]; nd.H = l.out_chw[1]; nd.W = l.out_chw[2];
+                MNB_CHECK(nd.C > 0 && nd.H > 0 && nd.W > 0, MNB_EINVAL, "bad input shape");
+            } else {
+                MNB_CHECK(l.src >= 0 && l.src < i, MNB_EINVAL, "node " + std::to_string(i) + ": bad src");
+                const NetNode& in = net->nodes[l.src];
+                switch (l.kind) {
+                    case MNB_FC: {
+                        MNB_CHECK(l.out_chw[0] > 0 && l.W && l.b, MNB_EINVAL, "fc: need out_chw[0], W, b");
+                        nd.C = l.out_chw[0]; nd.H = 1; nd.W = 1;
+                        const int din = in.C * in.H * in.W;
+                        nd.Wd = upload(l.W, (size_t)nd.C * din, &net->owned);
+                        nd.bd = upload(l.b, (size_t)nd.C, &net->owned);
+                        break;
+                    }
+                    case MNB_CONV: {
+                        MNB_CHECK(l.k > 0 && l.stride > 0 && l.pad >= 0 && l.W && l.b && l.out_chw[0] > 0,
+                                  MNB_EINVAL, "conv: need k, stride, pad, W, b, out channels");
+                        MNB_CHECK(in.C == l.in_chw[0] || l.in_chw[0] == 0, MNB_EINVAL, "conv: in channels");
+                        nd.k = l.k; nd.stride = l.stride; nd.pad = l.pad;
+                        nd.C = l.out_chw[0];
+                        nd.H = (in.H + 2 * l.pad - l.k) / l.stride + 1;
+                        nd.W = (in.W + 2 * l.pad - l.k) / l.stride + 1;
+                        MNB_CHECK(nd.H > 0 && nd.W > 0, MNB_EINVAL, "conv: empty output");
+                        if (l.out_chw[1]) MNB_CHECK(l.out_chw[1] == nd.H && l.out_chw[2] == nd.W, MNB_EINVAL,
+                                                    "conv: output shape mismatch");
+                        size_t nw = (size_t)nd.C * in.C * l.k * l.k;
+                        std::vector<float> Wh(l.W, l.W + nw);
+                        nd.Wd = upload(l.W, nw, &net->owned);
+                        nd.bd = upload(l.b, (size_t)nd.C, &net->owned);
+                        build_conv_geom(net, nd, Wh);
+                        break;
+                    }
+                    case MNB_RELU:
+                        MNB_CHECK(in.kind == MNB_FC || in.kind == MNB_CONV || in.kind == MNB_ADD, MNB_EINVAL,
+                                  "relu must follow fc, conv or add");
+                        nd.C = in.C; nd.H = in.H; nd.W = in.W;
+                        nd.relu_m = (int)net->relus.size();
+                        net->relus.push_back(i);
+                        break;
+                    case MNB_ADD: {
+                        MNB_CHECK(l.src2 >= 0 && l.src2 < i && l.src2 != l.src, MNB_EINVAL, "add: bad src2");
+                        const NetNode& in2 = net->nodes[l.src2];
+                        MNB_CHECK((in.kind == MNB_FC || in.kind == MNB_CONV) &&
+                                      (in2.kind == MNB_FC || in2.kind == MNB_CONV),
+                                  MNB_EINVAL, "add joins two affine nodes");
+                        MNB_CHECK(in.C == in2.C && in.H == in2.H && in.W == in2.W, MNB_EINVAL,
+                                  "add: shape mismatch");
+                        MNB_CHECK(in.src != in2.src, MNB_EINVAL, "add: both operands read the same node");
+                        nd.C = in.C; nd.H = in.H; nd.W = in.W;
+                        break;
+                    }
+                    default:
+                        throw Error{MNB_EINVAL, "unsupported node kind " + std::to_string(l.kind)};
+                }
+            }
+            nd.size = nd.C * nd.H * nd.W;
+            net->max_width = std::max(net->max_width, nd.size);
+        }
+        net->last = n - 1;
+        MNB_CHECK(net->nodes[n - 1].kind == MNB_FC, MNB_EINVAL, "last node must be MNB_FC");
+        // every affine/add node must have exactly one consumer (ReLU / ADD / the spec)
+        std::vector<int> cons(n, 0);
+        for (int i = 1; i < n; ++i) {
+            cons[net->nodes[i].src]++;
+            if (net->nodes[i].kind == MNB_ADD) cons[net->nodes[i].src2]++;
+        }
+        for (int i = 1; i < n - 1; ++i) {
+            int kd = net->nodes[i].kind;
+            if (kd == MNB_FC || kd == MNB_CONV || kd == MNB_ADD)
+                MNB_CHECK(cons[i] == 1, MNB_EINVAL, "affine node " + std::to_string(i) + " needs exactly one consumer");
+        }
+        net->d0 = net->nodes[0].size;
+        net->n_out = net->nodes[n - 1].size;
+        int off = 0;
+        for (int i : net->relus) {
+            net->relu_d.push_back(net->nodes[i].size);
+            net->relu_off.push_back(off);
+            off += net->nodes[i].size;
+            // effective bias of the node feeding this ReLU
+            const NetNode& s = net->nodes[net->nodes[i].src];
+            std::vector<float> bias(s.size, 0.f), tmp;
+            auto add_bias = [&](const NetNode& a) {
+                std::vector<float> bh(a.C);
+                MNB_HIP(hipMemcpy(bh.data(), a.bd, a.C * sizeof(float), hipMemcpyDeviceToHost));
+                for (int c = 0; c < a.C; ++c)
+                    for (int q = 0; q < a.H * a.W; ++q) bias[c * a.H * a.W + q] += bh[c];
+            };
+            MNB_HIP(hipStreamSynchronize(stream()));
+            if (s.kind == MNB_ADD) {
+                add_bias(net->nodes[s.src]);
+                add_bias(net->nodes[s.src2]);
+            } else {
+                add_bias(s);
+            }
+            net->relu_bias.push_back(upload(bias.data(), bias.size(), &net->owned));
+        }
+        net->total_d = off;
+        MNB_CHECK(!net->relus.empty(), MNB_EINVAL, "network without ReLU layers");
+        sync();
+    } catch (...) {
+        delete net;
+        throw;
+    }
+    *out = net;
+    API_END
+}
+
+extern "C" void mnb_net_destroy(mnb_net* net) {
+    if (!net) return;
+    try {
+        sync();
+    } catch (...) {
+    }
+    delete net;
+}
+
+extern "C" int mnb_net_info(const mnb_net* net, int* n_relu, int* relu_sizes, int* d_in, int* d_out) {
+    API_BEGIN
+    MNB_CHECK(net, MNB_EINVAL, "null net");
+    if (n_relu) *n_relu = (int)net->relus.size();
+    if (relu_sizes)
+        for (size_t m = 0; m < net->relus.size(); ++m) relu_sizes[m] = net->relu_d[m];
+    if (d_in) *d_in = net->d0;
+    if (d_out) *d_out = net->n_out;
+    API_END
+}
+
+// =====================================================================================
+// problem
+// =====================================================================================
+mnb_problem::~mnb_problem() {
+    for (void* p : owned) dfree(p);
+}
+
+static long pad16(long x) { return (x + 15) / 16 * 16; }
+
+static void grow_queries(mnb_problem* pb) {
+    int nc = std::max(4, pb->q_cap * 2);
+    mnb_net* net = pb->net;
+    const int S = pb->S, dl = net->nodes[net->nodes[net->last].src].size;
+    auto regrow = [&](float*& p, long per) {
+        float* np_ = (float*)dalloc(std::max<long>((long)nc * per * 4, 16));
+        if (p) {
+            MNB_HIP(hipMemcpyAsync(np_, p, (size_t)pb->q_cap * per * 4, hipMemcpyDeviceToDevice, stream()));
+        }
+        sync();
+        if (p) {
+            auto it = std::find(pb->owned.begin(), pb->owned.end(), (void*)p);
+            if (it != pb->owned.end()) pb->owned.erase(it);
+            dfree(p);
+        }
+        pb->owned.push_back(np_);
+        p = np_;
+    };
+    auto regrow_i = [&](int*& p, long per) {
+        float* f = (float*)p;
+        regrow(f, per);
+        p = (int*)f;
+    };
+    regrow(pb->lo, net->d0);
+    regrow(pb->hi, net->d0);
+    regrow(pb->Chat, (long)S * dl);
+    regrow(pb->chat, S);
+    regrow(pb->C, (long)S * net->n_out);
+    regrow(pb->c0, S);
+    if (pb->has_mnc) {
+        for (int m = 0; m < pb->R; ++m) {
+            auto& ml = pb->mnc[m];
+            const int d = net->relu_d[m];
+            regrow_i(ml.e_of, 1);
+            regrow_i(ml.colptr, d + 1);
+            regrow_i(ml.col_e, pb->nnz_cap);
+            regrow(ml.col_P, pb->nnz_cap);
+            regrow(ml.col_Ph, pb->nnz_cap);
+            regrow_i(ml.rowptr, pb->e_cap + 1);
+            regrow_i(ml.row_j, pb->nnz_cap);
+            regrow(ml.row_P, pb->nnz_cap);
+            regrow(ml.row_Ph, pb->nnz_cap);
+            regrow(ml.p, pb->e_cap);
+        }
+    }
+    pb->q_cap = nc;
+}
+
+extern "C" int mnb_problem_create(const mnb_net* net, int n_spec, int64_t capacity, int max_mnc,
+                                  mnb_problem** out) {
+    API_BEGIN
+    MNB_CHECK(net && out && n_spec > 0 && capacity > 0 && max_mnc >= 0, MNB_EINVAL, "bad problem arguments");
+    auto pb = new mnb_problem();
+    try {
+        pb->net = (mnb_net*)net;
+        pb->S = n_spec;
+        pb->cap = capacity;
+        pb->R = (int)net->relus.size();
+        pb->n_sets = 2 * pb->R - 1;
+        pb->e_cap = max_mnc;
+        pb->has_mnc = max_mnc > 0;
+        pb->nnz_cap = 4 * max_mnc;
+        pb->ld_state = pad16(net->total_d);
+        pb->ld_param = pb->ld_state;
+        pb->ld_gamma = pad16((long)pb->R * max_mnc);
+        const long cap = capacity;
+        auto A = [&](size_t bytes) {
+            void* p = dalloc(std::max<size_t>(bytes, 16));
+            pb->owned.push_back(p);
+            return p;
+        };
+        pb->l = (float*)A(cap * pb->ld_state * 4);
+        pb->u = (float*)A(cap * pb->ld_state * 4);
+        pb->S_ = (int8_t*)A(cap * pb->ld_state);
+        pb->alpha = (float*)A(cap * pb->n_sets * pb->ld_param * 4);
+        pb->beta = (float*)A(cap * pb->n_sets * pb->ld_param * 4);
+        pb->gamma = (float*)A(cap * pb->n_sets * pb->ld_gamma * 4);
+        pb->qid = (int32_t*)A(cap * 4);
+        pb->lb = (float*)A(cap * pb->S * 4);
+        pb->recompute_from.assign(cap, pb->R);
+        pb->slot_query.assign(cap, -1);
+        pb->used.assign(cap, 0);
+        for (int64_t s = cap - 1; s >= 0; --s) pb->free_list.push_back(s);
+        pb->mnc.resize(pb->R);
+        grow_queries(pb);
+    } catch (...) {
+        delete pb;
+        throw;
+    }
+    *out = pb;
+    API_END
+}
+
+extern "C" void mnb_problem_destroy(mnb_problem* pb) {
+    if (!pb) return;
+    try {
+        sync();
+    } catch (...) {
+    }
+    delete pb;
+}
+
+static int64_t alloc_slot(mnb_problem* pb) {
+    if (pb->free_list.empty()) throw Error{MNB_ENOMEM, "problem capacity exhausted"};
+    int64_t s = pb->free_list.back();
+    pb->free_list.pop_back();
+    pb->used[s] = 1;
+    pb->n_used++;
+    return s;
+}
+static void check_id(mnb_problem* pb, int64_t id) {
+    MNB_CHECK(id >= 0 && id < pb->cap && pb->used[id], MNB_EINVAL, "invalid subproblem id " + std::to_string(id));
+}
+
+extern "C" int mnb_release(mnb_problem* pb, const int64_t* ids, int n) {
+    API_BEGIN
+    MNB_CHECK(pb && (ids || n == 0), MNB_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(pb->mu);
+    for (int i = 0; i < n; ++i) check_id(pb, ids[i]);
+    for (int i = 0; i < n; ++i) {
+        if (!pb->used[ids[i]]) continue;   // duplicate within the call
+        pb->used[ids[i]] = 0;
+        pb->free_list.push_back(ids[i]);
+        pb->n_used--;
+    }
+    API_END
+}
+
+extern "C" int mnb_problem_usage(const mnb_problem* pb, int64_t* used, int64_t* capacity) {
+    API_BEGIN
+    MNB_CHECK(pb, MNB_EINVAL, "null problem");
+    if (used) *used = pb->n_used;
+    if (capacity) *capacity = pb->cap;
+    API_END
+}
+
+// =====================================================================================
+// passes
+// =====================================================================================
+namespace {
+
+struct PassChunk {
+    int M = 0;                  // rows
+    const RowDesc* rows = nullptr;   // device, chunk-relative row order
+    std::vector<InstDesc> inst;      // host, rows relative to the chunk
+    InstDesc* inst_d = nullptr;
+    int obj_layer = -1;         // ReLU layer of the objective, -1: spec rows
+};
+
+// A pool of [M, max_width] coefficient buffers with reference counts.
+struct BufPool {
+    std::vector<float*> bufs;
+    std::vector<int> ref;
+    float* acquire() {
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (ref[i] == 0) {
+                ref[i] = 1;
+                return bufs[i];
+            }
+        throw Error{MNB_EDEVICE, "coefficient buffer pool exhausted"};
+    }
+    void retain(float* p) {
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (bufs[i] == p) ref[i]++;
+    }
+    void release(float* p) {
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (bufs[i] == p) ref[i]--;
+    }
+};
+
+struct PassCtx {
+    mnb_problem* pb;
+    const int32_t* slots_d;   // local b -> global slot
+    float* c;                 // [M]
+    float* cpart; int ldcp;
+    int ncp = 0;
+    std::map<int, float*> ap; // relu node -> a' rows [M, d] (nullable)
+    float* G0 = nullptr;      // [M, d0]
+    uint8_t* xbits = nullptr; // [M, d0]
+    // gamma projections per relu layer: v, vhat [n_inst, d], gp [n_inst]
+    std::map<int, float*> v, vh, gp;
+};
+
+static int fold_cols(int d) { return cdiv(d, 256) * 4; }
+
+// Total partial-constant columns of a pass whose rows start at node `top`.
+static int pass_cols(const mnb_net* net, int top) {
+    int cols = 0;
+    for (int i : net->relus)
+        if (i <= top) cols += fold_cols(net->nodes[i].size);
+    return std::max(cols, 1);
+}
+
+static int pass_top(const mnb_net* net, int obj_layer) {
+    if (obj_layer < 0) return net->nodes[net->last].src;
+    const NetNode& o = net->nodes[net->nodes[net->relus[obj_layer]].src];
+    if (o.kind == MNB_ADD) return std::max(net->nodes[o.src].src, net->nodes[o.src2].src);
+    return o.src;
+}
+
+// Back-substitute a chunk of rows from its objective down to the input (Eq. 2 and
+// Eq. 5 per node, in reverse topological order) and leave the input coefficients
+// in the returned buffer.
+static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool store_ap) {
+    mnb_problem* pb = cx.pb;
+    mnb_net* net = pb->net;
+    hipStream_t st = stream();
+    const int M = ch.M;
+    std::map<int, float*> coef;
+    int top;
+    if (ch.obj_layer < 0) {
+        top = net->nodes[net->last].src;
+        float* A = pool.acquire();
+        const int d = net->nodes[top].size;
+        launch_init_spec(ch.rows, M, cx.slots_d, pb->qid, pb->Chat, pb->chat, pb->S, d, A, cx.c, st);
+        coef[top] = A;
+    } else {
+        const int ri = net->relus[ch.obj_layer];
+        const int on = net->nodes[ri].src;
+        const NetNode& o = net->nodes[on];
+        const float* be = net->relu_bias[ch.obj_layer];
+        auto init_aff = [&](int n, bool write_c) {
+            const NetNode& a = net->nodes[n];
+            float* A = pool.acquire();
+            if (a.kind == MNB_FC)
+                launch_init_fc(ch.rows, M, a.Wd, be, net->nodes[a.src].size, A, cx.c, write_c, st);
+            else
+                launch_init_conv(ch.rows, M, a.geom, be, A, cx.c, write_c, st);
+            MNB_CHECK(!coef.count(a.src), MNB_EINVAL, "objective operands share a producer");
+            coef[a.src] = A;
+        };
+        if (o.kind == MNB_ADD) {
+            init_aff(o.src, true);
+            init_aff(o.src2, false);
+        } else {
+            init_aff(on, true);
+        }
+        top = pass_top(net, ch.obj_layer);
+    }
+    int col = 0;
+    for (int n = top; n >= 1; --n) {
+        auto it = coef.find(n);
+        if (it == coef.end()) continue;
+        float* a = it->second;
+        coef.erase(it);
+        const NetNode& nd = net->nodes[n];
+        switch (nd.kind) {
+            case MNB_FC:
+            case MNB_CONV: {
+                const int dst = nd.src;
+                bool acc = coef.count(dst) > 0;
+                float* out = acc ? coef[dst] : pool.acquire();
+                if (nd.kind == MNB_FC)
+                    launch_fc_backsub(a, nd.Wd, out, M, nd.size, net->nodes[dst].size, acc, st);
+                else
+                    launch_conv_backsub(nd.geom, a, out, M, acc, st);
+                coef[dst] = out;
+                pool.release(a);
+                break;
+            }
+            case MNB_RELU: {
+                const int m = nd.relu_m;
+                FoldArgs fa{};
+                fa.A = a;
+                fa.Ap = store_ap ? cx.ap.at(n) : nullptr;
+                fa.cpart = cx.cpart; fa.ldcp = cx.ldcp; fa.col_off = col;
+                fa.inst = ch.inst_d; fa.n_inst = (int)ch.inst.size();
+                fa.slots = cx.slots_d;
+                fa.M = M; fa.d = nd.size;
+                fa.l = pb->l + net->relu_off[m]; fa.u = pb->u + net->relu_off[m];
+                fa.S = pb->S_ + net->relu_off[m]; fa.ld_state = pb->ld_state;
+                fa.alpha = pb->alpha + net->relu_off[m]; fa.beta = pb->beta + net->relu_off[m];
+                fa.ld_param = pb->ld_param; fa.n_sets = pb->n_sets;
+                fa.v = cx.v.count(m) ? cx.v[m] : nullptr;
+                fa.vhat = cx.vh.count(m) ? cx.vh[m] : nullptr;
+                fa.bias = net->relu_bias[m];
+                launch_relu_fold(fa, st, cx.gp.count(m) ? cx.gp[m] : nullptr);
+                col += fold_cols(nd.size);
+                MNB_CHECK(!coef.count(nd.src), MNB_EDEVICE, "relu input reached twice");
+                coef[nd.src] = a;
+                break;
+            }
+            case MNB_ADD: {
+                coef[nd.src] = a;
+                MNB_CHECK(!coef.count(nd.src2), MNB_EDEVICE, "add operand reached twice");
+                coef[nd.src2] = a;
+                pool.retain(a);
+                break;
+            }
+            default:
+                throw Error{MNB_EDEVICE, "unexpected node in back-substitution"};
+        }
+    }
+    cx.ncp = col;
+    MNB_CHECK(coef.size() == 1 && coef.count(0), MNB_EDEVICE, "back-substitution did not reach the input");
+    return coef[0];
+}
+
+// Adjoint of a pass: push x* forward through every row's relaxation and reduce
+// the parameter gradients of each instance.
+static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* g_alpha, float* g_beta,
+                        float* g_gamma, float* gs_hat, float* gs_out) {
+    mnb_problem* pb = cx.pb;
+    mnb_net* net = pb->net;
+    hipStream_t st = stream();
+    const int M = ch.M;
+    const int top = pass_top(net, ch.obj_layer);
+    const int n_inst = (int)ch.inst.size();
+    std::vector<float*> g(net->nodes.size(), nullptr);
+    std::vector<int> uses(net->nodes.size(), 0);
+    for (int n = 1; n <= top; ++n) {
+        uses[net->nodes[n].src]++;
+        if (net->nodes[n].kind == MNB_ADD) uses[net->nodes[n].src2]++;
+    }
+    g[0] = cx.G0;
+    auto done_with = [&](int n) {
+        if (--uses[n] == 0 && n != 0) pool.release(g[n]);
+    };
+    for (int n = 1; n <= top; ++n) {
+        const NetNode& nd = net->nodes[n];
+        switch (nd.kind) {
+            case MNB_FC:
+            case MNB_CONV: {
+                float* out = pool.acquire();
+                if (nd.kind == MNB_FC)
+                    launch_fc_forward(g[nd.src], nd.Wd, nd.bd, out, M, net->nodes[nd.src].size, nd.size, false, st);
+                else
+                    launch_conv_forward(nd.geom, g[nd.src], out, M, false, st);
+                g[n] = out;
+                done_with(nd.src);
+                break;
+            }
+            case MNB_ADD: {
+                float* out = g[nd.src];
+                launch_add2(g[nd.src], g[nd.src2], out, (long)M * nd.size, st);
+                g[n] = out;
+                pool.retain(out);
+                done_with(nd.src);
+                done_with(nd.src2);
+                break;
+            }
+            case MNB_RELU: {
+                const int m = nd.relu_m;
+                float* G = g[nd.src];
+                RelaxArgs ra{};
+                ra.G = G;
+                ra.Ap = cx.ap.at(n);
+                ra.inst = ch.inst_d; ra.n_inst = n_inst;
+                ra.slots = cx.slots_d;
+                ra.M = M; ra.d = nd.size;
+                ra.l = pb->l + net->relu_off[m]; ra.u = pb->u + net->relu_off[m];
+                ra.S = pb->S_ + net->relu_off[m]; ra.ld_state = pb->ld_state;
+                ra.alpha = pb->alpha + net->relu_off[m]; ra.ld_param = pb->ld_param; ra.n_sets = pb->n_sets;
+                ra.d_alpha = g_alpha; ra.d_beta = g_beta; ra.ldg = pb->ld_param; ra.goff = net->relu_off[m];
+                const bool mnc = pb->has_mnc;
+                ra.gsum_hat = mnc ? gs_hat : nullptr;
+                ra.gsum_out = mnc ? gs_out : nullptr;
+                launch_relu_relax(ra, st);
+                if (mnc) {
+                    auto& ml = pb->mnc[m];
+                    GammaArgs ga{};
+                    ga.inst = ch.inst_d; ga.n_inst = n_inst; ga.qid = pb->qid;
+                    ga.gamma = pb->gamma; ga.ld_gamma = pb->ld_gamma; ga.n_sets = pb->n_sets;
+                    ga.goff = m * pb->e_cap;
+                    ga.d = nd.size; ga.e_cap = pb->e_cap; ga.nnz_cap = pb->nnz_cap;
+                    ga.e_of = ml.e_of; ga.colptr = ml.colptr; ga.col_e = ml.col_e; ga.col_P = ml.col_P;
+                    ga.col_Ph = ml.col_Ph; ga.rowptr = ml.rowptr; ga.row_j = ml.row_j; ga.row_P = ml.row_P;
+                    ga.row_Ph = ml.row_Ph; ga.p = ml.p;
+                    launch_gamma_grad(ga, gs_hat, gs_out, g_gamma, pb->ld_gamma, st);
+                }
+                g[n] = G;   // relaxed in place
+                if (uses[nd.src] == 1) {
+                    uses[nd.src] = 0;
+                } else {
+                    pool.retain(G);
+                    done_with(nd.src);
+                }
+                break;
+            }
+            default:
+                throw Error{MNB_EDEVICE, "unexpected node in adjoint"};
+        }
+    }
+    for (int n = 1; n <= top; ++n)
+        if (uses[n] > 0 && g[n]) {
+            uses[n] = 0;
+            pool.release(g[n]);
+        }
+}
+
+// gamma projections v = P^T gamma, vhat = Phat^T gamma, gp = gamma . p for every
+// ReLU layer below the objective of a chunk.
+static void gamma_projections(PassCtx& cx, const PassChunk& ch, Workspace& ws, const std::string& tag) {
+    mnb_problem* pb = cx.pb;
+    if (!pb->has_mnc) return;
+    mnb_net* net = pb->net;
+    const int top = pass_top(net, ch.obj_layer);
+    const int n_inst = (int)ch.inst.size();
+    for (int m = 0; m < pb->R; ++m) {
+        const int ri = net->relus[m];
+        if (ri > top) break;
+        const int d = net->relu_d[m];
+        float* v = ws.get<float>(tag + "v" + std::to_string(m), (size_t)n_inst * d);
+        float* vh = ws.get<float>(tag + "vh" + std::to_string(m), (size_t)n_inst * d);
+        float* gp = ws.get<float>(tag + "gp" + std::to_string(m), (size_t)n_inst);
+        auto& ml = pb->mnc[m];
+        GammaArgs ga{};
+        ga.inst = ch.inst_d; ga.n_inst = n_inst; ga.qid = pb->qid;
+        ga.gamma = pb->gamma; ga.ld_gamma = pb->ld_gamma; ga.n_sets = pb->n_sets; ga.goff = m * pb->e_cap;
+        ga.d = d; ga.e_cap = pb->e_cap; ga.nnz_cap = pb->nnz_cap;
+        ga.e_of = ml.e_of; ga.colptr = ml.colptr; ga.col_e = ml.col_e; ga.col_P = ml.col_P; ga.col_Ph = ml.col_Ph;
+        ga.rowptr = ml.rowptr; ga.row_j = ml.row_j; ga.row_P = ml.row_P; ga.row_Ph = ml.row_Ph; ga.p = ml.p;
+        ga.v = v; ga.vhat = vh; ga.gp = gp;
+        launch_gamma_proj(ga, stream());
+        cx.v[m] = v;
+        cx.vh[m] = vh;
+        cx.gp[m] = gp;
+    }
+}
+
+// Device workspace needed by a chunk of M rows of a pass with the given top node.
+static size_t chunk_bytes(const mnb_net* net, int top, long M, int n_inst, bool adjoint) {
+    size_t b = 0;
+    b += 3 * (size_t)M * net->max_width * 4;           // coefficient / forward buffers
+    b += (size_t)M * (pass_cols(net, top) + 1) * 4;     // c + partials
+    b += (size_t)M * net->d0 * 5;                       // x* floats + bits
+    if (adjoint)
+        for (int i : net->relus)
+            if (i <= top) b += (size_t)M * net->nodes[i].size * 4;   // a'
+    b += (size_t)n_inst * net->total_d * 4 * 4;         // gradients / sums
+    return b;
+}
+
+}  // namespace
+
+// =====================================================================================
+// evaluation of chunks (shared by bound_init and bound_optimize)
+// =====================================================================================
+namespace {
+
+struct ChunkIO {
+    // spec-row outputs (mode 1)
+    float* lb_rows = nullptr;     // [M]
+    float* best = nullptr;        // [M]
+    uint8_t* improved = nullptr;  // [M]
+    uint8_t* best_bits = nullptr; // [M, d0]
+};
+
+// Evaluate one chunk (back-substitution + concretisation), optionally followed
+// by its adjoint and a projected Adam step.
+struct Evaluator {
+    mnb_problem* pb;
+    const int32_t* slots_d;
+    Workspace& ws;
+    Evaluator(mnb_problem* p, const int32_t* s) : pb(p), slots_d(s), ws(p->ws) {}
+
+    BufPool make_pool(int M, int nbuf) {
+        BufPool pool;
+        for (int i = 0; i < nbuf; ++i) {
+            pool.bufs.push_back(ws.get<float>("pool" + std::to_string(i), (size_t)M * pb->net->max_width));
+            pool.ref.push_back(0);
+        }
+        return pool;
+    }
+
+    bool no_write = false;   // concretise intermediate rows without touching l/u, skip Adam
+    float *g_alpha_last = nullptr, *g_beta_last = nullptr, *g_gamma_last = nullptr;
+    void eval(const PassChunk& ch, bool adjoint, bool keep_ap, const ChunkIO& io, const mnb_opt_cfg* cfg,
+              float* m_alpha, float* v_alpha, float* m_beta, float* v_beta, float* m_gamma, float* v_gamma, int t) {
+        mnb_net* net = pb->net;
+        hipStream_t st = stream();
+        const int M = ch.M;
+        if (M == 0) return;
+        const int top = pass_top(net, ch.obj_layer);
+        PassCtx cx{};
+        cx.pb = pb;
+        cx.slots_d = slots_d;
+        cx.c = ws.get<float>("c", M);
+        cx.ldcp = pass_cols(net, top);
+        cx.cpart = ws.get<float>("cpart", (size_t)M * cx.ldcp);
+        cx.G0 = ws.get<float>("G0", (size_t)M * net->d0);
+        const bool want_ap = adjoint || keep_ap;
+        if (want_ap)
+            for (int i : net->relus)
+                if (i <= top) cx.ap[i] = ws.get<float>("ap" + std::to_string(i), (size_t)M * net->nodes[i].size);
+        if (ch.obj_layer < 0) cx.xbits = ws.get<uint8_t>("xbits", (size_t)M * net->d0);
+        gamma_projections(cx, ch, ws, "gproj");
+        BufPool pool = make_pool(M, 3);
+        float* A0 = run_backsub(cx, ch, pool, want_ap);
+        ConcArgs ca{};
+        ca.A = A0; ca.c = cx.c; ca.cpart = cx.cpart; ca.ldcp = cx.ldcp; ca.ncp = cx.ncp;
+        ca.rows = ch.rows; ca.slots = slots_d; ca.qid = pb->qid; ca.lo = pb->lo; ca.hi = pb->hi;
+        ca.M = M; ca.d0 = net->d0;
+        ca.G0 = adjoint ? cx.G0 : nullptr;
+        if (ch.obj_layer < 0) {
+            ca.mode = 1;
+            ca.xbits = cx.xbits;
+            ca.lb_out = io.lb_rows; ca.best = io.best; ca.improved = io.improved;
+        } else if (no_write) {
+            ca.mode = 2;
+            ca.lb_out = io.lb_rows;
+        } else {
+            ca.mode = 0;
+            ca.l = pb->l; ca.u = pb->u; ca.ld_state = pb->ld_state;
+            ca.state_off = net->relu_off[ch.obj_layer];
+        }
+        launch_concretize(ca, st);
+        pool.release(A0);
+        if (ch.obj_layer < 0 && io.best_bits)
+            launch_keep_best_x(cx.xbits, io.best_bits, io.improved, M, net->d0, st);
+        if (keep_ap) last_ap = cx.ap;
+        if (!adjoint) return;
+        const int n_inst = (int)ch.inst.size();
+        float* g_alpha = ws.get<float>("g_alpha", (size_t)n_inst * pb->ld_param);
+        float* g_beta = ws.get<float>("g_beta", (size_t)n_inst * pb->ld_param);
+        float* g_gamma = pb->has_mnc ? ws.get<float>("g_gamma", (size_t)n_inst * pb->ld_gamma) : nullptr;
+        float* gs_hat = pb->has_mnc ? ws.get<float>("gs_hat", (size_t)n_inst * net->max_width) : nullptr;
+        float* gs_out = pb->has_mnc ? ws.get<float>("gs_out", (size_t)n_inst * net->max_width) : nullptr;
+        if (pb->has_mnc) launch_fill(g_gamma, (long)n_inst * pb->ld_gamma, 0.f, st);
+        run_adjoint(cx, ch, pool, g_alpha, g_beta, g_gamma, gs_hat, gs_out);
+        g_alpha_last = g_alpha;
+        g_beta_last = g_beta;
+        g_gamma_last = g_gamma;
+        if (no_write) return;
+        // projected Adam ascent on every instance's set
+        AdamArgs aa{};
+        aa.inst = ch.inst_d; aa.n_inst = n_inst;
+        aa.alpha = pb->alpha; aa.beta = pb->beta; aa.ld_param = pb->ld_param; aa.n_sets = pb->n_sets;
+        aa.m_alpha = m_alpha; aa.v_alpha = v_alpha; aa.m_beta = m_beta; aa.v_beta = v_beta;
+        aa.g_alpha = g_alpha; aa.g_beta = g_beta; aa.ldg = pb->ld_param;
+        const int obj = ch.obj_layer < 0 ? pb->R : ch.obj_layer;
+        aa.n_ab = obj < pb->R ? net->relu_off[obj] : net->total_d;
+        aa.gamma = pb->has_mnc ? pb->gamma : nullptr;
+        aa.m_gamma = m_gamma; aa.v_gamma = v_gamma; aa.g_gamma = g_gamma; aa.ld_gamma = pb->ld_gamma;
+        aa.n_gamma = pb->has_mnc ? obj * pb->e_cap : 0;
+        aa.lr = cfg->lr; aa.b1 = cfg->beta1; aa.b2 = cfg->beta2; aa.eps = cfg->eps;
+        aa.bc1 = 1.f - powf(cfg->beta1, (float)(t + 1));
+        aa.bc2 = 1.f - powf(cfg->beta2, (float)(t + 1));
+        launch_adam(aa, st);
+    }
+    std::map<int, float*> last_ap;
+};
+
+}  // namespace
+
+#include "engine_calls.inc"

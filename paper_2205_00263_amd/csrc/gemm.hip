@@ -1,0 +1,342 @@
+// FP32 MFMA products of back-substitution (Eq. 2) and of its adjoint.
+//
+// One generic LDS-staged GEMM  C[m, n] = sum_k A(m, k) B(k, n)  on
+// v_mfma_f32_16x16x4_f32, 256 threads (4 wavefronts of 64), with the operand
+// element maps supplied by a small "problem" class:
+//   FcBack   A = coefficient rows [M, dout], B = W [dout, din]            (a W)
+//   FcFwd    A = forward rows [M, din],      B(k, n) = W[n, k]            (g W^T + b)
+//   ConvBack A(m, k) gathers the coefficient of the conv output that feeds
+//            input position m through tap k (one stride phase per launch:
+//            implicit-GEMM transposed convolution), B = phase weights
+//   ConvFwd  A(m, k) gathers the input patch (implicit-GEMM convolution)
+// The K-reduction order of an output element depends only on (n, K), never
+// on M or on neighbouring rows, so a row's result is the same in any batch.
+#include "kernels.h"
+
+namespace mnb {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;
+
+// ------------------------------------------------------------------ problems
+struct FcBack {
+    static constexpr bool A_MFAST = false;   // A contiguous along k
+    static constexpr bool B_NFAST = true;    // B contiguous along n
+    const float* A; const float* W; float* C;
+    int M, N, K; int acc;
+    struct MCtx { long base, cbase; bool ok; };
+    __device__ MCtx mctx(int m) const { return {(long)m * K, (long)m * N, m < M}; }
+    __device__ float a(const MCtx& c, int k) const { return (c.ok && k < K) ? A[c.base + k] : 0.f; }
+    __device__ float b(int k, int n) const { return (k < K && n < N) ? W[(long)k * N + n] : 0.f; }
+    __device__ void store_ctx(const MCtx& c, int n, float v) const {
+        if (c.ok && n < N) {
+            float* p = C + c.cbase + n;
+            *p = acc ? *p + v : v;
+        }
+    }
+};
+
+struct FcFwd {
+    static constexpr bool A_MFAST = false;
+    static constexpr bool B_NFAST = false;   // B(k, n) = W[n*K + k], contiguous along k
+    const float* A; const float* W; const float* bias; float* C;
+    int M, N, K; int acc;
+    struct MCtx { long base, cbase; bool ok; };
+    __device__ MCtx mctx(int m) const { return {(long)m * K, (long)m * N, m < M}; }
+    __device__ float a(const MCtx& c, int k) const { return (c.ok && k < K) ? A[c.base + k] : 0.f; }
+    __device__ float b(int k, int n) const { return (k < K && n < N) ? W[(long)n * K + k] : 0.f; }
+    __device__ void store_ctx(const MCtx& c, int n, float v) const {
+        if (c.ok && n < N) {
+            float* p = C + c.cbase + n;
+            v += bias[n];
+            *p = acc ? *p + v : v;
+        }
+    }
+};
+
+struct ConvBack {
+    static constexpr bool A_MFAST = true;
+    static constexpr bool B_NFAST = true;
+    const float* A; float* C;
+    const float* Wp; const int2* ktab;
+    int M, N, K;          // M = rows*nY*nX, N = Ci, K = Co*Ty*Tx
+    int nY, nX, Ho, Wo, ldA, ldC, HiWi, Wi, Y0, X0, s, q0y, q0x;
+    int acc;
+    struct MCtx { long base; int yb, xb; bool ok; long cbase; };
+    __device__ MCtx mctx(int m) const {
+        MCtx c;
+        c.ok = m < M;
+        int mm = c.ok ? m : 0;
+        int per = nY * nX;
+        int r = mm / per, rem = mm - r * per;
+        int i = rem / nX, jx = rem - i * nX;
+        c.yb = q0y + i;
+        c.xb = q0x + jx;
+        c.base = (long)r * ldA + (long)c.yb * Wo + c.xb;
+        c.cbase = (long)r * ldC + (long)(Y0 + s * i) * Wi + (X0 + s * jx);
+        return c;
+    }
+    __device__ float a(const MCtx& c, int k) const {
+        if (!c.ok || k >= K) return 0.f;
+        int2 t = ktab[k];
+        int ty = t.y >> 16, tx = t.y & 0xffff;
+        int y = c.yb - ty, x = c.xb - tx;
+        if ((unsigned)y >= (unsigned)Ho || (unsigned)x >= (unsigned)Wo) return 0.f;
+        return A[c.base + t.x];
+    }
+    __device__ float b(int k, int n) const { return (k < K && n < N) ? Wp[(long)k * N + n] : 0.f; }
+    __device__ void store_ctx(const MCtx& c, int n, float v) const {
+        if (c.ok && n < N) {
+            float* p = C + c.cbase + (long)n * HiWi;
+            *p = acc ? *p + v : v;
+        }
+    }
+};
+
+struct ConvFwd {
+    static constexpr bool A_MFAST = true;
+    static constexpr bool B_NFAST = false;   // W[co][ci*k*k]
+    const float* A; float* C; const float* W; const float* bias; const int2* ktab;
+    int M, N, K;          // M = rows*Ho*Wo, N = Co, K = Ci*k*k
+    int Ho, Wo, Hi, Wi, ldA, ldC, s, p;
+    int acc;
+    struct MCtx { long base, cbase; int iy, ix; bool ok; };
+    __device__ MCtx mctx(int m) const {
+        MCtx c;
+        c.ok = m < M;
+        int mm = c.ok ? m : 0;
+        int per = Ho * Wo;
+        int r = mm / per, rem = mm - r * per;
+        int y = rem / Wo, x = rem - y * Wo;
+        c.iy = s * y - p;
+        c.ix = s * x - p;
+        c.base = (long)r * ldA + (long)c.iy * Wi + c.ix;
+        c.cbase = (long)r * ldC + rem;
+        return c;
+    }
+    __device__ float a(const MCtx& c, int k) const {
+        if (!c.ok || k >= K) return 0.f;
+        int2 t = ktab[k];
+        int ky = t.y >> 16, kx = t.y & 0xffff;
+        int y = c.iy + ky, x = c.ix + kx;
+        if ((unsigned)y >= (unsigned)Hi || (unsigned)x >= (unsigned)Wi) return 0.f;
+        return A[c.base + t.x];
+    }
+    __device__ float b(int k, int n) const { return (k < K && n < N) ? W[(long)n * K + k] : 0.f; }
+    __device__ void store_ctx(const MCtx& c, int n, float v) const {
+        if (c.ok && n < N) {
+            float* q = C + c.cbase + (long)n * Ho * Wo;
+            v += bias[n];
+            *q = acc ? *q + v : v;
+        }
+    }
+};
+
+// ------------------------------------------------------------------ kernel
+template <int BM, int BN, int WAVES_M, class P>
+__global__ __launch_bounds__(256) void k_gemm(P p) {
+    constexpr int WAVES_N = 4 / WAVES_M;
+    constexpr int WTM = BM / WAVES_M, WTN = BN / WAVES_N;
+    constexpr int FM = WTM / 16, FN = WTN / 16;
+    constexpr int APAD = (16 - (BM % 32) + 32) % 32;   // row stride = 16 mod 32 banks
+    constexpr int BPAD = (16 - (BN % 32) + 32) % 32;
+    constexpr int LDA_S = BM + APAD, LDB_S = BN + BPAD;
+    constexpr int A_PER = BM * BK / 256, B_PER = BN * BK / 256;
+    static_assert(A_PER >= 1 && B_PER >= 1, "tile too small");
+    __shared__ float As[2][BK][LDA_S];
+    __shared__ float Bs[2][BK][LDB_S];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int nk = (p.K + BK - 1) / BK;
+
+    // A element map: either m-fast (gathers along positions) or k-fast (row-major rows)
+    int a_m[A_PER > 0 ? (P::A_MFAST ? 1 : A_PER) : 1];
+    int a_k[A_PER];
+    typename P::MCtx actx[P::A_MFAST ? 1 : A_PER];
+    if (P::A_MFAST) {
+        constexpr int KSTEP = 256 / BM;
+        a_m[0] = tid % BM;
+        for (int i = 0; i < A_PER; ++i) a_k[i] = tid / BM + i * KSTEP;
+        actx[0] = p.mctx(m0 + a_m[0]);
+    } else {
+        for (int i = 0; i < A_PER; ++i) {
+            a_k[i] = tid % BK;
+            a_m[i] = tid / BK + i * (256 / BK);
+            actx[i] = p.mctx(m0 + a_m[i]);
+        }
+    }
+    int b_k[B_PER], b_n[B_PER];
+    for (int i = 0; i < B_PER; ++i) {
+        if (P::B_NFAST) {
+            constexpr int KSTEP = 256 / BN;
+            b_n[i] = tid % BN;
+            b_k[i] = tid / BN + i * KSTEP;
+        } else {
+            b_k[i] = tid % BK;
+            b_n[i] = tid / BK + i * (256 / BK);
+        }
+    }
+
+    float ra[A_PER], rb[B_PER];
+    auto load = [&](int kt) {
+        const int k0 = kt * BK;
+        for (int i = 0; i < A_PER; ++i)
+            ra[i] = p.a(actx[P::A_MFAST ? 0 : i], k0 + a_k[i]);
+        for (int i = 0; i < B_PER; ++i) rb[i] = p.b(k0 + b_k[i], n0 + b_n[i]);
+    };
+    auto stash = [&](int buf) {
+        for (int i = 0; i < A_PER; ++i) As[buf][a_k[i]][P::A_MFAST ? a_m[0] : a_m[i]] = ra[i];
+        for (int i = 0; i < B_PER; ++i) Bs[buf][b_k[i]][b_n[i]] = rb[i];
+    };
+
+    floatx4 acc[FM][FN];
+    for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    if (nk > 0) {
+        load(0);
+        stash(0);
+        __syncthreads();
+    }
+    const int lrow = lane & 15, lk = lane >> 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            float fa[FM], fb[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) fa[i] = As[cur][kk + lk][wm * WTM + i * 16 + lrow];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) fb[j] = Bs[cur][kk + lk][wn * WTN + j * 16 + lrow];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nk) stash(cur ^ 1);
+        __syncthreads();
+    }
+
+    // D layout of 16x16x4: lane holds rows 4*(lane/16) + v, column lane%16.
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = m0 + wm * WTM + i * 16 + 4 * lk + v;
+            const auto c = p.mctx(m);
+#pragma unroll
+            for (int j = 0; j < FN; ++j) p.store_ctx(c, n0 + wn * WTN + j * 16 + lrow, acc[i][j][v]);
+        }
+    }
+}
+
+template <class P>
+static void run_gemm(const P& p, hipStream_t st) {
+    dim3 blk(256);
+    if (p.N <= 16) {
+        dim3 grid(cdiv(p.M, 256), cdiv(p.N, 16));
+        hipLaunchKernelGGL((k_gemm<256, 16, 4, P>), grid, blk, 0, st, p);
+    } else if (p.N <= 32) {
+        dim3 grid(cdiv(p.M, 128), cdiv(p.N, 32));
+        hipLaunchKernelGGL((k_gemm<128, 32, 4, P>), grid, blk, 0, st, p);
+    } else if (p.N <= 64) {
+        dim3 grid(cdiv(p.M, 128), cdiv(p.N, 64));
+        hipLaunchKernelGGL((k_gemm<128, 64, 2, P>), grid, blk, 0, st, p);
+    } else {
+        dim3 grid(cdiv(p.M, 128), cdiv(p.N, 128));
+        hipLaunchKernelGGL((k_gemm<128, 128, 2, P>), grid, blk, 0, st, p);
+    }
+    MNB_HIP(hipGetLastError());
+}
+
+void launch_fc_backsub(const float* A, const float* W, float* C, int M, int dout, int din,
+                       bool accumulate, hipStream_t st) {
+    if (M <= 0) return;
+    FcBack p;
+    p.A = A; p.W = W; p.C = C; p.M = M; p.N = din; p.K = dout; p.acc = accumulate;
+    run_gemm(p, st);
+}
+
+void launch_fc_forward(const float* G, const float* W, const float* b, float* C, int M, int din,
+                       int dout, bool accumulate, hipStream_t st) {
+    if (M <= 0) return;
+    FcFwd p;
+    p.A = G; p.W = W; p.bias = b; p.C = C; p.M = M; p.N = dout; p.K = din; p.acc = accumulate;
+    run_gemm(p, st);
+}
+
+// ------------------------------------------------------------------ small-Ci transposed conv (VALU)
+// For layers whose input has very few channels (Ci < 16) an MFMA tile would be
+// mostly padding; these layers are HBM-bound, so one thread per output element
+// gathers its taps directly.
+__global__ __launch_bounds__(256) void k_convT_valu(const float* __restrict__ A, float* __restrict__ C,
+                                                   const float* __restrict__ W, int M, int Ci, int Hi,
+                                                   int Wi, int Co, int Ho, int Wo, int k, int s, int p,
+                                                   int acc) {
+    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long per = (long)Ci * Hi * Wi;
+    if (idx >= (long)M * per) return;
+    int r = (int)(idx / per);
+    int rem = (int)(idx - (long)r * per);
+    int ci = rem / (Hi * Wi);
+    int pos = rem - ci * Hi * Wi;
+    int Y = pos / Wi, X = pos - Y * Wi;
+    const float* Ar = A + (long)r * Co * Ho * Wo;
+    float sum = 0.f;
+    for (int ky = (Y + p) % s; ky < k; ky += s) {
+        int y = (Y + p - ky) / s;
+        if (y < 0 || y >= Ho) continue;
+        for (int kx = (X + p) % s; kx < k; kx += s) {
+            int x = (X + p - kx) / s;
+            if (x < 0 || x >= Wo) continue;
+            const float* w = W + ((long)ci * k + ky) * k + kx;
+            const float* a = Ar + (long)y * Wo + x;
+            for (int co = 0; co < Co; ++co) sum += a[(long)co * Ho * Wo] * w[(long)co * Ci * k * k];
+        }
+    }
+    float* out = C + idx;
+    *out = acc ? *out + sum : sum;
+}
+
+void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
+                         hipStream_t st) {
+    if (M <= 0) return;
+    if (g.Ci < 16) {
+        long total = (long)M * g.Ci * g.Hi * g.Wi;
+        hipLaunchKernelGGL(k_convT_valu, dim3(cdiv(total, 256)), dim3(256), 0, st, A, C, g.W, M, g.Ci,
+                           g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.k, g.s, g.p, (int)accumulate);
+        MNB_HIP(hipGetLastError());
+        return;
+    }
+    for (int f = 0; f < g.n_phase; ++f) {
+        const ConvPhase& ph = g.ph[f];
+        if (ph.nY <= 0 || ph.nX <= 0) continue;
+        ConvBack p;
+        p.A = A; p.C = C; p.Wp = ph.Wp; p.ktab = ph.ktab;
+        p.M = M * ph.nY * ph.nX; p.N = g.Ci; p.K = g.Co * ph.Ty * ph.Tx;
+        p.nY = ph.nY; p.nX = ph.nX; p.Ho = g.Ho; p.Wo = g.Wo;
+        p.ldA = g.Co * g.Ho * g.Wo; p.ldC = g.Ci * g.Hi * g.Wi; p.HiWi = g.Hi * g.Wi; p.Wi = g.Wi;
+        p.Y0 = ph.Y0; p.X0 = ph.X0; p.s = g.s; p.q0y = ph.q0y; p.q0x = ph.q0x;
+        p.acc = accumulate;
+        run_gemm(p, st);
+    }
+}
+
+void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
+                         hipStream_t st) {
+    if (M <= 0) return;
+    ConvFwd p;
+    p.A = G; p.C = C; p.W = g.W; p.bias = g.b; p.ktab = g.fwd_ktab;
+    p.M = M * g.Ho * g.Wo; p.N = g.Co; p.K = g.Ci * g.k * g.k;
+    p.Ho = g.Ho; p.Wo = g.Wo; p.Hi = g.Hi; p.Wi = g.Wi;
+    p.ldA = g.Ci * g.Hi * g.Wi; p.ldC = g.Co * g.Ho * g.Wo; p.s = g.s; p.p = g.p;
+    p.acc = accumulate;
+    run_gemm(p, st);
+}
+
+}  // namespace mnb

@@ -1,0 +1,161 @@
+// Launchers of the HIP kernels (internal interface between the engine and the kernels).
+#pragma once
+
+#include "common.h"
+
+namespace mnb {
+
+// Geometry of one convolution node plus the device tables its kernels use.
+struct ConvPhase {
+    int rho_y, rho_x;   // residues (Y + pad) mod stride of this phase
+    int Y0, X0;         // first output position of the phase
+    int nY, nX;         // positions of the phase
+    int Ty, Tx;         // taps of the phase
+    int q0y, q0x;       // (Y0 + pad - rho)/stride
+    const float* Wp;    // [Co][Ty][Tx][Ci] weights of the phase
+    const int2* ktab;   // [Co*Ty*Tx] {co*Ho*Wo - ty*Wo - tx, (ty<<16)|tx}
+};
+
+struct ConvGeom {
+    int Ci, Hi, Wi, Co, Ho, Wo, k, s, p;
+    const float* W;     // [Co][Ci][k][k]
+    const float* b;     // [Co]
+    const int2* fwd_ktab;  // [Ci*k*k] {ci*Hi*Wi + ky*Wi + kx, (ky<<16)|kx}
+    int n_phase;
+    ConvPhase ph[16];   // stride <= 4
+};
+
+// ---- back-substitution products (Eq. 2) ----
+// C[M, din] (+)= A[M, dout] * W[dout, din]
+void launch_fc_backsub(const float* A, const float* W, float* C, int M, int dout, int din,
+                       bool accumulate, hipStream_t st);
+// C[M, Ci*Hi*Wi] (+)= conv-transpose of A[M, Co*Ho*Wo]
+void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
+                         hipStream_t st);
+
+// ---- forward products (adjoint and upper-bound evaluation) ----
+// C[M, dout] = G[M, din] * W^T + b  (accumulate: C += ..., bias added either way)
+void launch_fc_forward(const float* G, const float* W, const float* b, float* C, int M, int din,
+                       int dout, bool accumulate, hipStream_t st);
+void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
+                         hipStream_t st);
+
+// ---- elementwise / reduction kernels (relu.hip) ----
+struct FoldArgs {
+    float* A;             // [M, d] in: a (coef on z), out: ahat (coef on zhat)
+    float* Ap;            // [M, d] out: a' (nullable)
+    float* cpart;         // [M, ldcp] per-wave partial constants (written at col_off + j/64)
+    int ldcp, col_off;
+    const InstDesc* inst; int n_inst;
+    const int32_t* slots; // local b -> global slot
+    int M, d;
+    // per-slot state (global slot index), layer offset already applied
+    const float* l; const float* u; const int8_t* S; long ld_state;
+    // parameters: base + (slot*n_sets + set)*ld_param + layer offset
+    const float* alpha; const float* beta; long ld_param; int n_sets;
+    // gamma projections (nullable): per instance [n_inst, d]
+    const float* v; const float* vhat;
+    const float* bias;    // [d] effective bias of the affine output feeding this ReLU
+};
+void launch_relu_fold(const FoldArgs& a, hipStream_t st);
+
+struct RelaxArgs {
+    float* G;             // [M, d] in: ghat (forward value at the ReLU input), out: g (at its output)
+    const float* Ap;      // [M, d] a' of the same rows
+    const InstDesc* inst; int n_inst;
+    const int32_t* slots;
+    int M, d;
+    const float* l; const float* u; const int8_t* S; long ld_state;
+    const float* alpha; long ld_param; int n_sets;
+    // gradient outputs per instance [n_inst, ldg] at column offset goff
+    float* d_alpha; float* d_beta; long ldg; long goff;
+    float* gsum_hat; float* gsum_out;  // nullable, [n_inst, d] (for gamma)
+};
+void launch_relu_relax(const RelaxArgs& a, hipStream_t st);
+void launch_relu_fold(const FoldArgs& a, hipStream_t st, const float* gp);
+
+struct ConcArgs {
+    int mode;              // 0: intermediate-bound rows (update l/u), 1: spec rows, 2: lb only
+    const float* A;        // [M, d0] coefficients on the input
+    const float* c;        // [M]
+    const float* cpart; int ldcp, ncp;  // partial constants of the folds
+    const RowDesc* rows; const int32_t* slots; const int32_t* qid;
+    const float* lo; const float* hi;   // [n_query, d0]
+    int M, d0;
+    float* G0;             // [M, d0] x* (nullable)
+    uint8_t* xbits;        // [M, d0] 1 where x* = hi (nullable)
+    // mode 0
+    float* l; float* u; long ld_state; int state_off;
+    // mode 1
+    float* lb_out; float* best; uint8_t* improved;
+};
+void launch_concretize(const ConcArgs& a, hipStream_t st);
+void launch_keep_best_x(const uint8_t* xbits, uint8_t* best_bits, const uint8_t* improved, int M, int d0,
+                        hipStream_t st);
+
+void launch_init_spec(const RowDesc* rows, int M, const int32_t* slots, const int32_t* qid, const float* Chat,
+                      const float* chat, int S, int d, float* A, float* c, hipStream_t st);
+void launch_init_fc(const RowDesc* rows, int M, const float* W, const float* bias_eff, int din, float* A,
+                    float* c, bool write_c, hipStream_t st);
+void launch_init_conv(const RowDesc* rows, int M, const ConvGeom& g, const float* bias_eff, float* A, float* c,
+                      bool write_c, hipStream_t st);
+
+void launch_ibp_fc(const float* W, const float* b, const float* L, const float* U, float* Lo, float* Uo, int din,
+                   int dout, hipStream_t st);
+void launch_ibp_conv(const ConvGeom& g, const float* L, const float* U, float* Lo, float* Uo, hipStream_t st);
+void launch_ibp_relu(const float* L, const float* U, const float* lk, const float* uk, float* Lo, float* Uo, int d,
+                     hipStream_t st);
+void launch_add2(const float* a, const float* b, float* o, long n, hipStream_t st);
+
+struct AdamArgs {
+    const InstDesc* inst; int n_inst;
+    float* alpha; float* beta; long ld_param; int n_sets;
+    float* m_alpha; float* v_alpha; float* m_beta; float* v_beta;   // [nb, n_sets, ld_param]
+    const float* g_alpha; const float* g_beta; long ldg;            // [n_inst, ldg]
+    int n_ab;              // alpha/beta entries of the set (prefix of the layer space)
+    float* gamma; float* m_gamma; float* v_gamma; const float* g_gamma; long ld_gamma; int n_gamma;
+    float lr, b1, b2, eps, bc1, bc2;
+};
+void launch_adam(const AdamArgs& a, hipStream_t st);
+
+struct GammaArgs {
+    const InstDesc* inst; int n_inst;
+    const int32_t* qid;
+    const float* gamma; long ld_gamma; int n_sets; int goff;   // this layer's gamma offset
+    int d, e_cap, nnz_cap;
+    const int* e_of;                                      // [n_query] constraints of this layer
+    const int* colptr; const int* col_e; const float* col_P; const float* col_Ph;   // CSC per query
+    const int* rowptr; const int* row_j; const float* row_P; const float* row_Ph;   // CSR per query
+    const float* p;                                       // [n_query, e_cap]
+    float* v; float* vhat; float* gp;                     // [n_inst, d], [n_inst, d], [n_inst]
+};
+void launch_gamma_proj(const GammaArgs& a, hipStream_t st);
+void launch_gamma_grad(const GammaArgs& a, const float* gsum_hat, const float* gsum_out, float* g_gamma, long ldgg,
+                       hipStream_t st);
+
+void launch_score(const InstDesc* inst, int n_inst, const float* Ap, int d, const float* l, const float* u,
+                  const int8_t* S, long ld_state, int state_off, float* score, long ld_score, int score_off,
+                  hipStream_t st);
+void launch_argmax(const float* score, long ld, int n, int nb, int32_t* out, hipStream_t st);
+
+void launch_bits_to_x(const uint8_t* bits, const int32_t* row_slot, const int32_t* qid, const float* lo,
+                      const float* hi, int d0, int M, float* X, hipStream_t st);
+void launch_relu_inplace(float* X, long n, hipStream_t st);
+void launch_spec_dot(const float* logits, int n_out, const RowDesc* rows, const int32_t* slots, const int32_t* qid,
+                     const float* C, const float* c0, int S, int M, float* ub, hipStream_t st);
+void launch_spec_fold(const float* C, const float* c0, const float* W, const float* b, int S, int n_out, int din,
+                      float* Chat, float* chat, hipStream_t st);
+void launch_fill(float* p, long n, float v, hipStream_t st);
+void launch_heuristic_alpha(const float* l, const float* u, long ld_state, int off, int d, float* alpha,
+                            long ld_param, int n_sets, int slot, hipStream_t st);
+void launch_count_unstable(const int32_t* slots, int nb, const float* l, const float* u, long ld_state, int off,
+                           int d, int32_t* count, hipStream_t st);
+void launch_build_rows(const int32_t* bs, int nk, const int32_t* slots, const int32_t* row0, const int32_t* inst0,
+                       const float* l, const float* u, long ld_state, int off, int d, RowDesc* rows,
+                       hipStream_t st);
+void launch_copy_slots(const int32_t* src, const int32_t* dst, int n, void* base, long bytes_per_slot,
+                       hipStream_t st);
+void launch_apply_split(const int32_t* child, const int32_t* off_j, const int32_t* sign, int n, float* l, float* u,
+                        int8_t* S, long ld_state, float* beta, long ld_param, int n_sets, hipStream_t st);
+
+}  // namespace mnb

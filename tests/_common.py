@@ -1,0 +1,52 @@
+"""Shared helpers of the test-suite: build the same query for the oracle and the GPU path."""
+import numpy as np
+
+import workloads as W
+from oracle import backsub as ob
+from oracle import bab as obab
+from oracle import mnc as omnc
+from oracle import net as onet
+from oracle import optimize as oo
+
+
+def tol(ref):
+    """Parity bar: |gpu - oracle| <= 1e-4 max(1, |oracle|)."""
+    return 1e-4 * np.maximum(1.0, np.abs(ref))
+
+
+def assert_parity(gpu, ref, what=""):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    err = np.abs(gpu - ref)
+    bad = err > tol(ref)
+    assert not np.any(bad), f"{what}: {bad.sum()} of {bad.size} outside 1e-4 rel; worst {err.max():.3e} " \
+                            f"at {np.unravel_index(np.argmax(err), err.shape)} gpu={gpu.ravel()[np.argmax(err)]} " \
+                            f"ref={ref.ravel()[np.argmax(err)]}"
+
+
+def oracle_query(wl, mncs=None):
+    net = onet.Net(wl.nodes)
+    return net, oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, mncs)
+
+
+def mnc_layers(net, mncs):
+    """oracle Mnc dict (relu node -> Mnc) -> GPU layer dict (relu layer -> CSR tuple)."""
+    from paper_2205_00263_amd import mnc_to_csr
+    out = {}
+    for i, m in mncs.items():
+        if m.e > 0:
+            out[net.relus.index(i)] = mnc_to_csr(m.P, m.Phat, m.p)
+    return out
+
+
+def sampled_min(net, wl, n=4000, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(wl.lo, wl.hi, size=(n, len(wl.lo)))
+    corners = np.where(rng.integers(0, 2, size=(64, len(wl.lo))) > 0, wl.hi, wl.lo)
+    X = np.vstack([X, corners])
+    f = onet.forward(net, X) @ np.asarray(wl.C, np.float64).T + wl.c0
+    return f.min(0)
+
+
+def root_unstable(net, sub):
+    return [np.nonzero((sub.states[i].l < 0) & (sub.states[i].u > 0))[0] for i in net.relus]

@@ -1,0 +1,40 @@
+"""The C ABI library loads and exports every symbol include/mnbab.h declares (CPU only, no compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mnbab.h")
+LIB = os.path.join(ROOT, "paper_2205_00263_amd", "libmnbab.so")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("typedef",)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for n in ("bound_init", "bound_optimize", "branch_split", "query_submit", "query_poll",
+              "mnb_net_create", "mnb_problem_create", "mnb_last_error"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_declares_only_exported_symbols():
+    from paper_2205_00263_amd import _lib
+    lib = ctypes.CDLL(LIB)
+    assert [n for n in _lib.exported_symbols() if not hasattr(lib, n)] == []
+    assert set(_lib.exported_symbols()) == set(declared_functions())

@@ -1,0 +1,250 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import backsub as ob
+from oracle import bab as obab
+from oracle import net as onet
+from oracle import optimize as oo
+
+from _common import assert_parity, oracle_query, root_unstable, sampled_min
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_00263_amd as P
+    P.lib()
+    yield
+
+
+def _P():
+    import paper_2205_00263_amd as P
+    return P
+
+
+# --------------------------------------------------------------------------- kernels
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+CONV_GEOMS = [  # (Ci, H, Co, k, s, p)
+    (1, 28, 16, 4, 2, 0), (16, 13, 32, 4, 2, 0),          # ConvSmall
+    (3, 32, 32, 3, 1, 1), (32, 32, 32, 4, 2, 1), (32, 16, 64, 3, 1, 1), (64, 16, 64, 4, 2, 1),  # ConvBig
+    (16, 16, 32, 3, 2, 1), (32, 8, 32, 3, 1, 1), (16, 16, 32, 1, 2, 0), (3, 32, 16, 3, 2, 1),   # ResNet6
+    (5, 7, 17, 3, 2, 1), (20, 9, 24, 4, 2, 1), (18, 6, 40, 2, 1, 0),                        # ragged
+]
+
+
+@pytest.mark.parametrize("geom", CONV_GEOMS)
+def test_conv_kernels_match_oracle(geom):
+    P = _P()
+    ci, h, co, k, s, p = geom
+    rng = np.random.default_rng(hash(geom) % 2**32)
+    nodes = [{"kind": "input", "shape": (ci, h, h)},
+             {"kind": "conv", "src": 0, "W": rng.normal(size=(co, ci, k, k)).astype(np.float32),
+              "b": rng.normal(size=co).astype(np.float32), "stride": s, "pad": p},
+             {"kind": "relu", "src": 1},
+             {"kind": "fc", "src": 2, "W": np.ones((2, co * ((h + 2 * p - k) // s + 1) ** 2), np.float32),
+              "b": np.zeros(2, np.float32)}]
+    net = P.Net(nodes)
+    onet_ = onet.Net(nodes)
+    din, dout = onet_.sizes[0], onet_.sizes[1]
+    for M in (1, 37, 300):
+        A = rng.normal(size=(M, dout)).astype(np.float32)
+        ref = onet.conv_adjoint(onet_.nodes[1]["W"], A.astype(np.float64), onet_.shapes[0], onet_.shapes[1], s, p)
+        a_d, c_d = _dev(A), torch.full((M, din), 7.0, device="cuda")
+        torch.cuda.synchronize()
+        net.conv_backsub(1, a_d.data_ptr(), c_d.data_ptr(), M)
+        net.sync()
+        out = c_d.cpu().numpy()
+        np.testing.assert_allclose(out, ref, rtol=0, atol=1e-5 * np.abs(ref).max() + 1e-5)
+        # accumulate mode
+        net.conv_backsub(1, a_d.data_ptr(), c_d.data_ptr(), M, accumulate=True)
+        net.sync()
+        np.testing.assert_allclose(c_d.cpu().numpy(), 2 * ref, rtol=0, atol=2e-5 * np.abs(ref).max() + 2e-5)
+        G = rng.normal(size=(M, din)).astype(np.float32)
+        reff = onet.conv_apply(onet_.nodes[1]["W"], G.astype(np.float64), onet_.shapes[0], onet_.shapes[1], s, p) \
+            + onet.bias_vector(onet_, 1)
+        g_d, o_d = _dev(G), torch.zeros((M, dout), device="cuda")
+        torch.cuda.synchronize()
+        net.conv_forward(1, g_d.data_ptr(), o_d.data_ptr(), M)
+        net.sync()
+        np.testing.assert_allclose(o_d.cpu().numpy(), reff, rtol=0, atol=1e-5 * np.abs(reff).max() + 1e-5)
+
+
+@pytest.mark.parametrize("dims", [(1, 10, 100), (37, 100, 784), (576, 100, 100), (300, 512, 4096), (129, 33, 65),
+                                  (64, 7, 3)])
+def test_fc_kernels_match_numpy(dims):
+    P = _P()
+    M, dout, din = dims
+    rng = np.random.default_rng(M * 7 + dout)
+    W = rng.normal(size=(dout, din)).astype(np.float32)
+    b = rng.normal(size=dout).astype(np.float32)
+    nodes = [{"kind": "input", "shape": (din, 1, 1)}, {"kind": "fc", "src": 0, "W": W, "b": b},
+             {"kind": "relu", "src": 1}, {"kind": "fc", "src": 2, "W": np.ones((1, dout), np.float32),
+                                          "b": np.zeros(1, np.float32)}]
+    net = P.Net(nodes)
+    A = rng.normal(size=(M, dout)).astype(np.float32)
+    ref = A.astype(np.float64) @ W.astype(np.float64)
+    a_d, c_d = _dev(A), torch.zeros((M, din), device="cuda")
+    torch.cuda.synchronize()
+    net.fc_backsub(1, a_d.data_ptr(), c_d.data_ptr(), M)
+    net.sync()
+    np.testing.assert_allclose(c_d.cpu().numpy(), ref, rtol=0, atol=2e-5 * np.abs(ref).max() + 1e-5)
+    G = rng.normal(size=(M, din)).astype(np.float32)
+    reff = G.astype(np.float64) @ W.astype(np.float64).T + b
+    g_d, o_d = _dev(G), torch.zeros((M, dout), device="cuda")
+    torch.cuda.synchronize()
+    net.fc_forward(1, g_d.data_ptr(), o_d.data_ptr(), M)
+    net.sync()
+    np.testing.assert_allclose(o_d.cpu().numpy(), reff, rtol=0, atol=2e-5 * np.abs(reff).max() + 1e-5)
+
+
+# --------------------------------------------------------------------------- root pass
+ROOT_CASES = [(1, "small"), (2, "small"), (3, "small"), (4, "small"), (1, "full"), (2, "full")]
+
+
+@pytest.mark.parametrize("cfg,scale", ROOT_CASES)
+def test_bound_init_matches_oracle(cfg, scale):
+    P = _P()
+    wl = W.make_workload(cfg, scale=scale)
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=8)
+    rid, lb, ub = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    print(f"cfg{cfg}/{scale}: gpu lb {lb[:3]} oracle {root.lb[:3]}", flush=True)
+    assert_parity(lb, root.lb, "root lb")
+    assert np.all(lb <= sampled_min(net_o, wl) + 1e-6)
+    assert np.all(ub >= lb)
+    for m, i in enumerate(net_o.relus):
+        l, u, S = pb.get_bounds(rid, m)
+        st = root.states[i]
+        # compare where both sides agree on the stability class decided by the interval pass
+        assert_parity(l, st.l, f"layer {m} l")
+        assert_parity(u, st.u, f"layer {m} u")
+
+
+# --------------------------------------------------------------------------- splits, T = 0 (config 1)
+def _make_subproblems(P, pb, rid, net_o, q, root, splits):
+    """Create subproblems by chained branch_split on both sides; returns (gpu ids, oracle subproblems)."""
+    ids, subs = [], []
+    for sp in splits:
+        gid, osub = rid, root
+        chain = []
+        for (m, j, sgn) in sp:
+            ch = pb.branch_split([gid], [m], [j])
+            pos, neg = obab.branch_split(net_o, osub, m, j)
+            keep = 0 if sgn > 0 else 1
+            chain.append(int(ch[1 - keep]))
+            gid = int(ch[keep])
+            osub = pos if sgn > 0 else neg
+        if chain:
+            pb.release(chain)
+        ids.append(gid)
+        subs.append(osub)
+    return np.array(ids), subs
+
+
+@pytest.mark.parametrize("scale,n_sub", [("small", 16), ("full", 64)])
+def test_config1_splits_T0(scale, n_sub):
+    P = _P()
+    wl = W.make_workload(1, scale=scale)
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=4 * n_sub + 8)
+    rid, lb0, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    splits = W.make_split_sets(root_unstable(net_o, root), n_sub, 1, 4, seed=3001)
+    ids, subs = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+    lb, ub = pb.bound_optimize(ids, steps=0)
+    ref = np.array([oo.bound_optimize(q, s, steps=0).lb for s in subs])
+    assert_parity(lb, ref, "T=0 lb")
+    assert np.all(lb >= lb0[None, :] - 1e-6)
+    for b in range(len(ids)):
+        for m, i in enumerate(net_o.relus):
+            l, u, _ = pb.get_bounds(ids[b], m)
+            assert_parity(l, subs[b].states[i].l, f"sub {b} layer {m} l")
+            assert_parity(u, subs[b].states[i].u, f"sub {b} layer {m} u")
+
+
+# --------------------------------------------------------------------------- gradient
+@pytest.mark.parametrize("cfg", [1, 2, 4])
+def test_gradient_matches_oracle(cfg):
+    P = _P()
+    wl = W.make_workload(cfg, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=16)
+    rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    unst = root_unstable(net_o, root)
+    m0 = 0
+    j0 = int(unst[0][0])
+    gid = int(pb.branch_split([rid], [m0], [j0])[0])
+    osub = obab.branch_split(net_o, root, m0, j0)[0]
+    # random feasible parameters on both sides
+    rng = np.random.default_rng(cfg)
+    offs = np.cumsum([0] + [net_o.sizes[i] for i in net_o.relus])
+    for key in oo.set_keys(net_o):
+        si = P.set_index(key)
+        alpha = rng.uniform(0, 1, offs[-1]).astype(np.float32)
+        beta = rng.uniform(0, 0.5, offs[-1]).astype(np.float32)
+        pb.set_params(gid, si, alpha=alpha, beta=beta)
+        for t, i in enumerate(net_o.relus):
+            if i in osub.sets[key]:
+                osub.sets[key][i]["alpha"] = alpha[offs[t]:offs[t + 1]].astype(np.float64)
+                osub.sets[key][i]["beta"] = beta[offs[t]:offs[t + 1]].astype(np.float64)
+    # recompute intermediate bounds with these parameters (T = 0) on both sides, then compare gradients
+    pb.bound_optimize([gid], steps=0)
+    oo.bound_optimize(q, osub, steps=0)
+    for key in oo.set_keys(net_o):
+        si = P.set_index(key)
+        lbr, ga, gb, _ = pb.bound_grad(gid, si)
+        if key == "final":
+            start, c0 = ob.spec_start(net_o, q.C), q.c0
+        else:
+            m, s = key
+            i = net_o.relus[m]
+            st = osub.states[i]
+            js = np.nonzero((st.l < 0) & (st.u > 0))[0]
+            if len(js) == 0:
+                assert len(lbr) == 0
+                continue
+            start, c0 = ob.neuron_start(net_o, i, js, s), np.zeros(len(js))
+        out = ob.backsub(net_o, start, c0, osub.states, osub.sets[key], None, q.lo, q.hi)
+        assert_parity(lbr, out["lb"], f"{key} rows")
+        g = oo.bound_grads(net_o, out)
+        ref_a = np.concatenate([g[i]["alpha"] if i in g else np.zeros(net_o.sizes[i]) for i in net_o.relus])
+        ref_b = np.concatenate([g[i]["beta"] if i in g else np.zeros(net_o.sizes[i]) for i in net_o.relus])
+        for name, gg, rr in (("alpha", ga, ref_a), ("beta", gb, ref_b)):
+            nrm = np.linalg.norm(rr)
+            assert np.linalg.norm(gg - rr) <= 1e-3 * max(nrm, 1e-6), (key, name, np.linalg.norm(gg - rr), nrm)
+
+
+# --------------------------------------------------------------------------- optimisation
+@pytest.mark.parametrize("cfg,n_sub,steps", [(1, 8, 5), (2, 6, 5), (4, 4, 3)])
+def test_optimize_matches_oracle(cfg, n_sub, steps):
+    P = _P()
+    wl = W.make_workload(cfg, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=4 * n_sub + 8)
+    rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    splits = W.make_split_sets(root_unstable(net_o, root), n_sub, 1, 3, seed=77 + cfg)
+    ids, subs = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+    lb, ub = pb.bound_optimize(ids, steps=steps, lr=0.1)
+    ref = np.array([oo.bound_optimize(q, s, steps=steps, lr=0.1).lb for s in subs])
+    print("gpu", lb[:2], "oracle", ref[:2], flush=True)
+    assert_parity(lb, ref, f"T={steps} lb")
+    smin = sampled_min(net_o, wl)
+    assert np.all(lb <= smin[None, :] + 1e-6)
+    assert np.all(ub >= lb - 1e-5)
