@@ -195,6 +195,19 @@ int mnb_kernel_fc_forward(const mnb_net* net, int node, const float* G, float* C
 int mnb_kernel_conv_forward(const mnb_net* net, int node, const float* G, float* C, int M);
 int mnb_sync(void);
 
+/* ------------------------------------------------------------------ kernel timer */
+/* HIP events recorded on the library stream around every launch of one
+ * kernel class while the timer runs.  node restricts timing to one network
+ * node (-1: all nodes of that class).  Algorithmic work per launch: products
+ * 2 * rows * (nonzero multiply-adds of the layer per row) flops; fold, relax
+ * and concretise the bytes they must move (coefficient rows read/written). */
+enum { MNB_T_FC_BACKSUB = 1, MNB_T_CONV_BACKSUB = 2, MNB_T_FC_FORWARD = 3, MNB_T_CONV_FORWARD = 4,
+       MNB_T_FOLD = 5, MNB_T_RELAX = 6, MNB_T_CONCRETIZE = 7 };
+int mnb_timer_begin(int kind, int node);
+/* Stop, wait for the stream and report launches, summed duration (ms), and
+ * summed algorithmic flops and bytes of the timed launches. */
+int mnb_timer_end(int64_t* launches, double* ms, double* flops, double* bytes);
+
 /* ------------------------------------------------------------------ serving */
 /* A verification query for the server: box, spec and MNC sets as in
  * bound_init, plus a per-query wall-clock budget. */

@@ -279,3 +279,23 @@ class Problem:
         u, c = C.c_int64(), C.c_int64()
         check(lib().mnb_problem_usage(self.h, C.byref(u), C.byref(c)))
         return u.value, c.value
+
+
+# --------------------------------------------------------------------------- kernel timer
+class KernelTimer:
+    """HIP-event timing of one kernel class inside the library (see mnb_timer_begin)."""
+
+    KINDS = {"fc_backsub": 1, "conv_backsub": 2, "fc_forward": 3, "conv_forward": 4, "fold": 5, "relax": 6,
+             "concretize": 7}
+
+    def __init__(self, net=None, kind="conv_backsub", node=-1):
+        self.kind, self.node = kind, node
+
+    def start(self):
+        check(lib().mnb_timer_begin(self.KINDS[self.kind], int(self.node)))
+
+    def stop(self):
+        n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        check(lib().mnb_timer_end(C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
+        return {"name": f"{self.kind}@node{self.node}", "count": n.value, "ms": ms.value, "flops": fl.value,
+                "bytes": by.value}

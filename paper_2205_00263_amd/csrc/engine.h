@@ -50,6 +50,14 @@ struct Workspace {
     }
 };
 
+// Kernel timer: events around launches of one kernel class (see mnb_timer_begin).
+struct TimerScope {
+    bool on = false;
+    hipEvent_t e0{}, e1{};
+    TimerScope(int kind, int node, double flops, double bytes);
+    ~TimerScope();
+};
+
 struct NetNode {
     int kind = 0, src = -1, src2 = -1;
     int C = 0, H = 0, W = 0, size = 0;
@@ -58,6 +66,7 @@ struct NetNode {
     float* bd = nullptr;
     ConvGeom geom{};
     int relu_m = -1;
+    double macs_per_row = 0;   // nonzero multiply-adds of the layer for one row
 };
 
 }  // namespace mnb

@@ -70,6 +70,39 @@ static T* upload(const T* h, size_t n, std::vector<void*>* owned) {
 static void sync() { MNB_HIP(hipStreamSynchronize(stream())); }
 }  // namespace mnb
 
+// ---------------------------------------------------------------- kernel timer
+namespace mnb {
+struct TimerState {
+    int kind = 0, node = -1;
+    bool running = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double flops = 0, bytes = 0;
+};
+static TimerState g_timer;
+static thread_local int t_timer_node = -1;
+
+TimerScope::TimerScope(int kind, int node, double flops, double bytes) {
+    if (!g_timer.running || g_timer.kind != kind || (g_timer.node >= 0 && g_timer.node != node)) return;
+    if (g_timer.used == g_timer.ev.size()) {
+        hipEvent_t a, b;
+        MNB_HIP(hipEventCreate(&a));
+        MNB_HIP(hipEventCreate(&b));
+        g_timer.ev.push_back({a, b});
+    }
+    e0 = g_timer.ev[g_timer.used].first;
+    e1 = g_timer.ev[g_timer.used].second;
+    g_timer.used++;
+    g_timer.flops += flops;
+    g_timer.bytes += bytes;
+    on = true;
+    MNB_HIP(hipEventRecord(e0, stream()));
+}
+TimerScope::~TimerScope() {
+    if (on) (void)hipEventRecord(e1, stream());
+}
+}  // namespace mnb
+
 #define API_BEGIN try {
 #define API_END                                  \
     }                                            \
@@ -98,6 +131,36 @@ extern "C" int mnb_set_allocator(mnb_alloc_fn a, mnb_free_fn f, void* ctx) {
 extern "C" int mnb_set_stream(void* s) {
     g_user_stream = (hipStream_t)s;
     return MNB_OK;
+}
+
+extern "C" int mnb_timer_begin(int kind, int node) {
+    if (kind < MNB_T_FC_BACKSUB || kind > MNB_T_CONCRETIZE) {
+        t_err = "bad timer kind";
+        return MNB_EINVAL;
+    }
+    g_timer.kind = kind;
+    g_timer.node = node;
+    g_timer.used = 0;
+    g_timer.flops = g_timer.bytes = 0;
+    g_timer.running = true;
+    return MNB_OK;
+}
+
+extern "C" int mnb_timer_end(int64_t* launches, double* ms, double* flops, double* bytes) {
+    API_BEGIN
+    g_timer.running = false;
+    sync();
+    double tot = 0;
+    for (size_t i = 0; i < g_timer.used; ++i) {
+        float t = 0;
+        MNB_HIP(hipEventElapsedTime(&t, g_timer.ev[i].first, g_timer.ev[i].second));
+        tot += t;
+    }
+    if (launches) *launches = (int64_t)g_timer.used;
+    if (ms) *ms = tot;
+    if (flops) *flops = g_timer.flops;
+    if (bytes) *bytes = g_timer.bytes;
+    API_END
 }
 
 // =====================================================================================
@@ -183,6 +246,7 @@ extern "C" int mnb_net_create(const mnb_layer* L, int n, mnb_net** out) {
                         const int din = in.C * in.H * in.W;
                         nd.Wd = upload(l.W, (size_t)nd.C * din, &net->owned);
                         nd.bd = upload(l.b, (size_t)nd.C, &net->owned);
+                        nd.macs_per_row = (double)nd.C * din;
                         break;
                     }
                     case MNB_CONV: {
@@ -201,6 +265,21 @@ extern "C" int mnb_net_create(const mnb_layer* L, int n, mnb_net** out) {
                         nd.Wd = upload(l.W, nw, &net->owned);
                         nd.bd = upload(l.b, (size_t)nd.C, &net->owned);
                         build_conv_geom(net, nd, Wh);
+                        {
+                            // nonzero multiply-adds per row: taps that do not fall on padding
+                            double taps = 0;
+                            for (int y = 0; y < nd.H; ++y)
+                                for (int ky = 0; ky < l.k; ++ky) {
+                                    int Y = y * l.stride - l.pad + ky;
+                                    if (Y < 0 || Y >= in.H) continue;
+                                    for (int x = 0; x < nd.W; ++x)
+                                        for (int kx = 0; kx < l.k; ++kx) {
+                                            int X = x * l.stride - l.pad + kx;
+                                            if (X >= 0 && X < in.W) taps += 1;
+                                        }
+                                }
+                            nd.macs_per_row = taps * nd.C * in.C;
+                        }
                         break;
                     }
                     case MNB_RELU:
@@ -560,10 +639,15 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
                 const int dst = nd.src;
                 bool acc = coef.count(dst) > 0;
                 float* out = acc ? coef[dst] : pool.acquire();
-                if (nd.kind == MNB_FC)
-                    launch_fc_backsub(a, nd.Wd, out, M, nd.size, net->nodes[dst].size, acc, st);
-                else
-                    launch_conv_backsub(nd.geom, a, out, M, acc, st);
+                {
+                    TimerScope ts(nd.kind == MNB_FC ? MNB_T_FC_BACKSUB : MNB_T_CONV_BACKSUB, n,
+                                  2.0 * M * nd.macs_per_row,
+                                  4.0 * M * (nd.size + net->nodes[dst].size * (acc ? 2 : 1)));
+                    if (nd.kind == MNB_FC)
+                        launch_fc_backsub(a, nd.Wd, out, M, nd.size, net->nodes[dst].size, acc, st);
+                    else
+                        launch_conv_backsub(nd.geom, a, out, M, acc, st);
+                }
                 coef[dst] = out;
                 pool.release(a);
                 break;
@@ -584,7 +668,10 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
                 fa.v = cx.v.count(m) ? cx.v[m] : nullptr;
                 fa.vhat = cx.vh.count(m) ? cx.vh[m] : nullptr;
                 fa.bias = net->relu_bias[m];
-                launch_relu_fold(fa, st, cx.gp.count(m) ? cx.gp[m] : nullptr);
+                {
+                    TimerScope ts(MNB_T_FOLD, n, 0.0, (double)M * nd.size * (store_ap ? 12 : 8));
+                    launch_relu_fold(fa, st, cx.gp.count(m) ? cx.gp[m] : nullptr);
+                }
                 col += fold_cols(nd.size);
                 MNB_CHECK(!coef.count(nd.src), MNB_EDEVICE, "relu input reached twice");
                 coef[nd.src] = a;
@@ -632,10 +719,15 @@ static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* 
             case MNB_FC:
             case MNB_CONV: {
                 float* out = pool.acquire();
-                if (nd.kind == MNB_FC)
-                    launch_fc_forward(g[nd.src], nd.Wd, nd.bd, out, M, net->nodes[nd.src].size, nd.size, false, st);
-                else
-                    launch_conv_forward(nd.geom, g[nd.src], out, M, false, st);
+                {
+                    TimerScope ts(nd.kind == MNB_FC ? MNB_T_FC_FORWARD : MNB_T_CONV_FORWARD, n,
+                                  2.0 * M * nd.macs_per_row, 4.0 * M * (nd.size + net->nodes[nd.src].size));
+                    if (nd.kind == MNB_FC)
+                        launch_fc_forward(g[nd.src], nd.Wd, nd.bd, out, M, net->nodes[nd.src].size, nd.size, false,
+                                          st);
+                    else
+                        launch_conv_forward(nd.geom, g[nd.src], out, M, false, st);
+                }
                 g[n] = out;
                 done_with(nd.src);
                 break;
@@ -665,7 +757,10 @@ static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* 
                 const bool mnc = pb->has_mnc;
                 ra.gsum_hat = mnc ? gs_hat : nullptr;
                 ra.gsum_out = mnc ? gs_out : nullptr;
-                launch_relu_relax(ra, st);
+                {
+                    TimerScope ts(MNB_T_RELAX, n, 0.0, 12.0 * M * nd.size);
+                    launch_relu_relax(ra, st);
+                }
                 if (mnc) {
                     auto& ml = pb->mnc[m];
                     GammaArgs ga{};
@@ -814,7 +909,10 @@ struct Evaluator {
             ca.l = pb->l; ca.u = pb->u; ca.ld_state = pb->ld_state;
             ca.state_off = net->relu_off[ch.obj_layer];
         }
-        launch_concretize(ca, st);
+        {
+            TimerScope ts(MNB_T_CONCRETIZE, 0, 0.0, (double)M * net->d0 * (4 + (ca.G0 ? 4 : 0) + (ca.xbits ? 1 : 0)));
+            launch_concretize(ca, st);
+        }
         pool.release(A0);
         if (ch.obj_layer < 0 && io.best_bits)
             launch_keep_best_x(cx.xbits, io.best_bits, io.improved, M, net->d0, st);

@@ -50,3 +50,21 @@ def sampled_min(net, wl, n=4000, seed=0):
 
 def root_unstable(net, sub):
     return [np.nonzero((sub.states[i].l < 0) & (sub.states[i].u > 0))[0] for i in net.relus]
+
+
+def sampled_min_sub(net, wl, S, n=20000, seed=0):
+    """min of the spec over samples that satisfy a subproblem's split constraints (inf if none do).
+
+    S: dict relu-node -> split diagonal (-1: zhat >= 0, +1: zhat <= 0)."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(wl.lo, wl.hi, size=(n, len(wl.lo)))
+    vals = onet.forward_all(net, X)
+    ok = np.ones(len(X), dtype=bool)
+    for i, s in S.items():
+        zh = vals[net.nodes[i]["src"]]
+        for j in np.nonzero(s)[0]:
+            ok &= (zh[:, j] >= 0) if s[j] == -1 else (zh[:, j] <= 0)
+    if not ok.any():
+        return np.full(np.asarray(wl.C).shape[0], np.inf)
+    f = vals[-1][ok] @ np.asarray(wl.C, np.float64).T + wl.c0
+    return f.min(0)
