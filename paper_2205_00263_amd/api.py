@@ -299,3 +299,67 @@ class KernelTimer:
         check(lib().mnb_timer_end(C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
         return {"name": f"{self.kind}@node{self.node}", "count": n.value, "ms": ms.value, "flops": fl.value,
                 "bytes": by.value}
+
+
+# --------------------------------------------------------------------------- serving
+VERDICTS = {1: "verified", 2: "falsified", 3: "unknown", 4: "timeout"}
+
+
+class Server:
+    """Continuous-batching verification server (query_submit / query_poll)."""
+
+    def __init__(self, nets, max_batch=256, queue_cap=4096, mem_budget=64 << 30, steps=20, lr=0.1):
+        self.nets = list(nets)
+        cfg = _lib.ServerCfg()
+        lib().mnb_server_cfg_default(C.byref(cfg))
+        cfg.max_batch, cfg.queue_cap, cfg.mem_budget = int(max_batch), int(queue_cap), int(mem_budget)
+        cfg.opt.steps, cfg.opt.lr = int(steps), float(lr)
+        arr = (C.c_void_p * len(self.nets))(*[n.h.value for n in self.nets])
+        h = C.c_void_p()
+        check(lib().mnb_server_create(arr, len(self.nets), C.byref(cfg), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().mnb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query_submit(self, net_index, lo, hi, Cm, c0, mncs=None, timeout_s=60.0):
+        lo, hi, Cm, c0 = _f32(lo), _f32(hi), _f32(Cm), _f32(c0)
+        pack = _MncPack(mncs or {})
+        q = _lib.Query()
+        q.net_index = int(net_index)
+        q.x_lo, q.x_hi, q.C, q.c0 = _ptr(lo), _ptr(hi), _ptr(Cm), _ptr(c0)
+        q.n_spec = int(Cm.shape[0])
+        q.mnc = pack.arr if pack.n else None
+        q.n_mnc = pack.n
+        q.timeout_s = float(timeout_s)
+        t = C.c_uint64()
+        check(lib().query_submit(self.h, C.byref(q), C.byref(t)))
+        return t.value
+
+    def query_poll(self, ticket):
+        r = _lib.Result()
+        rc = check(lib().query_poll(self.h, C.c_uint64(ticket), C.byref(r)))
+        if rc == _lib.MNB_PENDING:
+            return None
+        return {"verdict": VERDICTS.get(r.verdict, str(r.verdict)), "lb": r.lb, "subproblems": r.subproblems,
+                "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
+                "latency": r.t_done - r.t_submit}
+
+    def wait(self, ticket, timeout=600.0, poll_s=0.002):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.query_poll(ticket)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout:
+                raise TimeoutError(f"query {ticket} not done after {timeout} s")
+            time.sleep(poll_s)

@@ -13,6 +13,7 @@ LIB = os.path.join(ROOT, "paper_2205_00263_amd", "libmnbab.so")
 def declared_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    txt = "\n".join(ln for ln in txt.splitlines() if not ln.strip().startswith("typedef"))
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
                        txt, flags=re.M)
     return sorted(set(n for n in names if n not in ("typedef",)))
