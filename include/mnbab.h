@@ -200,9 +200,12 @@ int mnb_sync(void);
  * kernel class while the timer runs.  node restricts timing to one network
  * node (-1: all nodes of that class).  Algorithmic work per launch: products
  * 2 * rows * (nonzero multiply-adds of the layer per row) flops; fold, relax
- * and concretise the bytes they must move (coefficient rows read/written). */
+ * and concretise the bytes they must move (coefficient rows read/written);
+ * MNB_T_BOTTOM (fused first-layer fold + transposed convolution +
+ * concretisation + adjoint convolution) 4 * rows * (multiply-adds of the first
+ * convolution) flops and 4 * rows * d1 bytes. */
 enum { MNB_T_FC_BACKSUB = 1, MNB_T_CONV_BACKSUB = 2, MNB_T_FC_FORWARD = 3, MNB_T_CONV_FORWARD = 4,
-       MNB_T_FOLD = 5, MNB_T_RELAX = 6, MNB_T_CONCRETIZE = 7 };
+       MNB_T_FOLD = 5, MNB_T_RELAX = 6, MNB_T_CONCRETIZE = 7, MNB_T_BOTTOM = 8 };
 int mnb_timer_begin(int kind, int node);
 /* Stop, wait for the stream and report launches, summed duration (ms), and
  * summed algorithmic flops and bytes of the timed launches. */

@@ -1,0 +1,44 @@
+// Fused bottom-of-pass kernel (first convolution + ReLU layer 0): arguments and launcher.
+#pragma once
+
+#include "kernels.h"
+
+namespace mnb {
+
+struct BottomArgs {
+    int mode;        // 0: intermediate rows (update l/u), 1: spec rows (lb + best), 2: lb only
+    int src_mode;    // 0: rows read from A; 1: rows built from the objective convolution's filter
+    const float* A;  // [M, d1] coefficients on the output of ReLU layer 0 (src_mode 0)
+    const float* c;  // [M] (src_mode 0)
+    const float* cpart; int ldcp, ncp;
+    // objective convolution (src_mode 1): its input is the output of ReLU layer 0
+    const float* Wobj; const float* bias_obj;
+    int oCi, oHi, oWi, oCo, oHo, oWo, ok, os, op;
+    const RowDesc* rows; const InstDesc* inst; const int32_t* slots; const int32_t* qid;
+    int M, d1, d0;
+    // first convolution: input (Ci,Hi,Wi) -> ReLU layer 0 input (Co,Ho,Wo)
+    int Ci, Hi, Wi, Co, Ho, Wo, k, s, p;
+    const float* W1; const float* b1; const float* bias1;
+    const float* l; const float* u; const int8_t* S; long ld_state;
+    const float* alpha; const float* beta; long ld_param; int n_sets;
+    const float* v; const float* vhat; const float* gp;
+    const float* lo; const float* hi;
+    // outputs
+    float* lw; float* uw; int state_off_obj;
+    float* lb_out; float* best; uint8_t* improved; uint8_t* xbits;
+    int adjoint;
+    float* Gout; float* Ap_out;
+    float* d_alpha; float* d_beta; long ldg;
+    float* gsum_hat; float* gsum_out;
+    // row chunks: block b handles rows [cr0[b], cr1[b]) of instance cinst[b]; gradient
+    // partials [n_chunk][4][d1] are summed per instance in chunk order
+    const int* cinst; const int* cr0; const int* cr1; int n_chunk;
+    const int* ichunk0; const int* ichunk1;   // [n_inst] chunk range of each instance
+    float* part;
+};
+
+bool bottom_supported(int d1, int d0, int n_weights);
+void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st);
+constexpr int BOTTOM_CHUNK_ROWS = 16;
+
+}  // namespace mnb

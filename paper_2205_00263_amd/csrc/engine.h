@@ -77,6 +77,7 @@ struct mnb_net {
     std::vector<float*> relu_bias;   // effective bias of each ReLU's input node, expanded [d]
     std::vector<void*> owned;
     int total_d = 0, d0 = 0, n_out = 0, last = 0, max_width = 0;
+    bool bottom_ok = false;   // first layer is a small conv of the input feeding ReLU layer 0
     ~mnb_net();
 };
 

@@ -1,6 +1,7 @@
 // Host engine: network and problem state on the device, the back-substitution
 // passes, their adjoint, and the C ABI of include/mnbab.h.
 #include "engine.h"
+#include "bottom.h"
 
 #include <math.h>
 #include <string.h>
@@ -134,7 +135,7 @@ extern "C" int mnb_set_stream(void* s) {
 }
 
 extern "C" int mnb_timer_begin(int kind, int node) {
-    if (kind < MNB_T_FC_BACKSUB || kind > MNB_T_CONCRETIZE) {
+    if (kind < MNB_T_FC_BACKSUB || kind > MNB_T_BOTTOM) {
         t_err = "bad timer kind";
         return MNB_EINVAL;
     }
@@ -348,6 +349,13 @@ extern "C" int mnb_net_create(const mnb_layer* L, int n, mnb_net** out) {
         }
         net->total_d = off;
         MNB_CHECK(!net->relus.empty(), MNB_EINVAL, "network without ReLU layers");
+        {
+            const NetNode& r0 = net->nodes[net->relus[0]];
+            const NetNode& a1 = net->nodes[r0.src];
+            net->bottom_ok = a1.kind == MNB_CONV && a1.src == 0 &&
+                             bottom_supported(r0.size, net->d0, a1.C * net->nodes[0].C * a1.k * a1.k);
+            if (getenv("MNB_NO_FUSED_BOTTOM")) net->bottom_ok = false;
+        }
         sync();
     } catch (...) {
         delete net;
@@ -528,6 +536,9 @@ extern "C" int mnb_problem_usage(const mnb_problem* pb, int64_t* used, int64_t* 
 namespace {
 
 struct PassChunk {
+    // row chunks of the fused bottom kernel (built on first use)
+    std::vector<int> bchunk_inst, bchunk_r0, bchunk_r1, bchunk_first, bchunk_last;
+    int* bchunk_d = nullptr;
     int M = 0;                  // rows
     const RowDesc* rows = nullptr;   // device, chunk-relative row order
     std::vector<InstDesc> inst;      // host, rows relative to the chunk
@@ -590,7 +601,7 @@ static int pass_top(const mnb_net* net, int obj_layer) {
 // Back-substitute a chunk of rows from its objective down to the input (Eq. 2 and
 // Eq. 5 per node, in reverse topological order) and leave the input coefficients
 // in the returned buffer.
-static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool store_ap) {
+static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool store_ap, int stop = 0) {
     mnb_problem* pb = cx.pb;
     mnb_net* net = pb->net;
     hipStream_t st = stream();
@@ -627,7 +638,7 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
         top = pass_top(net, ch.obj_layer);
     }
     int col = 0;
-    for (int n = top; n >= 1; --n) {
+    for (int n = top; n > stop; --n) {
         auto it = coef.find(n);
         if (it == coef.end()) continue;
         float* a = it->second;
@@ -689,14 +700,14 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
         }
     }
     cx.ncp = col;
-    MNB_CHECK(coef.size() == 1 && coef.count(0), MNB_EDEVICE, "back-substitution did not reach the input");
-    return coef[0];
+    MNB_CHECK(coef.size() == 1 && coef.count(stop), MNB_EDEVICE, "back-substitution did not reach its stop node");
+    return coef[stop];
 }
 
 // Adjoint of a pass: push x* forward through every row's relaxation and reduce
 // the parameter gradients of each instance.
 static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* g_alpha, float* g_beta,
-                        float* g_gamma, float* gs_hat, float* gs_out) {
+                        float* g_gamma, float* gs_hat, float* gs_out, int start = 0, float* g_start = nullptr) {
     mnb_problem* pb = cx.pb;
     mnb_net* net = pb->net;
     hipStream_t st = stream();
@@ -705,15 +716,15 @@ static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* 
     const int n_inst = (int)ch.inst.size();
     std::vector<float*> g(net->nodes.size(), nullptr);
     std::vector<int> uses(net->nodes.size(), 0);
-    for (int n = 1; n <= top; ++n) {
+    for (int n = start + 1; n <= top; ++n) {
         uses[net->nodes[n].src]++;
         if (net->nodes[n].kind == MNB_ADD) uses[net->nodes[n].src2]++;
     }
-    g[0] = cx.G0;
+    g[start] = start == 0 ? cx.G0 : g_start;
     auto done_with = [&](int n) {
         if (--uses[n] == 0 && n != 0) pool.release(g[n]);
     };
-    for (int n = 1; n <= top; ++n) {
+    for (int n = start + 1; n <= top; ++n) {
         const NetNode& nd = net->nodes[n];
         switch (nd.kind) {
             case MNB_FC:
@@ -786,7 +797,7 @@ static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* 
                 throw Error{MNB_EDEVICE, "unexpected node in adjoint"};
         }
     }
-    for (int n = 1; n <= top; ++n)
+    for (int n = std::max(start, 1); n <= top; ++n)
         if (uses[n] > 0 && g[n]) {
             uses[n] = 0;
             pool.release(g[n]);
@@ -891,6 +902,109 @@ struct Evaluator {
         if (ch.obj_layer < 0) cx.xbits = ws.get<uint8_t>("xbits", (size_t)M * net->d0);
         gamma_projections(cx, ch, ws, "gproj");
         BufPool pool = make_pool(M, 3);
+        const int r0n = net->relus[0];
+        const bool fused = net->bottom_ok && ch.obj_layer != 0;
+        float* g_bottom = nullptr;
+        if (fused) {
+            // back-substitute down to the output of ReLU layer 0 (or build the rows there) and
+            // finish the pass, and the first part of its adjoint, in the fused bottom kernel
+            const NetNode& a1 = net->nodes[net->nodes[r0n].src];
+            BottomArgs ba{};
+            float* A1 = nullptr;
+            bool src1 = false;
+            if (ch.obj_layer == 1) {
+                const NetNode& on = net->nodes[net->nodes[net->relus[1]].src];
+                src1 = on.kind == MNB_CONV && on.src == r0n;
+                if (src1) {
+                    ba.Wobj = on.Wd; ba.bias_obj = net->relu_bias[1];
+                    ba.oCi = on.geom.Ci; ba.oHi = on.geom.Hi; ba.oWi = on.geom.Wi;
+                    ba.oCo = on.C; ba.oHo = on.H; ba.oWo = on.W; ba.ok = on.k; ba.os = on.stride; ba.op = on.pad;
+                }
+            }
+            if (!src1) {
+                A1 = run_backsub(cx, ch, pool, want_ap, r0n);
+            } else {
+                cx.ncp = 0;
+            }
+            ba.src_mode = src1 ? 1 : 0;
+            ba.A = A1; ba.c = cx.c; ba.cpart = cx.cpart; ba.ldcp = cx.ldcp; ba.ncp = cx.ncp;
+            ba.rows = ch.rows; ba.inst = ch.inst_d; ba.slots = slots_d; ba.qid = pb->qid;
+            ba.M = M; ba.d1 = net->relu_d[0]; ba.d0 = net->d0;
+            ba.Ci = a1.geom.Ci; ba.Hi = a1.geom.Hi; ba.Wi = a1.geom.Wi;
+            ba.Co = a1.C; ba.Ho = a1.H; ba.Wo = a1.W; ba.k = a1.k; ba.s = a1.stride; ba.p = a1.pad;
+            ba.W1 = a1.Wd; ba.b1 = a1.bd; ba.bias1 = net->relu_bias[0];
+            ba.l = pb->l; ba.u = pb->u; ba.S = pb->S_; ba.ld_state = pb->ld_state;
+            ba.alpha = pb->alpha; ba.beta = pb->beta; ba.ld_param = pb->ld_param; ba.n_sets = pb->n_sets;
+            ba.v = cx.v.count(0) ? cx.v[0] : nullptr;
+            ba.vhat = cx.vh.count(0) ? cx.vh[0] : nullptr;
+            ba.gp = cx.gp.count(0) ? cx.gp[0] : nullptr;
+            ba.lo = pb->lo; ba.hi = pb->hi;
+            if (ch.obj_layer < 0) {
+                ba.mode = 1;
+                ba.lb_out = io.lb_rows; ba.best = io.best; ba.improved = io.improved; ba.xbits = cx.xbits;
+            } else if (no_write) {
+                ba.mode = 2;
+                ba.lb_out = io.lb_rows;
+            } else {
+                ba.mode = 0;
+                ba.lw = pb->l; ba.uw = pb->u; ba.state_off_obj = net->relu_off[ch.obj_layer];
+            }
+            ba.adjoint = adjoint;
+            const int top = pass_top(net, ch.obj_layer);
+            if (adjoint && top > r0n) g_bottom = pool.acquire();
+            ba.Gout = g_bottom;
+            ba.Ap_out = keep_ap ? cx.ap.at(r0n) : nullptr;
+            if (adjoint || keep_ap) {
+                const int n_inst = (int)ch.inst.size();
+                ba.d_alpha = ws.get<float>("g_alpha", (size_t)n_inst * pb->ld_param);
+                ba.d_beta = ws.get<float>("g_beta", (size_t)n_inst * pb->ld_param);
+                ba.ldg = pb->ld_param;
+                if (pb->has_mnc) {
+                    ba.gsum_hat = ws.get<float>("gs_hat0", (size_t)n_inst * net->max_width);
+                    ba.gsum_out = ws.get<float>("gs_out0", (size_t)n_inst * net->max_width);
+                }
+            }
+            {
+                // fixed 16-row chunks per instance (independent of the rest of the batch)
+                const int n_inst = (int)ch.inst.size();
+                if (ch.bchunk_inst.empty()) {
+                    auto& c = const_cast<PassChunk&>(ch);
+                    for (int i = 0; i < n_inst; ++i) {
+                        c.bchunk_first.push_back((int)c.bchunk_inst.size());
+                        for (int r = ch.inst[i].r0; r < ch.inst[i].r1; r += BOTTOM_CHUNK_ROWS) {
+                            c.bchunk_inst.push_back(i);
+                            c.bchunk_r0.push_back(r);
+                            c.bchunk_r1.push_back(std::min(r + BOTTOM_CHUNK_ROWS, ch.inst[i].r1));
+                        }
+                        c.bchunk_last.push_back((int)c.bchunk_inst.size());
+                    }
+                    const std::string tg = "bch" + std::to_string((long)ch.inst_d);
+                    const int nc = (int)c.bchunk_inst.size();
+                    int* dv = ws.get<int>(tg, (size_t)3 * nc + 2 * n_inst + 4);
+                    std::vector<int> hv;
+                    hv.insert(hv.end(), c.bchunk_inst.begin(), c.bchunk_inst.end());
+                    hv.insert(hv.end(), c.bchunk_r0.begin(), c.bchunk_r0.end());
+                    hv.insert(hv.end(), c.bchunk_r1.begin(), c.bchunk_r1.end());
+                    hv.insert(hv.end(), c.bchunk_first.begin(), c.bchunk_first.end());
+                    hv.insert(hv.end(), c.bchunk_last.begin(), c.bchunk_last.end());
+                    h2d(dv, hv.data(), hv.size() * 4);
+                    c.bchunk_d = dv;
+                }
+                const int nc = (int)ch.bchunk_inst.size();
+                ba.cinst = ch.bchunk_d;
+                ba.cr0 = ch.bchunk_d + nc;
+                ba.cr1 = ch.bchunk_d + 2 * nc;
+                ba.ichunk0 = ch.bchunk_d + 3 * nc;
+                ba.ichunk1 = ch.bchunk_d + 3 * nc + n_inst;
+                ba.n_chunk = nc;
+                if (adjoint) ba.part = ws.get<float>("bpart", (size_t)nc * 4 * net->relu_d[0]);
+                TimerScope ts(MNB_T_BOTTOM, r0n, 2.0 * M * 2.0 * a1.macs_per_row, (double)M * net->relu_d[0] * 4.0);
+                launch_bottom(ba, n_inst, st);
+            }
+            if (A1) pool.release(A1);
+            if (ch.obj_layer < 0 && io.best_bits)
+                launch_keep_best_x(cx.xbits, io.best_bits, io.improved, M, net->d0, st);
+        } else {
         float* A0 = run_backsub(cx, ch, pool, want_ap);
         ConcArgs ca{};
         ca.A = A0; ca.c = cx.c; ca.cpart = cx.cpart; ca.ldcp = cx.ldcp; ca.ncp = cx.ncp;
@@ -916,6 +1030,7 @@ struct Evaluator {
         pool.release(A0);
         if (ch.obj_layer < 0 && io.best_bits)
             launch_keep_best_x(cx.xbits, io.best_bits, io.improved, M, net->d0, st);
+        }
         if (keep_ap) last_ap = cx.ap;
         if (!adjoint) return;
         const int n_inst = (int)ch.inst.size();
@@ -925,7 +1040,24 @@ struct Evaluator {
         float* gs_hat = pb->has_mnc ? ws.get<float>("gs_hat", (size_t)n_inst * net->max_width) : nullptr;
         float* gs_out = pb->has_mnc ? ws.get<float>("gs_out", (size_t)n_inst * net->max_width) : nullptr;
         if (pb->has_mnc) launch_fill(g_gamma, (long)n_inst * pb->ld_gamma, 0.f, st);
-        run_adjoint(cx, ch, pool, g_alpha, g_beta, g_gamma, gs_hat, gs_out);
+        if (fused) {
+            if (pb->has_mnc) {
+                // gamma gradient of ReLU layer 0 from the bottom kernel's column sums
+                auto& ml = pb->mnc[0];
+                GammaArgs ga{};
+                ga.inst = ch.inst_d; ga.n_inst = n_inst; ga.qid = pb->qid;
+                ga.gamma = pb->gamma; ga.ld_gamma = pb->ld_gamma; ga.n_sets = pb->n_sets; ga.goff = 0;
+                ga.d = net->relu_d[0]; ga.e_cap = pb->e_cap; ga.nnz_cap = pb->nnz_cap;
+                ga.e_of = ml.e_of; ga.colptr = ml.colptr; ga.col_e = ml.col_e; ga.col_P = ml.col_P;
+                ga.col_Ph = ml.col_Ph; ga.rowptr = ml.rowptr; ga.row_j = ml.row_j; ga.row_P = ml.row_P;
+                ga.row_Ph = ml.row_Ph; ga.p = ml.p;
+                launch_gamma_grad(ga, ws.get<float>("gs_hat0", (size_t)n_inst * net->max_width),
+                                  ws.get<float>("gs_out0", (size_t)n_inst * net->max_width), g_gamma, pb->ld_gamma, st);
+            }
+            if (g_bottom) run_adjoint(cx, ch, pool, g_alpha, g_beta, g_gamma, gs_hat, gs_out, r0n, g_bottom);
+        } else {
+            run_adjoint(cx, ch, pool, g_alpha, g_beta, g_gamma, gs_hat, gs_out);
+        }
         g_alpha_last = g_alpha;
         g_beta_last = g_beta;
         g_gamma_last = g_gamma;
