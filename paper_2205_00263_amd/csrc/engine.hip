@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <numeric>
+#include <set>
 
 using namespace mnb;
 
@@ -579,6 +580,16 @@ struct PassCtx {
     uint8_t* xbits = nullptr; // [M, d0]
     // gamma projections per relu layer: v, vhat [n_inst, d], gp [n_inst]
     std::map<int, float*> v, vh, gp;
+    // adjoint checkpoints (ckpt_stride > 1): the live coefficient rows copied before every
+    // stride-th ReLU of the pass (top first), with the partial-constant column at that point
+    int ckpt_stride = 1;
+    struct Ckpt {
+        int node;
+        int col;
+        std::map<int, float*> coef;
+    };
+    std::vector<Ckpt> ckpts;
+    Workspace* ws = nullptr;
 };
 
 static int fold_cols(int d) { return cdiv(d, 256) * 4; }
@@ -601,46 +612,35 @@ static int pass_top(const mnb_net* net, int obj_layer) {
 // Back-substitute a chunk of rows from its objective down to the input (Eq. 2 and
 // Eq. 5 per node, in reverse topological order) and leave the input coefficients
 // in the returned buffer.
-static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool store_ap, int stop = 0) {
+// Process nodes (to, from] of a pass in reverse topological order (Eq. 2 / Eq. 5 per
+// node).  With record_ckpt and a checkpoint stride > 1 the live coefficient rows are
+// copied before every stride-th ReLU (counting from the top of the pass).
+static void walk_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, std::map<int, float*>& coef, int from,
+                         int to, bool store_ap, int& col, bool record_ckpt) {
     mnb_problem* pb = cx.pb;
     mnb_net* net = pb->net;
     hipStream_t st = stream();
     const int M = ch.M;
-    std::map<int, float*> coef;
-    int top;
-    if (ch.obj_layer < 0) {
-        top = net->nodes[net->last].src;
-        float* A = pool.acquire();
-        const int d = net->nodes[top].size;
-        launch_init_spec(ch.rows, M, cx.slots_d, pb->qid, pb->Chat, pb->chat, pb->S, d, A, cx.c, st);
-        coef[top] = A;
-    } else {
-        const int ri = net->relus[ch.obj_layer];
-        const int on = net->nodes[ri].src;
-        const NetNode& o = net->nodes[on];
-        const float* be = net->relu_bias[ch.obj_layer];
-        auto init_aff = [&](int n, bool write_c) {
-            const NetNode& a = net->nodes[n];
-            float* A = pool.acquire();
-            if (a.kind == MNB_FC)
-                launch_init_fc(ch.rows, M, a.Wd, be, net->nodes[a.src].size, A, cx.c, write_c, st);
-            else
-                launch_init_conv(ch.rows, M, a.geom, be, A, cx.c, write_c, st);
-            MNB_CHECK(!coef.count(a.src), MNB_EINVAL, "objective operands share a producer");
-            coef[a.src] = A;
-        };
-        if (o.kind == MNB_ADD) {
-            init_aff(o.src, true);
-            init_aff(o.src2, false);
-        } else {
-            init_aff(on, true);
-        }
-        top = pass_top(net, ch.obj_layer);
-    }
-    int col = 0;
-    for (int n = top; n > stop; --n) {
+    int relu_seen = 0;
+    for (int n = from; n > to; --n) {
         auto it = coef.find(n);
         if (it == coef.end()) continue;
+        if (record_ckpt && cx.ckpt_stride > 1 && net->nodes[n].kind == MNB_RELU) {
+            if (relu_seen % cx.ckpt_stride == 0) {
+                PassCtx::Ckpt ck;
+                ck.node = n;
+                ck.col = col;
+                for (auto& kv : coef) {
+                    const size_t cnt = (size_t)M * net->nodes[kv.first].size;
+                    float* cp = cx.ws->get<float>("ck" + std::to_string(cx.ckpts.size()) + "_" + std::to_string(kv.first),
+                                                  cnt);
+                    MNB_HIP(hipMemcpyAsync(cp, kv.second, cnt * sizeof(float), hipMemcpyDeviceToDevice, st));
+                    ck.coef[kv.first] = cp;
+                }
+                cx.ckpts.push_back(ck);
+            }
+            ++relu_seen;
+        }
         float* a = it->second;
         coef.erase(it);
         const NetNode& nd = net->nodes[n];
@@ -699,6 +699,46 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
                 throw Error{MNB_EDEVICE, "unexpected node in back-substitution"};
         }
     }
+}
+
+static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool store_ap, int stop = 0) {
+    mnb_problem* pb = cx.pb;
+    mnb_net* net = pb->net;
+    hipStream_t st = stream();
+    const int M = ch.M;
+    std::map<int, float*> coef;
+    int top;
+    if (ch.obj_layer < 0) {
+        top = net->nodes[net->last].src;
+        float* A = pool.acquire();
+        const int d = net->nodes[top].size;
+        launch_init_spec(ch.rows, M, cx.slots_d, pb->qid, pb->Chat, pb->chat, pb->S, d, A, cx.c, st);
+        coef[top] = A;
+    } else {
+        const int ri = net->relus[ch.obj_layer];
+        const int on = net->nodes[ri].src;
+        const NetNode& o = net->nodes[on];
+        const float* be = net->relu_bias[ch.obj_layer];
+        auto init_aff = [&](int n, bool write_c) {
+            const NetNode& a = net->nodes[n];
+            float* A = pool.acquire();
+            if (a.kind == MNB_FC)
+                launch_init_fc(ch.rows, M, a.Wd, be, net->nodes[a.src].size, A, cx.c, write_c, st);
+            else
+                launch_init_conv(ch.rows, M, a.geom, be, A, cx.c, write_c, st);
+            MNB_CHECK(!coef.count(a.src), MNB_EINVAL, "objective operands share a producer");
+            coef[a.src] = A;
+        };
+        if (o.kind == MNB_ADD) {
+            init_aff(o.src, true);
+            init_aff(o.src2, false);
+        } else {
+            init_aff(on, true);
+        }
+        top = pass_top(net, ch.obj_layer);
+    }
+    int col = 0;
+    walk_backsub(cx, ch, pool, coef, top, stop, store_ap, col, true);
     cx.ncp = col;
     MNB_CHECK(coef.size() == 1 && coef.count(stop), MNB_EDEVICE, "back-substitution did not reach its stop node");
     return coef[stop];
@@ -723,6 +763,35 @@ static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* 
     g[start] = start == 0 ? cx.G0 : g_start;
     auto done_with = [&](int n) {
         if (--uses[n] == 0 && n != 0) pool.release(g[n]);
+    };
+    // checkpointed mode: rebuild a' of one segment (between two checkpoints) from its
+    // checkpoint just before the forward pass reaches it; only that segment's a' is live
+    std::set<int> ready;
+    auto recompute_segment = [&](int n) {
+        int s = -1;
+        for (int k = 0; k < (int)cx.ckpts.size(); ++k)
+            if (cx.ckpts[k].node >= n) s = k;
+        MNB_CHECK(s >= 0, MNB_EDEVICE, "no checkpoint above ReLU node " + std::to_string(n));
+        const PassCtx::Ckpt& ck = cx.ckpts[s];
+        const int lower = s + 1 < (int)cx.ckpts.size() ? cx.ckpts[s + 1].node : start;
+        std::map<int, float*> coef;
+        for (auto& kv : ck.coef) {
+            float* b = pool.acquire();
+            MNB_HIP(hipMemcpyAsync(b, kv.second, (size_t)M * net->nodes[kv.first].size * sizeof(float),
+                                   hipMemcpyDeviceToDevice, st));
+            coef[kv.first] = b;
+        }
+        int k = 0;
+        for (int i = ck.node; i > lower; --i)
+            if (net->nodes[i].kind == MNB_RELU) {
+                cx.ap[i] = cx.ws->get<float>("apseg" + std::to_string(k++), (size_t)M * net->max_width);
+                ready.insert(i);
+            }
+        int col = ck.col;
+        walk_backsub(cx, ch, pool, coef, ck.node, lower, true, col, false);
+        std::set<float*> live;
+        for (auto& kv : coef) live.insert(kv.second);
+        for (auto& kv : coef) pool.release(kv.second);
     };
     for (int n = start + 1; n <= top; ++n) {
         const NetNode& nd = net->nodes[n];
@@ -754,6 +823,7 @@ static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* 
             }
             case MNB_RELU: {
                 const int m = nd.relu_m;
+                if (cx.ckpt_stride > 1 && !ready.count(n)) recompute_segment(n);
                 float* G = g[nd.src];
                 RelaxArgs ra{};
                 ra.G = G;
@@ -880,6 +950,7 @@ struct Evaluator {
     }
 
     bool no_write = false;   // concretise intermediate rows without touching l/u, skip Adam
+    int ckpt_stride = 1;     // adjoint checkpoint stride over ReLU layers (1: keep every a')
     float *g_alpha_last = nullptr, *g_beta_last = nullptr, *g_gamma_last = nullptr;
     void eval(const PassChunk& ch, bool adjoint, bool keep_ap, const ChunkIO& io, const mnb_opt_cfg* cfg,
               float* m_alpha, float* v_alpha, float* m_beta, float* v_beta, float* m_gamma, float* v_gamma, int t) {
@@ -895,13 +966,15 @@ struct Evaluator {
         cx.ldcp = pass_cols(net, top);
         cx.cpart = ws.get<float>("cpart", (size_t)M * cx.ldcp);
         cx.G0 = ws.get<float>("G0", (size_t)M * net->d0);
-        const bool want_ap = adjoint || keep_ap;
+        cx.ws = &ws;
+        cx.ckpt_stride = (adjoint && !keep_ap && ckpt_stride > 1) ? ckpt_stride : 1;
+        const bool want_ap = (adjoint || keep_ap) && cx.ckpt_stride == 1;
         if (want_ap)
             for (int i : net->relus)
                 if (i <= top) cx.ap[i] = ws.get<float>("ap" + std::to_string(i), (size_t)M * net->nodes[i].size);
         if (ch.obj_layer < 0) cx.xbits = ws.get<uint8_t>("xbits", (size_t)M * net->d0);
         gamma_projections(cx, ch, ws, "gproj");
-        BufPool pool = make_pool(M, 3);
+        BufPool pool = make_pool(M, cx.ckpt_stride > 1 ? 6 : 3);
         const int r0n = net->relus[0];
         const bool fused = net->bottom_ok && ch.obj_layer != 0;
         float* g_bottom = nullptr;

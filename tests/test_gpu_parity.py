@@ -253,3 +253,68 @@ def test_optimize_matches_oracle(cfg, n_sub, steps):
     ref_ub = np.array([s.ub for s in subs])
     close = np.abs(ub - ref_ub) <= 1e-3 * np.maximum(1.0, np.abs(ref_ub))
     assert close.mean() >= 0.9, close.mean()
+
+
+# --------------------------------------------------------------------------- checkpointed adjoint
+@pytest.mark.parametrize("cfg,stride", [(1, 2), (2, 2), (4, 2), (4, 3)])
+def test_checkpointed_adjoint_is_bitwise_identical(cfg, stride):
+    """Layer-wise recomputation from checkpoints gives exactly the stored-a' result."""
+    P = _P()
+    wl = W.make_workload(cfg, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    splits = W.make_split_sets(root_unstable(net_o, root), 6, 1, 3, seed=11)
+    out = []
+    for st in (1, stride):
+        net = P.Net(wl.nodes)
+        pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=64)
+        rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+        ids, _ = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+        lb, ub = pb.bound_optimize(ids, steps=4, ckpt_stride=st)
+        alphas = np.stack([pb.get_params(i, 0)[0] for i in ids])
+        out.append((lb, ub, alphas))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+
+
+def test_chunked_passes_are_bitwise_identical():
+    """A memory budget that splits passes into chunks does not change any result."""
+    P = _P()
+    wl = W.make_workload(2, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    splits = W.make_split_sets(root_unstable(net_o, root), 12, 1, 4, seed=12)
+    out = []
+    for budget in (0, 2 << 20):
+        net = P.Net(wl.nodes)
+        pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=128)
+        rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+        ids, _ = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+        out.append(pb.bound_optimize(ids, steps=3, mem_budget=budget))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_batch_composition_does_not_change_results():
+    """A subproblem bounded alone or inside a larger, permuted batch gives bitwise the same bound."""
+    P = _P()
+    wl = W.make_workload(4, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    splits = W.make_split_sets(root_unstable(net_o, root), 8, 1, 3, seed=13)
+    net = P.Net(wl.nodes)
+    res = {}
+    for mode in ("alone", "batch"):
+        pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=128)
+        rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+        ids, _ = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+        if mode == "alone":
+            res[mode] = np.stack([pb.bound_optimize([i], steps=3)[0][0] for i in ids])
+        else:
+            perm = np.random.default_rng(0).permutation(len(ids))
+            lb, _ = pb.bound_optimize(ids[perm], steps=3)
+            back = np.empty_like(lb)
+            back[perm] = lb
+            res[mode] = back
+    np.testing.assert_array_equal(res["alone"], res["batch"])
