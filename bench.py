@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--adam-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--roofline-kernel", default="bottom",
+                    help="kernel class timed for the roofline object (dominant one for this workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -111,7 +113,7 @@ def main():
     batches = [make_batch(P, pb, rid, splits) for _ in range(n_steps)]
     kw = dict(steps=args.adam_steps, lr=0.1)
 
-    timer = P.KernelTimer(net)
+    timer = P.KernelTimer(net, kind=args.roofline_kernel)
     for b in batches[: args.warmup]:
         pb.bound_optimize(b, **kw)
     torch.cuda.synchronize()
@@ -134,7 +136,9 @@ def main():
         avg_s = kstats["ms"] / kstats["count"] / 1e3
         flops = kstats["flops"] / kstats["count"]
         achieved = flops / avg_s / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": 157.3, "unit": "TFLOP/s",
+        # the fused bottom kernel runs its convolutions on the FP32 vector ALUs; the GEMMs on MFMA
+        bound = "alu" if args.roofline_kernel in ("bottom", "fold", "relax", "concretize") else "mfma"
+        roof = {"bound": bound, "achieved": round(achieved, 3), "peak": 157.3, "unit": "TFLOP/s",
                 "frac": round(achieved / 157.3, 4), "traffic": None, "kernel": kstats["name"],
                 "launches": kstats["count"], "avg_us": round(avg_s * 1e6, 2),
                 "algorithmic_gflop_per_launch": round(flops / 1e9, 4)}

@@ -39,6 +39,8 @@ struct BottomArgs {
 
 bool bottom_supported(int d1, int d0, int n_weights);
 void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st);
+// instance gradients from the chunk partials (after launch_bottom with adjoint)
+void launch_bottom_reduce(const BottomArgs& a, int n_inst, hipStream_t st);
 constexpr int BOTTOM_CHUNK_ROWS = 16;
 
 }  // namespace mnb

@@ -347,10 +347,12 @@ void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
     else
         launch_bottom_k<0, 0, 0>(a, nb, lds, st);
     MNB_HIP(hipGetLastError());
-    if (a.adjoint) {
-        hipLaunchKernelGGL(k_bottom_reduce, dim3(cdiv(a.d1, 256), n_inst), dim3(256), 0, st, a);
-        MNB_HIP(hipGetLastError());
-    }
+}
+
+void launch_bottom_reduce(const BottomArgs& a, int n_inst, hipStream_t st) {
+    if (!a.adjoint || n_inst <= 0 || a.n_chunk <= 0) return;
+    hipLaunchKernelGGL(k_bottom_reduce, dim3(cdiv(a.d1, 256), n_inst), dim3(256), 0, st, a);
+    MNB_HIP(hipGetLastError());
 }
 
 }  // namespace mnb

@@ -180,13 +180,19 @@ static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>&
     g.k = nd.k; g.s = nd.stride; g.p = nd.pad;
     g.W = nd.Wd; g.b = nd.bd;
     const int k = g.k, s = g.s;
-    // forward gather table
-    std::vector<int2> ft(g.Ci * k * k);
-    for (int ci = 0; ci < g.Ci; ++ci)
-        for (int ky = 0; ky < k; ++ky)
-            for (int kx = 0; kx < k; ++kx)
-                ft[(ci * k + ky) * k + kx] = make_int2(ci * g.Hi * g.Wi + ky * g.Wi + kx, (ky << 16) | kx);
+    // forward gather table and weights with K ordered (ky, kx, ci), input channel innermost
+    std::vector<int2> ft((size_t)g.Ci * k * k);
+    std::vector<float> wf((size_t)g.Co * g.Ci * k * k);
+    for (int ky = 0; ky < k; ++ky)
+        for (int kx = 0; kx < k; ++kx)
+            for (int ci = 0; ci < g.Ci; ++ci) {
+                const int kk2 = (ky * k + kx) * g.Ci + ci;
+                ft[kk2] = make_int2(ci * g.Hi * g.Wi + ky * g.Wi + kx, (ky << 16) | kx);
+                for (int co = 0; co < g.Co; ++co)
+                    wf[(size_t)co * g.Ci * k * k + kk2] = Wh[(((size_t)co * g.Ci + ci) * k + ky) * k + kx];
+            }
     g.fwd_ktab = upload(ft.data(), ft.size(), &net->owned);
+    g.Wf = upload(wf.data(), wf.size(), &net->owned);
     // stride phases of the transposed convolution
     MNB_CHECK(s * s <= 16, MNB_EINVAL, "conv stride above 4 is not supported");
     g.n_phase = 0;
@@ -206,10 +212,11 @@ static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>&
             if (T > 0) {
                 std::vector<float> wp((size_t)g.Co * T * g.Ci);
                 std::vector<int2> kt((size_t)g.Co * T);
+                // K ordered (ty, tx, co): output channel innermost
                 for (int co = 0; co < g.Co; ++co)
                     for (int ty = 0; ty < ph.Ty; ++ty)
                         for (int tx = 0; tx < ph.Tx; ++tx) {
-                            const int kk = (co * ph.Ty + ty) * ph.Tx + tx;
+                            const int kk = (ty * ph.Tx + tx) * g.Co + co;
                             kt[kk] = make_int2(co * g.Ho * g.Wo - ty * g.Wo - tx, (ty << 16) | tx);
                             for (int ci = 0; ci < g.Ci; ++ci)
                                 wp[(size_t)kk * g.Ci + ci] =
@@ -1071,8 +1078,12 @@ struct Evaluator {
                 ba.ichunk1 = ch.bchunk_d + 3 * nc + n_inst;
                 ba.n_chunk = nc;
                 if (adjoint) ba.part = ws.get<float>("bpart", (size_t)nc * 4 * net->relu_d[0]);
-                TimerScope ts(MNB_T_BOTTOM, r0n, 2.0 * M * 2.0 * a1.macs_per_row, (double)M * net->relu_d[0] * 4.0);
-                launch_bottom(ba, n_inst, st);
+                {
+                    TimerScope ts(MNB_T_BOTTOM, r0n, 2.0 * M * (adjoint ? 2.0 : 1.0) * a1.macs_per_row,
+                                  (double)M * net->relu_d[0] * 4.0 * (src1 ? 0.0 : 1.0) + (double)M * net->d0);
+                    launch_bottom(ba, n_inst, st);
+                }
+                launch_bottom_reduce(ba, n_inst, st);
             }
             if (A1) pool.release(A1);
             if (ch.obj_layer < 0 && io.best_bits)

@@ -29,6 +29,9 @@ struct FcBack {
     __device__ MCtx mctx(int m) const { return {(long)m * K, (long)m * N, m < M}; }
     __device__ float a(const MCtx& c, int k) const { return (c.ok && k < K) ? A[c.base + k] : 0.f; }
     __device__ float b(int k, int n) const { return (k < K && n < N) ? W[(long)k * N + n] : 0.f; }
+    static constexpr int tile_ok = 0;
+    template <int NA>
+    __device__ void a_tile(const MCtx&, int, const int*, float*) const {}
     __device__ void store_ctx(const MCtx& c, int n, float v) const {
         if (c.ok && n < N) {
             float* p = C + c.cbase + n;
@@ -46,6 +49,9 @@ struct FcFwd {
     __device__ MCtx mctx(int m) const { return {(long)m * K, (long)m * N, m < M}; }
     __device__ float a(const MCtx& c, int k) const { return (c.ok && k < K) ? A[c.base + k] : 0.f; }
     __device__ float b(int k, int n) const { return (k < K && n < N) ? W[(long)n * K + k] : 0.f; }
+    static constexpr int tile_ok = 0;
+    template <int NA>
+    __device__ void a_tile(const MCtx&, int, const int*, float*) const {}
     __device__ void store_ctx(const MCtx& c, int n, float v) const {
         if (c.ok && n < N) {
             float* p = C + c.cbase + n;
@@ -86,6 +92,19 @@ struct ConvBack {
         return A[c.base + t.x];
     }
     __device__ float b(int k, int n) const { return (k < K && n < N) ? Wp[(long)k * N + n] : 0.f; }
+    // A elements k0 + ks[i] of one K-tile that lies within a single tap (Co % 16 == 0)
+    int tile_ok, Co, Tx, HoWo;
+    template <int NA>
+    __device__ void a_tile(const MCtx& c, int k0, const int* ks, float* out) const {
+        const int tap = k0 / Co;
+        const int ty = tap / Tx, tx = tap - ty * Tx;
+        const int co0 = k0 - tap * Co;
+        const int y = c.yb - ty, x = c.xb - tx;
+        const bool ok = c.ok && k0 < K && (unsigned)y < (unsigned)Ho && (unsigned)x < (unsigned)Wo;
+        const float* src = A + (c.base + (long)co0 * HoWo - ty * Wo - tx);
+#pragma unroll
+        for (int i = 0; i < NA; ++i) out[i] = ok ? src[(long)ks[i] * HoWo] : 0.f;
+    }
     __device__ void store_ctx(const MCtx& c, int n, float v) const {
         if (c.ok && n < N) {
             float* p = C + c.cbase + (long)n * HiWi;
@@ -124,6 +143,19 @@ struct ConvFwd {
         return A[c.base + t.x];
     }
     __device__ float b(int k, int n) const { return (k < K && n < N) ? W[(long)n * K + k] : 0.f; }
+    // A elements of one K-tile within a single tap (Ci % 16 == 0)
+    int tile_ok, Ci, kw, HiWi;
+    template <int NA>
+    __device__ void a_tile(const MCtx& c, int k0, const int* ks, float* out) const {
+        const int tap = k0 / Ci;
+        const int ky = tap / kw, kx = tap - ky * kw;
+        const int ci0 = k0 - tap * Ci;
+        const int y = c.iy + ky, x = c.ix + kx;
+        const bool ok = c.ok && k0 < K && (unsigned)y < (unsigned)Hi && (unsigned)x < (unsigned)Wi;
+        const float* src = A + (c.base + (long)ci0 * HiWi + ky * Wi + kx);
+#pragma unroll
+        for (int i = 0; i < NA; ++i) out[i] = ok ? src[(long)ks[i] * HiWi] : 0.f;
+    }
     __device__ void store_ctx(const MCtx& c, int n, float v) const {
         if (c.ok && n < N) {
             float* q = C + c.cbase + (long)n * Ho * Wo;
@@ -183,8 +215,15 @@ __global__ __launch_bounds__(256) void k_gemm(P p) {
     float ra[A_PER], rb[B_PER];
     auto load = [&](int kt) {
         const int k0 = kt * BK;
-        for (int i = 0; i < A_PER; ++i)
-            ra[i] = p.a(actx[P::A_MFAST ? 0 : i], k0 + a_k[i]);
+        if (P::A_MFAST && p.tile_ok) {
+            int kofs[A_PER];
+#pragma unroll
+            for (int i = 0; i < A_PER; ++i) kofs[i] = a_k[i] - a_k[0];
+            p.template a_tile<A_PER>(actx[0], k0 + a_k[0], kofs, ra);
+        } else {
+            for (int i = 0; i < A_PER; ++i)
+                ra[i] = p.a(actx[P::A_MFAST ? 0 : i], k0 + a_k[i]);
+        }
         for (int i = 0; i < B_PER; ++i) rb[i] = p.b(k0 + b_k[i], n0 + b_n[i]);
     };
     auto stash = [&](int buf) {
@@ -323,6 +362,8 @@ void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, boo
         p.ldA = g.Co * g.Ho * g.Wo; p.ldC = g.Ci * g.Hi * g.Wi; p.HiWi = g.Hi * g.Wi; p.Wi = g.Wi;
         p.Y0 = ph.Y0; p.X0 = ph.X0; p.s = g.s; p.q0y = ph.q0y; p.q0x = ph.q0x;
         p.acc = accumulate;
+        p.Co = g.Co; p.Tx = ph.Tx; p.HoWo = g.Ho * g.Wo;
+        p.tile_ok = (g.Co % BK) == 0;
         run_gemm(p, st);
     }
 }
@@ -331,7 +372,9 @@ void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, boo
                          hipStream_t st) {
     if (M <= 0) return;
     ConvFwd p;
-    p.A = G; p.C = C; p.W = g.W; p.bias = g.b; p.ktab = g.fwd_ktab;
+    p.A = G; p.C = C; p.W = g.Wf; p.bias = g.b; p.ktab = g.fwd_ktab;
+    p.Ci = g.Ci; p.kw = g.k; p.HiWi = g.Hi * g.Wi;
+    p.tile_ok = (g.Ci % BK) == 0;
     p.M = M * g.Ho * g.Wo; p.N = g.Co; p.K = g.Ci * g.k * g.k;
     p.Ho = g.Ho; p.Wo = g.Wo; p.Hi = g.Hi; p.Wi = g.Wi;
     p.ldA = g.Ci * g.Hi * g.Wi; p.ldC = g.Co * g.Ho * g.Wo; p.s = g.s; p.p = g.p;

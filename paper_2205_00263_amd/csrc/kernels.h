@@ -12,15 +12,16 @@ struct ConvPhase {
     int nY, nX;         // positions of the phase
     int Ty, Tx;         // taps of the phase
     int q0y, q0x;       // (Y0 + pad - rho)/stride
-    const float* Wp;    // [Co][Ty][Tx][Ci] weights of the phase
-    const int2* ktab;   // [Co*Ty*Tx] {co*Ho*Wo - ty*Wo - tx, (ty<<16)|tx}
+    const float* Wp;    // [Ty][Tx][Co][Ci] weights of the phase
+    const int2* ktab;   // [Ty*Tx*Co] {co*Ho*Wo - ty*Wo - tx, (ty<<16)|tx}
 };
 
 struct ConvGeom {
     int Ci, Hi, Wi, Co, Ho, Wo, k, s, p;
     const float* W;     // [Co][Ci][k][k]
     const float* b;     // [Co]
-    const int2* fwd_ktab;  // [Ci*k*k] {ci*Hi*Wi + ky*Wi + kx, (ky<<16)|kx}
+    const int2* fwd_ktab;  // [k*k*Ci] {ci*Hi*Wi + ky*Wi + kx, (ky<<16)|kx}, K ordered (ky, kx, ci)
+    const float* Wf;       // [Co][k*k*Ci] weights in that K order
     int n_phase;
     ConvPhase ph[16];   // stride <= 4
 };
