@@ -13,6 +13,8 @@
 #include "bottom.h"
 #include "../../include/mnbab.h"
 
+#include <stdlib.h>
+
 namespace mnb {
 
 constexpr int BT = 256;     // threads
@@ -51,7 +53,12 @@ __device__ __forceinline__ void block_sum3(float& x, float& y, float& z, float (
 
 // KS: kernel size and stride of the first convolution as compile-time constants
 // (0: taken from the arguments).
-template <int NJ, int KK, int SS, int CO>
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// MF: the two first-layer convolutions run on v_mfma_f32_16x16x4_f32 (needs CO == 16 and
+// Ci*k*k <= 32): the transposed one as T = ahat^T W (positions x taps) plus a col2im
+// gather, the adjoint one as im2col(x*) W^T (positions x output channels).
+template <int NJ, int KK, int SS, int CO, bool MF>
 __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
     extern __shared__ float smem[];
     const int d1 = a.d1;
@@ -64,6 +71,7 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
     float* s_ad = s_bn + d1;            // [d1]  S beta + (Phat^T gamma)
     float* s_x = s_ad + d1;             // [d0]  x* of the current row
     float* s_w = s_x + a.d0;            // [Co*Ci*k*k] first-layer weights
+    float* s_T = s_w + a.Co * a.Ci * a.k * a.k;   // [Ho*Wo][32] tap products (MF only)
     __shared__ float red[3][4];
 
     const int ib = a.cinst[blockIdx.x];
@@ -108,6 +116,25 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
     const float* lo = a.lo + (long)q * a.d0;
     const float* hi = a.hi + (long)q * a.d0;
     __syncthreads();
+    const int lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+    const int ntap = a.Ci * kk;                  // taps (ci, ky, kx) of one output channel
+    const int MT = (HoWo + 15) >> 4;             // 16-row tiles over the positions of ReLU layer 0
+    float bT[2][4], bF[8];
+    if constexpr (MF) {
+        // transposed: B[k = co][n = tap]; adjoint: B[k = tap][n = co]
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int co = ks * 4 + lk, n = nt * 16 + lr;
+                bT[nt][ks] = n < ntap ? s_w[co * ntap + n] : 0.f;
+            }
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const int kq = ks * 4 + lk;
+            bF[ks] = kq < ntap ? s_w[lr * ntap + kq] : 0.f;
+        }
+    }
 
     for (int r = a.cr0[blockIdx.x]; r < a.cr1[blockIdx.x]; ++r) {
         const RowDesc rd = a.rows[r];
@@ -170,6 +197,27 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
         // ---- transposed first convolution and concretisation
         float lbp = 0.f, mag = 0.f;
         const int wst = a.Ci * kk;
+        if constexpr (MF) {
+            // T[pos][tap] = sum_co ahat[co][pos] W[co][tap]
+            const int NTT = ntap > 16 ? 2 : 1;
+            for (int mt = wave; mt < MT; mt += 4) {
+                const int pos = mt * 16 + lr;
+                float av[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) av[ks] = pos < HoWo ? s_ah[(ks * 4 + lk) * HoWo + pos] : 0.f;
+                for (int nt = 0; nt < NTT; ++nt) {
+                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], bT[nt][ks], acc, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int p2 = mt * 16 + 4 * lk + v;
+                        if (p2 < HoWo) s_T[p2 * 32 + nt * 16 + lr] = acc[v];
+                    }
+                }
+            }
+            __syncthreads();
+        }
         for (int o = t; o < a.d0; o += BT) {
             const int ci = div_HiWi.div(o);
             const int qq = o - ci * HiWi;
@@ -188,6 +236,10 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                     if (!KK && kx >= k) break;
                     const int x = (Xp - kx) / s;
                     if (kx >= k || x < 0 || x >= a.Wo) continue;
+                    if constexpr (MF) {
+                        acc += s_T[(y * a.Wo + x) * 32 + (ci * k + ky) * k + kx];
+                        continue;
+                    }
                     const float* ah = s_ah + y * a.Wo + x;
                     const float* w = s_w + (ci * k + ky) * k + kx;
                     if (CO) {
@@ -228,6 +280,35 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
         }
         if (a.adjoint) {
             // ---- adjoint: first convolution of x* into s_ah (ahat is no longer read) ...
+            if constexpr (MF) {
+                const int KS = (ntap + 3) >> 2;
+                for (int mt = wave; mt < MT; mt += 4) {
+                    const int pos = mt * 16 + lr;
+                    const int y = div_Wo.div(pos), x = pos - y * a.Wo;
+                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < 8; ++ks) {
+                        if (ks >= KS) break;
+                        const int kq = ks * 4 + lk;
+                        float av = 0.f;
+                        if (kq < ntap && pos < HoWo) {
+                            const int ci = kq / kk, rr = kq - ci * kk;
+                            const int ky = rr / k, kx = rr - ky * k;
+                            const int Y = s * y - a.p + ky, X = s * x - a.p + kx;
+                            if ((unsigned)Y < (unsigned)a.Hi && (unsigned)X < (unsigned)a.Wi)
+                                av = s_x[(ci * a.Hi + Y) * a.Wi + X];
+                        }
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bF[ks], acc, 0, 0, 0);
+                    }
+                    const float bco = a.b1[lr];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int p2 = mt * 16 + 4 * lk + v;
+                        if (p2 < HoWo) s_ah[lr * HoWo + p2] = acc[v] + bco;
+                    }
+                }
+                __syncthreads();
+            } else
             for (int j = t; j < d1; j += BT) {
                 const int co = div_HoWo.div(j);
                 const int qq = j - co * HoWo;
@@ -320,32 +401,41 @@ bool bottom_supported(int d1, int d0, int n_weights) {
            (5 * d1 + d0 + n_weights) * sizeof(float) <= 150 * 1024;
 }
 
-template <int KK, int SS, int CO>
+template <int KK, int SS, int CO, bool MF>
 static void launch_bottom_k(const BottomArgs& a, int n_blk, size_t lds, hipStream_t st) {
     const int nj = cdiv(a.d1, BT);
     if (nj <= 4)
-        hipLaunchKernelGGL((k_bottom<4, KK, SS, CO>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<4, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
     else if (nj <= 8)
-        hipLaunchKernelGGL((k_bottom<8, KK, SS, CO>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<8, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
     else if (nj <= 12)
-        hipLaunchKernelGGL((k_bottom<12, KK, SS, CO>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<12, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
     else
-        hipLaunchKernelGGL((k_bottom<16, KK, SS, CO>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<16, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
 }
 
 void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
     if (n_inst <= 0) return;
     MNB_CHECK(bottom_supported(a.d1, a.d0, a.Co * a.Ci * a.k * a.k) && a.k <= 3 * a.s && (a.s >= 2 || a.k <= 3),
               MNB_EDEVICE, "bottom kernel: unsupported shape");
-    const size_t lds = (size_t)(5 * a.d1 + a.d0 + a.Co * a.Ci * a.k * a.k) * sizeof(float);
+    const size_t base = (size_t)(5 * a.d1 + a.d0 + a.Co * a.Ci * a.k * a.k);
     const int nb = a.n_chunk;
     if (nb <= 0) return;
-    if (a.k == 4 && a.s == 2 && a.Co == 16)
-        launch_bottom_k<4, 2, 16>(a, nb, lds, st);
+    const bool mf = a.Co == 16 && a.Ci * a.k * a.k <= 32 &&
+                    (base + (size_t)a.Ho * a.Wo * 32) * sizeof(float) <= 150 * 1024 && !getenv("MNB_BOTTOM_VALU");
+    const size_t lds = (base + (mf ? (size_t)a.Ho * a.Wo * 32 : 0)) * sizeof(float);
+    if (mf && a.k == 4 && a.s == 2)
+        launch_bottom_k<4, 2, 16, true>(a, nb, lds, st);
+    else if (mf && a.k == 3 && a.s == 2)
+        launch_bottom_k<3, 2, 16, true>(a, nb, lds, st);
+    else if (mf)
+        launch_bottom_k<0, 0, 16, true>(a, nb, lds, st);
+    else if (a.k == 4 && a.s == 2 && a.Co == 16)
+        launch_bottom_k<4, 2, 16, false>(a, nb, lds, st);
     else if (a.k == 3 && a.s == 2 && a.Co == 16)
-        launch_bottom_k<3, 2, 16>(a, nb, lds, st);
+        launch_bottom_k<3, 2, 16, false>(a, nb, lds, st);
     else
-        launch_bottom_k<0, 0, 0>(a, nb, lds, st);
+        launch_bottom_k<0, 0, 0, false>(a, nb, lds, st);
     MNB_HIP(hipGetLastError());
 }
 
