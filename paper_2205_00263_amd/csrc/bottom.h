@@ -31,7 +31,7 @@ struct BottomArgs {
     float* d_alpha; float* d_beta; long ldg;
     float* gsum_hat; float* gsum_out;
     // row chunks: block b handles rows [cr0[b], cr1[b]) of instance cinst[b]; gradient
-    // partials [n_chunk][4][d1] are summed per instance in chunk order
+    // partials [n_chunk][3][d1] are summed per instance in chunk order
     const int* cinst; const int* cr0; const int* cr1; int n_chunk;
     const int* ichunk0; const int* ichunk1;   // [n_inst] chunk range of each instance
     float* part;
@@ -41,6 +41,6 @@ bool bottom_supported(int d1, int d0, int n_weights);
 void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st);
 // instance gradients from the chunk partials (after launch_bottom with adjoint)
 void launch_bottom_reduce(const BottomArgs& a, int n_inst, hipStream_t st);
-constexpr int BOTTOM_CHUNK_ROWS = 16;
+constexpr int BOTTOM_CHUNK_ROWS = 32;
 
 }  // namespace mnb

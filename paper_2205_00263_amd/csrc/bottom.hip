@@ -364,14 +364,17 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
         __syncthreads();   // red[] and s_x are rewritten by the next row
     }
     if (!a.adjoint) return;
-    float* pt = a.part + (long)blockIdx.x * 4 * d1;
+    // partial sums of this chunk: alpha only where the neuron is unstable, the ghat sum only
+    // where it is split or MNC sums are wanted, the g sum only for MNCs (the reduction reads
+    // exactly the same entries)
+    float* pt = a.part + (long)blockIdx.x * 3 * d1;
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         const int j = t + i * BT;
         if (j < d1) {
-            pt[j] = da[i];
-            pt[d1 + j] = sh[i];
-            pt[2 * d1 + j] = sg[i];
+            if (s_bn[j] > 0.f) pt[j] = da[i];
+            if (a.gsum_hat || a.S[(long)in.slot * a.ld_state + j] != 0) pt[d1 + j] = sh[i];
+            if (a.gsum_out) pt[2 * d1 + j] = sg[i];
         }
     }
 }
@@ -382,16 +385,22 @@ __global__ void k_bottom_reduce(BottomArgs a) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= a.d1) return;
     const InstDesc in = a.inst[ib];
+    const long so = (long)in.slot * a.ld_state + j;
+    const int sj = (int)a.S[so];
+    // unstable exactly where the fold used the triangle (same test as the kernel)
+    const float l = a.l[so], u = a.u[so];
+    const bool unst = sj == 0 && !(l >= 0.f) && !(u <= 0.f) && (-(u * l) / (u - l)) > 0.f;
+    const bool need_h = a.gsum_hat || sj != 0;
     float da = 0.f, sh = 0.f, sg = 0.f;
     for (int c = a.ichunk0[ib]; c < a.ichunk1[ib]; ++c) {
-        const float* pt = a.part + (long)c * 4 * a.d1;
-        da += pt[j];
-        sh += pt[a.d1 + j];
-        sg += pt[2 * a.d1 + j];
+        const float* pt = a.part + (long)c * 3 * a.d1;
+        if (unst) da += pt[j];
+        if (need_h) sh += pt[a.d1 + j];
+        if (a.gsum_out) sg += pt[2 * a.d1 + j];
     }
     const long go = (long)ib * a.ldg + j;
     a.d_alpha[go] = da;
-    a.d_beta[go] = (float)a.S[(long)in.slot * a.ld_state + j] * sh;
+    a.d_beta[go] = (float)sj * sh;
     if (a.gsum_hat) a.gsum_hat[(long)ib * a.d1 + j] = sh;
     if (a.gsum_out) a.gsum_out[(long)ib * a.d1 + j] = sg;
 }

@@ -1077,7 +1077,7 @@ struct Evaluator {
                 ba.ichunk0 = ch.bchunk_d + 3 * nc;
                 ba.ichunk1 = ch.bchunk_d + 3 * nc + n_inst;
                 ba.n_chunk = nc;
-                if (adjoint) ba.part = ws.get<float>("bpart", (size_t)nc * 4 * net->relu_d[0]);
+                if (adjoint) ba.part = ws.get<float>("bpart", (size_t)nc * 3 * net->relu_d[0]);
                 {
                     TimerScope ts(MNB_T_BOTTOM, r0n, 2.0 * M * (adjoint ? 2.0 : 1.0) * a1.macs_per_row,
                                   (double)M * net->relu_d[0] * 4.0 * (src1 ? 0.0 : 1.0) + (double)M * net->d0);
