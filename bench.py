@@ -7,6 +7,15 @@ neurons; one step = one bound_optimize of the batch: intermediate bounds of
 the layers after each subproblem's earliest split recomputed and alpha/beta
 optimised by 20 Adam steps (lr 0.1) through the hand-written adjoint.
 Inputs (network, boxes, subproblem state) are resident in HBM before timing.
+Beside the batch it times two per-subproblem loops on the same subproblems:
+the library called with one subproblem at a time, and a plain PyTorch loop
+(autograd + torch.optim.Adam), each with the bounds it reaches.
+
+--serving runs the query stream instead: Poisson arrivals of queries on the
+FC / ConvSmall / ConvBig nets (one spec row, eps ~ U[0.005, 0.03]) through the
+continuous-batching server, with p50/p99 query latency, subproblems/s and the
+verdict mix, and the same stream served one query at a time by a
+per-subproblem loop for comparison.
 
 Prints one JSON line (see the repository's measurement notes).
 """
@@ -89,6 +98,339 @@ def cpu_baseline(wl, splits, budget_s=20.0):
                       f"{el:.1f} s FP64 numpy"}
 
 
+# --------------------------------------------------------------------------- per-subproblem loops
+def engine_loop(pb, ids, kw, budget_s):
+    """The same library, one subproblem per bound_optimize call (no batching)."""
+    import torch
+    lat, lbs = [], []
+    t0 = time.perf_counter()
+    for sid in ids:
+        ts = time.perf_counter()
+        lb, _ = pb.bound_optimize([int(sid)], **kw)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        lbs.append(lb[0])
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return len(lbs) / (time.perf_counter() - t0), lat, np.array(lbs)
+
+
+class TorchLoop:
+    """The plain per-subproblem loop on the same GPU, written with PyTorch ops.
+
+    One subproblem at a time: the back-substitution (Eq. 2, conv layers as
+    transposed convolutions), the ReLU rule of Eq. 5 with alpha and beta, box
+    concretisation (Eq. 6) and the intermediate-bound recompute of the layers
+    after the subproblem's earliest split, with gradients by autograd and
+    torch.optim.Adam (projected), T + 1 evaluations and the best bound per row
+    kept -- the schedule bound_optimize runs, without batching or the
+    hand-written adjoint."""
+
+    def __init__(self, wl, dev="cuda"):
+        import torch
+        from workloads import node_shapes
+        self.torch = torch
+        self.nodes = wl.nodes
+        self.shapes = node_shapes(wl.nodes)
+        self.relus = [i for i, n in enumerate(wl.nodes) if n["kind"] == "relu"]
+        self.sizes = [int(np.prod(self.shapes[i])) for i in self.relus]
+        self.offs = np.cumsum([0] + self.sizes)
+        self.dev = dev
+        self.W, self.bias = {}, {}
+        for i, n in enumerate(wl.nodes):
+            if n["kind"] in ("fc", "conv"):
+                self.W[i] = torch.tensor(np.asarray(n["W"], np.float32), device=dev)
+                b = torch.tensor(np.asarray(n["b"], np.float32), device=dev)
+                c, h, w = self.shapes[i]
+                self.bias[i] = b.repeat_interleave(h * w) if n["kind"] == "conv" else b
+        self.lo = torch.tensor(np.asarray(wl.lo, np.float32), device=dev)
+        self.hi = torch.tensor(np.asarray(wl.hi, np.float32), device=dev)
+        self.C = torch.tensor(np.asarray(wl.C, np.float32), device=dev)
+        self.c0 = torch.tensor(np.asarray(wl.c0, np.float32), device=dev)
+
+    def _adjoint(self, i, a):
+        import torch.nn.functional as F
+        n = self.nodes[i]
+        if n["kind"] == "fc":
+            return a @ self.W[i]
+        ci, hi, wi = self.shapes[n["src"]]
+        co, ho, wo = self.shapes[i]
+        s, p, k = n["stride"], n["pad"], self.W[i].shape[2]
+        op = hi - ((ho - 1) * s - 2 * p + k)
+        out = F.conv_transpose2d(a.reshape(-1, co, ho, wo), self.W[i], stride=s, padding=p, output_padding=op)
+        return out.reshape(a.shape[0], -1)
+
+    def _bound(self, start_node, a, c, st, par):
+        torch = self.torch
+        coef = {start_node: a}
+        for i in range(start_node, 0, -1):
+            if i not in coef:
+                continue
+            a = coef.pop(i)
+            n = self.nodes[i]
+            if n["kind"] in ("fc", "conv"):
+                c = c + a @ self.bias[i]
+                v = self._adjoint(i, a)
+                coef[n["src"]] = coef[n["src"]] + v if n["src"] in coef else v
+            elif n["kind"] == "relu":
+                m = self.relus.index(i)
+                l, u, S = st[m]
+                al, be = par[m]
+                pos, neg = S < 0, S > 0
+                act = ~pos & ~neg & (l >= 0)
+                ina = ~pos & ~neg & ~act & (u <= 0)
+                uns = ~pos & ~neg & ~act & ~ina
+                w = torch.where(uns, u - l, torch.ones_like(u))
+                chord = torch.where(uns, u / w, torch.zeros_like(u))
+                icpt = torch.where(uns, -u * l / w, torch.zeros_like(u))
+                ngt = a < 0
+                one = (pos | act).to(a.dtype).expand_as(a)
+                D = torch.where(uns & ~ngt, al.expand_as(a), one)
+                D = torch.where(uns & ngt, chord.expand_as(a), D)
+                c = c + (a * torch.where(uns & ngt, icpt.expand_as(a), torch.zeros_like(a))).sum(1)
+                v = a * D + S * be
+                coef[n["src"]] = coef[n["src"]] + v if n["src"] in coef else v
+            elif n["kind"] == "add":
+                for s_ in (n["src"], n["src2"]):
+                    coef[s_] = coef[s_] + a if s_ in coef else a
+        a0 = coef[0]
+        return torch.minimum(a0 * self.lo, a0 * self.hi).sum(1) + c
+
+    def load(self, pb, sid, rf):
+        """Subproblem state (bounds, splits, parameters) copied from the library to torch tensors."""
+        torch = self.torch
+        R = len(self.relus)
+        st = []
+        for m in range(R):
+            l, u, S = pb.get_bounds(int(sid), m)
+            st.append([torch.tensor(l, device=self.dev), torch.tensor(u, device=self.dev),
+                       torch.tensor(S.astype(np.float32), device=self.dev)])
+        sets = [0] + [s for m in range(max(rf, 1), R) for s in (2 * m - 1, 2 * m)]
+        par = {}
+        for si in sets:
+            a_, b_, _ = pb.get_params(int(sid), si)
+            nm = R if si == 0 else (si + 1) // 2
+            par[si] = [[torch.tensor(a_[self.offs[k]:self.offs[k + 1]], device=self.dev),
+                        torch.tensor(b_[self.offs[k]:self.offs[k + 1]], device=self.dev)] for k in range(nm)]
+        return st, par, list(range(max(rf, 1), R))
+
+    def run(self, state, parent_lb, steps, lr):
+        torch = self.torch
+        st, par, layers = state
+        st = [[x.clone() for x in s] for s in st]
+        for si in par:
+            for pr in par[si]:
+                for k in range(2):
+                    pr[k] = pr[k].clone().requires_grad_()
+        rows = {m: torch.nonzero((st[m][0] < 0) & (st[m][1] > 0)).flatten() for m in layers}
+        opts = {si: torch.optim.Adam([t for pr in par[si] for t in pr], lr=lr, maximize=True) for si in par}
+        best = torch.tensor(parent_lb, device=self.dev)
+        last = len(self.nodes) - 1
+        for t in range(steps + 1):
+            objs = []
+            for m in layers:
+                js = rows[m]
+                if len(js) == 0:
+                    continue
+                src = self.nodes[self.relus[m]]["src"]
+                d = int(np.prod(self.shapes[src]))
+                for sgn, si in ((1.0, 2 * m - 1), (-1.0, 2 * m)):
+                    E = torch.zeros(len(js), d, device=self.dev)
+                    E[torch.arange(len(js), device=self.dev), js] = sgn
+                    lbm = self._bound(src, E, torch.zeros(len(js), device=self.dev), st, par[si])
+                    objs.append((si, lbm.sum()))
+                    with torch.no_grad():
+                        k = 0 if sgn > 0 else 1
+                        cur = st[m][k].clone()
+                        cur[js] = torch.maximum(cur[js], lbm) if sgn > 0 else torch.minimum(cur[js], -lbm)
+                        st[m][k] = cur
+            lbf = self._bound(last, self.C, self.c0, st, par[0])
+            objs.append((0, lbf.sum()))
+            best = torch.maximum(best, lbf.detach())
+            if t == steps:
+                break
+            for si, obj in objs:
+                opts[si].zero_grad()
+                obj.backward()
+                opts[si].step()
+                with torch.no_grad():
+                    for al, be in par[si]:
+                        al.clamp_(0.0, 1.0)
+                        be.clamp_(min=0.0)
+        return best
+
+
+def torch_loop(wl, pb, ids, rfs, parent_lb, kw, budget_s):
+    import torch
+    tl = TorchLoop(wl)
+    states = [tl.load(pb, sid, rf) for sid, rf in list(zip(ids, rfs))[:64]]   # untimed: state resident in HBM
+    tl.run(states[-1], parent_lb, 1, kw["lr"])                      # untimed warm-up (library kernels load)
+    torch.cuda.synchronize()
+    lat, lbs = [], []
+    t0 = time.perf_counter()
+    for s in states:
+        ts = time.perf_counter()
+        b = tl.run(s, parent_lb, kw["steps"], kw["lr"])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        lbs.append(b.cpu().numpy())
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return len(lbs) / (time.perf_counter() - t0), lat, np.array(lbs)
+
+
+def loop_summary(name, rate, lat, lbs, ref):
+    d = np.abs(lbs - ref[: len(lbs)])
+    return {"kind": name, "value": round(rate, 3), "unit": "subproblems/s", "sample": len(lbs),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "lb_mean": float(lbs.min(1).mean()), "batched_lb_mean": float(ref[: len(lbs)].min(1).mean()),
+            "max_abs_lb_diff_vs_batched": float(d.max()),
+            "max_rel_lb_diff_vs_batched": float((d / np.maximum(1.0, np.abs(ref[: len(lbs)]))).max())}
+
+
+# --------------------------------------------------------------------------- serving stream
+SERVE_SEED = 5005
+
+
+def make_stream(W, nodes, n, rate, seed=SERVE_SEED):
+    """Poisson arrivals; each query: a random net of the list, x0 ~ U[0,1], eps ~ U[0.005, 0.03],
+    one spec row against a random class."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for _ in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        ni = int(rng.integers(0, len(nodes)))
+        eps = float(rng.uniform(0.005, 0.03))
+        x0, lo, hi = W.make_input(nodes[ni][0]["shape"], eps, int(rng.integers(0, 2**31)))
+        Cm, c0, _ = W.make_spec(nodes[ni], x0, n_spec=1, seed=int(rng.integers(0, 2**31)))
+        out.append((t, ni, lo, hi, Cm, c0))
+    return out
+
+
+def loop_bab(pb, lo, hi, Cm, c0, kw, timeout_s, queue_cap, t_start):
+    """BaB of one query with one subproblem per bound_optimize call (lowest lb first)."""
+    import heapq
+    rid, lb, ub = pb.bound_init(lo, hi, Cm, c0)
+    if (ub < 0).any():
+        pb.release([rid])
+        return "falsified", 1
+    if (lb > 0).all():
+        pb.release([rid])
+        return "verified", 1
+    heap, order, n_sub, verdict = [(float(lb.min()), 0, rid)], 1, 0, "verified"
+    while heap:
+        if time.perf_counter() - t_start > timeout_s:
+            verdict = "timeout"
+            break
+        _, _, sid = heapq.heappop(heap)
+        lb, ub, bl, bn = pb.bound_optimize([sid], want_branch=True, **kw)
+        n_sub += 1
+        if (ub[0] < 0).any():
+            pb.release([sid])
+            verdict = "falsified"
+            break
+        if (lb[0] > 0).all():
+            pb.release([sid])
+            continue
+        if bl[0] < 0 or len(heap) + 2 > queue_cap:
+            pb.release([sid])
+            verdict = "unknown"
+            break
+        kids = pb.branch_split([sid], [int(bl[0])], [int(bn[0])])
+        pb.release([sid])
+        for k in kids:
+            heapq.heappush(heap, (float(lb[0].min()), order, int(k)))
+            order += 1
+    if heap:
+        pb.release([h[2] for h in heap])
+    return verdict, n_sub
+
+
+def serving(args):
+    import collections
+    import torch
+    import paper_2205_00263_amd as P
+    import workloads as W
+    torch.cuda.set_device(0)
+    cfgs = [int(c) for c in args.serve_nets.split(",")]
+    nodes = [W.make_net(c) for c in cfgs]
+    nets = [P.Net(n) for n in nodes]
+    stream = make_stream(W, nodes, args.serve_queries, args.serve_rate)
+    kw = dict(steps=args.adam_steps, lr=0.1)
+    srv = P.Server(nets, max_batch=args.serve_batch, steps=args.adam_steps, lr=0.1)
+    # untimed warm-up: one query per net (problem pools are created on first use)
+    for ni in range(len(nets)):
+        q = next(s for s in stream if s[1] == ni)
+        srv.wait(srv.query_submit(ni, *q[2:], timeout_s=5.0), timeout=600)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for (ta, ni, lo, hi, Cm, c0) in stream:
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.query_submit(ni, lo, hi, Cm, c0, timeout_s=args.serve_timeout))
+    print(f"[serving] {len(tickets)} queries submitted at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    res, step = [], max(1, len(tickets) // 10)
+    for k, tk in enumerate(tickets):
+        res.append(srv.wait(tk, timeout=args.serve_timeout + 3600))
+        if (k + 1) % step == 0:
+            print(f"[serving] {k + 1} results at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r["latency"] for r in res])
+    n_sub = int(sum(r["subproblems"] for r in res))
+    mix = collections.Counter(r["verdict"] for r in res)
+    per_net = {f"cfg{c}": {"queries": int(sum(1 for s in stream if s[1] == i)),
+                           "p50_s": round(float(np.percentile([r["latency"] for r, s in zip(res, stream)
+                                                               if s[1] == i] or [0], 50)), 4),
+                           "subproblems": int(sum(r["subproblems"] for r, s in zip(res, stream) if s[1] == i))}
+               for i, c in enumerate(cfgs)}
+    out = {"metric": "BaB subproblems bounded/sec + p50/p99 query latency (serving stream)",
+           "value": round(n_sub / wall, 2), "unit": "subproblems/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+           "wall_s": round(wall, 2), "queries": len(res), "subproblems": n_sub, "verdicts": dict(mix),
+           "per_net": per_net,
+           "config": {"workload": "serving_stream", "nets": [f"cfg{c}" for c in cfgs], "n_spec": 1,
+                      "eps": "U[0.005,0.03]", "arrivals": f"Poisson {args.serve_rate}/s",
+                      "timeout_s": args.serve_timeout, "max_batch": args.serve_batch, "adam_steps": args.adam_steps,
+                      "mem_budget_GiB": 64, "queue_cap": 4096}}
+    if args.serve_loop_budget > 0:
+        # the plain per-subproblem loop: queries in arrival order, one at a time, batch 1
+        pbs = [P.Problem(n, n_spec=1, capacity=4096 + 64) for n in nets]
+        for ni in range(len(nets)):   # untimed warm-up
+            q = next(s for s in stream if s[1] == ni)
+            loop_bab(pbs[ni], *q[2:], kw, 2.0, 4096, time.perf_counter())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat_l, verd_l, nsub_l, done = [], [], 0, 0
+        for (ta, ni, lo, hi, Cm, c0) in stream:
+            now = time.perf_counter() - t0
+            if now > args.serve_loop_budget:
+                break
+            if ta > now:
+                time.sleep(ta - now)
+            v, ns = loop_bab(pbs[ni], lo, hi, Cm, c0, kw, args.serve_timeout, 4096, t0 + ta)
+            lat_l.append(time.perf_counter() - t0 - ta)
+            verd_l.append(v)
+            nsub_l += ns
+            done += 1
+        wall_l = time.perf_counter() - t0
+        srv_lat = lat[:done]
+        out["per_subproblem_loop"] = {
+            "kind": "library, one subproblem per bound_optimize, queries FIFO", "queries_done": done,
+            "budget_s": args.serve_loop_budget, "value": round(nsub_l / wall_l, 2), "unit": "subproblems/s",
+            "p50_s": round(float(np.percentile(lat_l, 50)), 4), "p99_s": round(float(np.percentile(lat_l, 99)), 4),
+            "server_p50_s_same_queries": round(float(np.percentile(srv_lat, 50)), 4),
+            "server_p99_s_same_queries": round(float(np.percentile(srv_lat, 99)), 4),
+            "verdicts": dict(collections.Counter(verd_l)),
+            "verdicts_agree_with_server": int(sum(a == r["verdict"] for a, r in zip(verd_l, res)))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,16 +440,30 @@ def main():
     ap.add_argument("--adam-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-loop-baseline", action="store_true",
+                    help="skip the per-subproblem loops (library at batch 1, PyTorch autograd)")
+    ap.add_argument("--loop-budget", type=float, default=10.0, help="seconds per per-subproblem loop")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (a kernel of known traffic for counter calibration)")
     ap.add_argument("--roofline-kernel", default="bottom",
                     help="kernel class timed for the roofline object (dominant one for this workload)")
+    ap.add_argument("--serving", action="store_true", help="serving stream instead of the batch benchmark")
+    ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=10.0, help="Poisson arrival rate (queries/s)")
+    ap.add_argument("--serve-timeout", type=float, default=60.0)
+    ap.add_argument("--serve-batch", type=int, default=1024)
+    ap.add_argument("--serve-nets", default="1,2,3", help="configurations whose nets the stream draws from")
+    ap.add_argument("--serve-loop-budget", type=float, default=60.0,
+                    help="seconds for the per-subproblem FIFO loop on the same stream (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(subproblems shard across GPUs without collectives; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    if args.serving:
+        serving(args)
+        return
     import torch
     import paper_2205_00263_amd as P
     import workloads as W
@@ -123,7 +479,7 @@ def main():
     wl = W.make_workload(2)
     net = P.Net(wl.nodes)
     n_steps = args.warmup + args.steps
-    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=args.batch * (n_steps + 3) + 64)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=args.batch * (n_steps + 5) + 64)
     rid, root_lb, root_ub = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
     unstable = []
     for m in range(net.n_relu):
@@ -177,6 +533,18 @@ def main():
                           "batch_lb_mean": float(np.mean([x.min(1).mean() for x in lbs]))},
         "roofline": roof,
     }
+    if not args.no_loop_baseline:
+        ref = lbs[0]
+        ids = make_batch(P, pb, rid, splits)
+        r = engine_loop(pb, ids, kw, args.loop_budget)
+        loops = [loop_summary("library, one subproblem per call", *r, ref)]
+        pb.release(ids)
+        ids = make_batch(P, pb, rid, splits)
+        rfs = [min(m for m, _, _ in sp) + 1 for sp in splits]
+        r = torch_loop(wl, pb, ids, rfs, root_lb, kw, args.loop_budget)
+        loops.append(loop_summary("PyTorch ops + autograd + torch.optim.Adam, one subproblem at a time", *r, ref))
+        pb.release(ids)
+        out["per_subproblem_loops"] = loops
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, splits, args.cpu_budget)
     print(json.dumps(out), flush=True)

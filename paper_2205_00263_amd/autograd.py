@@ -1,0 +1,81 @@
+"""torch.autograd interface to the library's hand-written adjoint of back-substitution.
+
+`SetBound.apply(alpha, beta, gamma, problem, sid, set_idx)` evaluates one
+parameter set of one subproblem: its rows (the spec rows for set 0, the
+lower / upper rows of one ReLU layer otherwise) are back-substituted through
+Eq. 2 and the ReLU rule of Eq. 5 and concretised over the input box (Eq. 6).
+It returns the set's objective (the sum of its rows' lower bounds, the
+quantity the projected gradient ascent of Section 3.1 maximises) and the rows'
+lower bounds (not differentiable).  The backward pass is the library's
+adjoint: x* pushed forward through every row's linearised network, which
+gives d lb / d(alpha, beta, gamma) with the intermediate bounds l, u held
+constant, summed over the set's rows.  Both passes run in the HIP library;
+this module only marshals tensors.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+__all__ = ["SetBound", "set_bound", "optimize_set"]
+
+
+def _host(t):
+    return None if t is None or t.numel() == 0 else t.detach().to("cpu", torch.float32).contiguous().numpy()
+
+
+class SetBound(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, alpha, beta, gamma, problem, sid, set_idx):
+        problem.set_params(sid, set_idx, alpha=_host(alpha), beta=_host(beta), gamma=_host(gamma))
+        lb, ga, gb, gg = problem.bound_grad(sid, set_idx)
+        dev = alpha.device
+        ctx.save_for_backward(torch.from_numpy(ga).to(dev), torch.from_numpy(gb).to(dev),
+                              torch.from_numpy(np.ascontiguousarray(gg)).to(dev))
+        ctx.gamma_shape = gamma.shape
+        lbt = torch.from_numpy(lb).to(dev)
+        obj = lbt.double().sum().float()
+        ctx.mark_non_differentiable(lbt)
+        return obj, lbt
+
+    @staticmethod
+    def backward(ctx, g_obj, g_lb):
+        ga, gb, gg = ctx.saved_tensors
+        g_gamma = (gg * g_obj).reshape(ctx.gamma_shape) if gg.numel() else torch.zeros(ctx.gamma_shape,
+                                                                                      device=ga.device)
+        return ga * g_obj, gb * g_obj, g_gamma, None, None, None
+
+
+def set_bound(problem, sid, set_idx, alpha, beta, gamma=None):
+    """(objective, row lower bounds) of one parameter set at the given parameters."""
+    if gamma is None:
+        gamma = torch.zeros(0, device=alpha.device)
+    return SetBound.apply(alpha, beta, gamma, problem, sid, set_idx)
+
+
+def optimize_set(problem, sid, set_idx, steps=20, lr=0.1):
+    """Projected Adam ascent (PyTorch's optimiser, the library's adjoint) on one set.
+
+    Starts from the subproblem's stored parameters; keeps the best lower bound
+    per row over the steps + 1 evaluations and writes the final parameters back.
+    Returns the best row bounds."""
+    a0, b0, g0 = problem.get_params(sid, set_idx)
+    alpha = torch.tensor(a0, requires_grad=True)
+    beta = torch.tensor(b0, requires_grad=True)
+    gamma = torch.tensor(g0, requires_grad=True)
+    opt = torch.optim.Adam([alpha, beta, gamma], lr=lr, maximize=True)
+    best = None
+    for t in range(steps + 1):
+        obj, lb = set_bound(problem, sid, set_idx, alpha, beta, gamma)
+        best = lb.clone() if best is None else torch.maximum(best, lb)
+        if t == steps:
+            break
+        opt.zero_grad()
+        obj.backward()
+        opt.step()
+        with torch.no_grad():
+            alpha.clamp_(0.0, 1.0)
+            beta.clamp_(min=0.0)
+            gamma.clamp_(min=0.0)
+    problem.set_params(sid, set_idx, alpha=_host(alpha), beta=_host(beta), gamma=_host(gamma))
+    return best.numpy()
