@@ -203,9 +203,13 @@ int mnb_sync(void);
  * and concretise the bytes they must move (coefficient rows read/written);
  * MNB_T_BOTTOM (fused first-layer fold + transposed convolution +
  * concretisation + adjoint convolution) 4 * rows * (multiply-adds of the first
- * convolution) flops and 4 * rows * d1 bytes. */
+ * convolution) flops and 4 * rows * d1 bytes; MNB_T_BOTTOM_WIN (its
+ * window-sparse form for rows whose objective is ReLU layer 1) 2 * rows *
+ * (window positions x first-layer channels x taps) flops, doubled with the
+ * adjoint. */
 enum { MNB_T_FC_BACKSUB = 1, MNB_T_CONV_BACKSUB = 2, MNB_T_FC_FORWARD = 3, MNB_T_CONV_FORWARD = 4,
-       MNB_T_FOLD = 5, MNB_T_RELAX = 6, MNB_T_CONCRETIZE = 7, MNB_T_BOTTOM = 8 };
+       MNB_T_FOLD = 5, MNB_T_RELAX = 6, MNB_T_CONCRETIZE = 7, MNB_T_BOTTOM = 8,
+       MNB_T_BOTTOM_WIN = 9 };
 int mnb_timer_begin(int kind, int node);
 /* Stop, wait for the stream and report launches, summed duration (ms), and
  * summed algorithmic flops and bytes of the timed launches. */

@@ -286,7 +286,7 @@ class KernelTimer:
     """HIP-event timing of one kernel class inside the library (see mnb_timer_begin)."""
 
     KINDS = {"fc_backsub": 1, "conv_backsub": 2, "fc_forward": 3, "conv_forward": 4, "fold": 5, "relax": 6,
-             "concretize": 7, "bottom": 8}
+             "concretize": 7, "bottom": 8, "bottom_win": 9}
 
     def __init__(self, net=None, kind="conv_backsub", node=-1):
         self.kind, self.node = kind, node

@@ -43,4 +43,33 @@ void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st);
 void launch_bottom_reduce(const BottomArgs& a, int n_inst, hipStream_t st);
 constexpr int BOTTOM_CHUNK_ROWS = 32;
 
+// Window-sparse variant for intermediate rows whose objective is ReLU layer 1 fed by a
+// convolution of ReLU layer 0 (no MNC): one workgroup per (instance, window position).
+struct WinArgs {
+    int mode;        // 0: update l/u of the objective layer, 2: lb only
+    const RowDesc* rows; const InstDesc* inst; const int32_t* qid;
+    int d1, d0;
+    // first convolution: input (Ci,Hi,Wi) -> ReLU layer 0 input (C1,Ho,Wo)
+    int Ci, Hi, Wi, C1, Ho, Wo, k, s, p;
+    const float* W1; const float* b1;
+    // objective convolution on the output of ReLU layer 0
+    int oCi, oHi, oWi, oCo, oHo, oWo, ok, os, op;
+    const float* Wobj; const float* bobj;   // bobj: bias per objective neuron
+    const float* l; const float* u; const int8_t* S; long ld_state;
+    const float* alpha; const float* beta; long ld_param; int n_sets;
+    const float* lo; const float* hi;
+    float* lw; float* uw; int state_off_obj;
+    float* lb_out;
+    int adjoint;
+    // per instance: A_s [n_inst][d0] and {sum min(A_s lo, A_s hi), sum |A_s| max(|lo|,|hi|), S beta . b, 0}
+    float* asplit; float* scal;
+    // per (instance, window): alpha partials [E], x* sums minus n x*_s [Ci IH IH], row counts
+    float* part_a; float* part_x; int* part_n;
+    float* d_alpha; float* d_beta; long ldg;
+};
+
+bool win_supported(int C1, int Ci, int k, int s, int ok, int oCo, int d1, int d0);
+void launch_bottom_win(const WinArgs& a, int n_inst, hipStream_t st);
+void launch_bottom_win_reduce(const WinArgs& a, int n_inst, hipStream_t st);
+
 }  // namespace mnb

@@ -1,0 +1,419 @@
+// Row-resident implicit-GEMM convolutions on v_mfma_f32_16x16x4_f32 for layers
+// whose coefficient rows fit in LDS (ConvSmall's second convolution, the ResNet
+// block convolutions).
+//
+// Back-substitution through a convolution (Eq. 2) and the forward product of
+// its adjoint are, per row, small GEMMs over (channels x positions) with the
+// layer's weights as one operand.  Each wavefront stages one row into LDS with
+// a zero halo, so every tap reads the row from LDS instead of gathering it again
+// from global memory; the workgroup's four wavefronts share the weights in LDS
+// and walk disjoint rows.  Per row the K-reduction order is fixed, so a row's
+// result does not depend on the other rows of the batch.
+//   transposed (k_convT_rows): per stride phase, D[ci][pos] = sum over (tap, co)
+//       of W_phase[tap][co][ci] * A_row[co][yb - ty][xb - tx]
+//   forward    (k_conv_rows):  D[co][pos] = sum over (ky, kx, ci) of
+//       Wf[co][(ky, kx, ci)] * G_row[ci][s y - p + ky][s x - p + kx] + b[co]
+#include "kernels.h"
+
+#include <stdlib.h>
+
+#include <algorithm>
+#include <type_traits>
+
+namespace mnb {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int RT = 256;                 // threads: 4 wavefronts, one row each at a time
+constexpr size_t ROW_LDS_MAX = 128 * 1024;
+
+// Wavefront-scope ordering of the row buffer between staging and use.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exact n / d for 0 <= n < 2^22 via a float reciprocal and one correction each way.
+struct Div {
+    int d;
+    float inv;
+    __device__ explicit Div(int d_) : d(d_), inv(1.0f / (float)d_) {}
+    __device__ __forceinline__ int operator()(int n) const {
+        int q = (int)((float)n * inv);
+        if ((q + 1) * d <= n) ++q;
+        if (q * d > n) --q;
+        return q;
+    }
+};
+
+// One row of up to 256 PF floats (length a multiple of 4) held as PF float4 per lane, so
+// that the next row's global loads are in flight while the current row is computed.
+template <int PF>
+struct RowFetch {
+    f4 v[PF];
+    __device__ __forceinline__ void fetch(const float* base, long r, int rowlen, bool ok, int lane) {
+        const f4* s4 = reinterpret_cast<const f4*>(base + (ok ? r : 0) * rowlen);
+        const int n4 = rowlen >> 2;
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = lane + 64 * u;
+            v[u] = (ok && i < n4) ? s4[i] : f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    // element e = c*HW + y*W + x  ->  lds[c*CS + (y + hy)*Wq + x + hx]
+    __device__ __forceinline__ void stash(float* lds, int rowlen, int lane, const Div& dHW, const Div& dW, int HW,
+                                          int W, int CS, int Wq, int hy, int hx) const {
+        const int n4 = rowlen >> 2;
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = lane + 64 * u;
+            if (i < n4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = 4 * i + q, c = dHW(e), rem = e - c * HW, y = dW(rem), x = rem - y * W;
+                    lds[c * CS + (y + hy) * Wq + x + hx] = v[u][q];
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void stash_dense(float* lds, int rowlen, int lane) const {
+        const int n4 = rowlen >> 2;
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = lane + 64 * u;
+            if (i < n4) *reinterpret_cast<f4*>(lds + 4 * i) = v[u];
+        }
+    }
+};
+
+struct RowPh {
+    int Y0, X0, nY, nX, Ty, Tx, q0y, q0x, woff;
+};
+
+struct ConvTRowsArgs {
+    const float* A; float* C; long M; int acc;
+    int Ci, Hi, Wi, Co, Ho, Wo, s;
+    int hy, hx, Hp, Wq, CS, RP; // padded row Co x CS (CS >= Hp Wq), halo hy, hx before the first position
+    int n_phase; RowPh ph[4]; const float* Wsrc[4];
+    int wtot;
+};
+
+template <int NT, int C4, int PF>   // C4 = Co / 4; rows of at most 256 PF floats
+__global__ __launch_bounds__(RT) void k_convT_rows(ConvTRowsArgs a) {
+    extern __shared__ float sm[];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+    float* s_W = sm;
+    float* s_row = sm + a.wtot + wave * a.RP;
+    for (int f = 0; f < a.n_phase; ++f) {
+        const int n = a.ph[f].Ty * a.ph[f].Tx * a.Co * a.Ci;
+        for (int i = t; i < n; i += RT) s_W[a.ph[f].woff + i] = a.Wsrc[f][i];
+    }
+    for (int i = lane; i < a.RP; i += 64) s_row[i] = 0.f;
+    __syncthreads();
+    const int HoWo = a.Ho * a.Wo, HpWq = a.CS, HiWi = a.Hi * a.Wi;
+    const int rowA = a.Co * HoWo;
+    const long ldC = (long)a.Ci * HiWi;
+    const Div dHoWo(HoWo), dWo(a.Wo);
+    const long stride = (long)gridDim.x * 4;
+    long r = (long)blockIdx.x * 4 + wave;
+    RowFetch<PF> pf;
+    pf.fetch(a.A, r, rowA, r < a.M, lane);
+    for (; r < a.M; r += stride) {
+        pf.stash(s_row, rowA, lane, dHoWo, dWo, HoWo, a.Wo, HpWq, a.Wq, a.hy, a.hx);
+        wave_lds_sync();
+        pf.fetch(a.A, r + stride, rowA, r + stride < a.M, lane);
+        float* dst = a.C + r * ldC;
+        for (int f = 0; f < a.n_phase; ++f) {
+            const RowPh P = a.ph[f];
+            const int npos = P.nY * P.nX;
+            if (npos <= 0) continue;
+            if (P.Ty * P.Tx <= 0) {
+                // positions no tap reaches (kernel smaller than the stride): zero coefficient
+                if (!a.acc)
+                    for (int idx = lane; idx < a.Ci * npos; idx += 64) {
+                        const int ci = idx / npos, n = idx - ci * npos, i = n / P.nX, jx = n - i * P.nX;
+                        dst[(long)ci * HiWi + (P.Y0 + a.s * i) * a.Wi + P.X0 + a.s * jx] = 0.f;
+                    }
+                continue;
+            }
+            const int ntile = (npos + 15) >> 4;
+            for (int ct = 0; ct < a.Ci; ct += 16) {
+                // one group of NA position tiles (NA = NT, or the phase's remainder)
+                auto group = [&](int n0, auto na_c) {
+                    constexpr int NA = decltype(na_c)::value;
+                    int pb[NA];
+#pragma unroll
+                    for (int j = 0; j < NA; ++j) {
+                        int n = (n0 + j) * 16 + lr;
+                        n = n < npos ? n : npos - 1;
+                        const int i = n / P.nX, jx = n - i * P.nX;
+                        pb[j] = (P.q0y + i + a.hy) * a.Wq + P.q0x + jx + a.hx;
+                    }
+                    f4 acc[NA];
+#pragma unroll
+                    for (int j = 0; j < NA; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+                    // per tap, the C4 groups of 4 output channels are unrolled so that all of
+                    // the tap's LDS reads are in flight before its MFMAs
+                    const float* wl = s_W + P.woff + ct + lr + lk * a.Ci;
+                    const float* rl = s_row + lk * HpWq;
+                    for (int ty = 0; ty < P.Ty; ++ty)
+                        for (int tx = 0; tx < P.Tx; ++tx) {
+                            const int tap = ty * P.Tx + tx;
+                            const float* wt = wl + (long)tap * a.Co * a.Ci;
+                            const float* rt = rl - ty * a.Wq - tx;
+                            float av[C4], bv[C4][NA];
+#pragma unroll
+                            for (int c = 0; c < C4; ++c) {
+                                av[c] = wt[4 * c * a.Ci];
+#pragma unroll
+                                for (int j = 0; j < NA; ++j) bv[c][j] = rt[4 * c * HpWq + pb[j]];
+                            }
+#pragma unroll
+                            for (int c = 0; c < C4; ++c)
+#pragma unroll
+                                for (int j = 0; j < NA; ++j)
+                                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c][j], acc[j], 0, 0, 0);
+                        }
+                    // D: lane holds ci = ct + 4 lk + v at position (n0 + j) * 16 + lr
+#pragma unroll
+                    for (int j = 0; j < NA; ++j) {
+                        const int n = (n0 + j) * 16 + lr;
+                        if (n < npos) {
+                            const int i = n / P.nX, jx = n - i * P.nX;
+                            float* q = dst + (long)(ct + 4 * lk) * HiWi + (P.Y0 + a.s * i) * a.Wi + P.X0 + a.s * jx;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                float* qq = q + (long)v * HiWi;
+                                *qq = a.acc ? *qq + acc[j][v] : acc[j][v];
+                            }
+                        }
+                    }
+                };
+                int n0 = 0;
+                for (; n0 + NT <= ntile; n0 += NT) group(n0, std::integral_constant<int, NT>{});
+                const int rem = ntile - n0;
+                if (NT > 3 && rem == 3) group(n0, std::integral_constant<int, (NT > 3 ? 3 : 1)>{});
+                if (NT > 2 && rem == 2) group(n0, std::integral_constant<int, (NT > 2 ? 2 : 1)>{});
+                if (rem == 1) group(n0, std::integral_constant<int, 1>{});
+            }
+        }
+        wave_lds_sync();   // every lane is done with this row before the next one is staged
+    }
+}
+
+struct ConvRowsArgs {
+    const float* G; float* C; const float* bias; const float* Wf; long M; int acc;
+    int Ci, Hi, Wi, Co, Ho, Wo, k, s, p;
+    int Hp, Wq, RP, K, KW;      // padded row Ci x Hp x Wq; K = k k Ci; KW = LDS weight row stride
+};
+
+template <int NT, int MT, int C4, int PF>   // C4 = Ci / 4; rows of at most 256 PF floats
+__global__ __launch_bounds__(RT) void k_conv_rows(ConvRowsArgs a) {
+    extern __shared__ float sm[];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+    float* s_W = sm;                              // [Co][KW]
+    float* s_row = sm + (long)a.Co * a.KW + wave * a.RP;
+    for (int i = t; i < a.Co * a.K; i += RT) {
+        const int co = i / a.K;
+        s_W[co * a.KW + (i - co * a.K)] = a.Wf[i];
+    }
+    for (int i = lane; i < a.RP; i += 64) s_row[i] = 0.f;
+    __syncthreads();
+    const int HoWo = a.Ho * a.Wo, HpWq = a.Hp * a.Wq, HiWi = a.Hi * a.Wi;
+    const int rowG = a.Ci * HiWi;
+    const long ldC = (long)a.Co * HoWo;
+    const int ntile = (HoWo + 15) >> 4;
+    const Div dHiWi(HiWi), dWi(a.Wi);
+    const bool dense = a.p == 0 && a.Hp == a.Hi && a.Wq == a.Wi;   // padded layout == row layout
+    const long stride = (long)gridDim.x * 4;
+    long r = (long)blockIdx.x * 4 + wave;
+    RowFetch<PF> pf;
+    pf.fetch(a.G, r, rowG, r < a.M, lane);
+    for (; r < a.M; r += stride) {
+        if (dense)
+            pf.stash_dense(s_row, rowG, lane);
+        else
+            pf.stash(s_row, rowG, lane, dHiWi, dWi, HiWi, a.Wi, HpWq, a.Wq, a.p, a.p);
+        wave_lds_sync();
+        pf.fetch(a.G, r + stride, rowG, r + stride < a.M, lane);
+        float* dst = a.C + r * ldC;
+        for (int ct = 0; ct < a.Co; ct += 16 * MT) {
+            for (int n0 = 0; n0 < ntile; n0 += NT) {
+                int pb[NT];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    int n = (n0 + j) * 16 + lr;
+                    n = n < HoWo ? n : HoWo - 1;
+                    const int y = n / a.Wo, x = n - y * a.Wo;
+                    pb[j] = a.s * y * a.Wq + a.s * x;
+                }
+                f4 acc[MT][NT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) acc[m][j] = f4{0.f, 0.f, 0.f, 0.f};
+                const float* wrow[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    int co = ct + m * 16 + lr;
+                    co = co < a.Co ? co : a.Co - 1;
+                    wrow[m] = s_W + (long)co * a.KW + lk;   // + 4 ks (K ordered (ky, kx, ci))
+                }
+                // per tap, the C4 groups of 4 input channels are unrolled so that all of the
+                // tap's LDS reads are in flight before its MFMAs
+                const float* rl = s_row + lk * HpWq;
+                for (int ky = 0; ky < a.k; ++ky)
+                    for (int kx = 0; kx < a.k; ++kx) {
+                        const int kb = (ky * a.k + kx) * a.Ci;
+                        const float* rt = rl + ky * a.Wq + kx;
+                        float av[C4][MT], bv[C4][NT];
+#pragma unroll
+                        for (int c = 0; c < C4; ++c) {
+#pragma unroll
+                            for (int m = 0; m < MT; ++m) av[c][m] = wrow[m][kb + 4 * c];
+#pragma unroll
+                            for (int j = 0; j < NT; ++j) bv[c][j] = rt[4 * c * HpWq + pb[j]];
+                        }
+#pragma unroll
+                        for (int c = 0; c < C4; ++c)
+#pragma unroll
+                            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                                for (int j = 0; j < NT; ++j)
+                                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][m], bv[c][j], acc[m][j], 0, 0, 0);
+                    }
+                // D: lane holds co = ct + 16 m + 4 lk + v at position (n0 + j) * 16 + lr
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int co = ct + m * 16 + 4 * lk + v;
+                        if (co >= a.Co) continue;
+                        const float b = a.bias[co];
+#pragma unroll
+                        for (int j = 0; j < NT; ++j) {
+                            const int n = (n0 + j) * 16 + lr;
+                            if (n < HoWo) {
+                                float* q = dst + (long)co * HoWo + n;
+                                const float val = acc[m][j][v] + b;
+                                *q = a.acc ? *q + val : val;
+                            }
+                        }
+                    }
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+int row_grid(long M) {
+    const long nb = (M + 3) / 4;
+    return (int)(nb < 2048 ? nb : 2048);
+}
+
+}  // namespace
+
+bool launch_conv_backsub_rows(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
+                              hipStream_t st) {
+    static const bool off = getenv("MNB_NO_ROW_CONV") != nullptr;
+    if (off || g.Ci % 16 != 0 || (g.Co != 16 && g.Co != 32 && g.Co != 64) || g.n_phase > 4) return false;
+    const int rowA = g.Co * g.Ho * g.Wo;
+    if (rowA % 4 != 0 || rowA > 4096 || ((uintptr_t)A & 15) != 0) return false;
+    ConvTRowsArgs a{};
+    a.A = A; a.C = C; a.M = M; a.acc = accumulate;
+    a.Ci = g.Ci; a.Hi = g.Hi; a.Wi = g.Wi; a.Co = g.Co; a.Ho = g.Ho; a.Wo = g.Wo; a.s = g.s;
+    int hy = 0, hx = 0, ey = g.Ho, ex = g.Wo, woff = 0, maxtile = 0;
+    a.n_phase = 0;
+    for (int f = 0; f < g.n_phase; ++f) {
+        const ConvPhase& ph = g.ph[f];
+        if (ph.nY <= 0 || ph.nX <= 0) continue;
+        RowPh& q = a.ph[a.n_phase];
+        q.Y0 = ph.Y0; q.X0 = ph.X0; q.nY = ph.nY; q.nX = ph.nX; q.Ty = ph.Ty; q.Tx = ph.Tx;
+        q.q0y = ph.q0y; q.q0x = ph.q0x; q.woff = woff;
+        a.Wsrc[a.n_phase] = ph.Wp;
+        a.n_phase++;
+        if (ph.Ty <= 0 || ph.Tx <= 0) continue;
+        woff += ph.Ty * ph.Tx * g.Co * g.Ci;
+        hy = std::max(hy, ph.Ty - 1 - ph.q0y);
+        hx = std::max(hx, ph.Tx - 1 - ph.q0x);
+        ey = std::max(ey, ph.q0y + ph.nY);
+        ex = std::max(ex, ph.q0x + ph.nX);
+        maxtile = std::max(maxtile, (ph.nY * ph.nX + 15) / 16);
+    }
+    if (a.n_phase == 0) return false;
+    a.hy = hy; a.hx = hx; a.Hp = hy + ey; a.Wq = hx + ex;
+    // channel stride = 16 mod 32 words: the four k-groups of a wavefront's read fall on
+    // different LDS banks
+    a.CS = a.Hp * a.Wq + ((16 - (a.Hp * a.Wq) % 32) + 32) % 32;
+    a.RP = (g.Co * a.CS + 3) & ~3;
+    a.wtot = (woff + 3) & ~3;
+    const size_t lds = ((size_t)a.wtot + 4 * (size_t)a.RP) * sizeof(float);
+    if (lds > ROW_LDS_MAX) return false;
+    if (M <= 0) return true;
+    const dim3 grid(row_grid(M));
+    const int c4 = g.Co / 4;
+    const bool pf4 = g.Co * g.Ho * g.Wo <= 1024;
+    const int nt = maxtile >= 4 ? 4 : maxtile >= 2 ? 2 : 1;
+#define MNB_CT(NT_, C4_)                                                                  \
+    if (pf4) hipLaunchKernelGGL((k_convT_rows<NT_, C4_, 4>), grid, dim3(RT), lds, st, a);  \
+    else hipLaunchKernelGGL((k_convT_rows<NT_, C4_, 16>), grid, dim3(RT), lds, st, a)
+#define MNB_CT_NT(C4_)          \
+    if (nt == 4) MNB_CT(4, C4_); \
+    else if (nt == 2) MNB_CT(2, C4_); \
+    else MNB_CT(1, C4_)
+    if (c4 == 4) { MNB_CT_NT(4); }
+    else if (c4 == 8) { MNB_CT_NT(8); }
+    else { MNB_CT_NT(16); }
+#undef MNB_CT_NT
+#undef MNB_CT
+    MNB_HIP(hipGetLastError());
+    return true;
+}
+
+bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
+                              hipStream_t st) {
+    static const bool off = getenv("MNB_NO_ROW_CONV") != nullptr;
+    if (off || g.Co % 16 != 0 || (g.Ci != 16 && g.Ci != 32 && g.Ci != 64)) return false;
+    const int rowG = g.Ci * g.Hi * g.Wi;
+    if (rowG % 4 != 0 || rowG > 4096 || ((uintptr_t)G & 15) != 0) return false;
+    ConvRowsArgs a{};
+    a.G = G; a.C = C; a.bias = g.b; a.Wf = g.Wf; a.M = M; a.acc = accumulate;
+    a.Ci = g.Ci; a.Hi = g.Hi; a.Wi = g.Wi; a.Co = g.Co; a.Ho = g.Ho; a.Wo = g.Wo;
+    a.k = g.k; a.s = g.s; a.p = g.p;
+    a.Hp = std::max(g.Hi + 2 * g.p, (g.Ho - 1) * g.s + g.k);
+    a.Wq = std::max(g.Wi + 2 * g.p, (g.Wo - 1) * g.s + g.k);
+    a.RP = (g.Ci * a.Hp * a.Wq + 3) & ~3;
+    a.K = g.k * g.k * g.Ci;
+    a.KW = a.K + 4;
+    const size_t lds = ((size_t)g.Co * a.KW + 4 * (size_t)a.RP) * sizeof(float);
+    if (lds > ROW_LDS_MAX) return false;
+    if (M <= 0) return true;
+    const dim3 grid(row_grid(M));
+    const int ntile = (g.Ho * g.Wo + 15) / 16;
+    const int nt = ntile >= 4 ? 4 : ntile >= 2 ? 2 : 1;
+    const int mt = g.Co % 32 == 0 ? 2 : 1;
+    const int c4 = g.Ci / 4;
+    const bool pf4 = g.Ci * g.Hi * g.Wi <= 1024;
+#define MNB_CF(NT_, MT_, C4_)                                                                  \
+    if (pf4) hipLaunchKernelGGL((k_conv_rows<NT_, MT_, C4_, 4>), grid, dim3(RT), lds, st, a);   \
+    else hipLaunchKernelGGL((k_conv_rows<NT_, MT_, C4_, 16>), grid, dim3(RT), lds, st, a)
+#define MNB_CF_NT(MT_, C4_)             \
+    if (nt == 4) MNB_CF(4, MT_, C4_);    \
+    else if (nt == 2) MNB_CF(2, MT_, C4_); \
+    else MNB_CF(1, MT_, C4_)
+#define MNB_CF_MT(C4_)                  \
+    if (mt == 2) { MNB_CF_NT(2, C4_); }  \
+    else { MNB_CF_NT(1, C4_); }
+    if (c4 == 4) { MNB_CF_MT(4) }
+    else if (c4 == 8) { MNB_CF_MT(8) }
+    else { MNB_CF_MT(16) }
+#undef MNB_CF_MT
+#undef MNB_CF_NT
+#undef MNB_CF
+    MNB_HIP(hipGetLastError());
+    return true;
+}
+
+}  // namespace mnb

@@ -78,6 +78,7 @@ struct mnb_net {
     std::vector<void*> owned;
     int total_d = 0, d0 = 0, n_out = 0, last = 0, max_width = 0;
     bool bottom_ok = false;   // first layer is a small conv of the input feeding ReLU layer 0
+    bool win_ok = false;      // ReLU layer 1 is fed by a conv of ReLU layer 0 the window kernel takes
     ~mnb_net();
 };
 

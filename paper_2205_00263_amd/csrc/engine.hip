@@ -136,7 +136,7 @@ extern "C" int mnb_set_stream(void* s) {
 }
 
 extern "C" int mnb_timer_begin(int kind, int node) {
-    if (kind < MNB_T_FC_BACKSUB || kind > MNB_T_BOTTOM) {
+    if (kind < MNB_T_FC_BACKSUB || kind > MNB_T_BOTTOM_WIN) {
         t_err = "bad timer kind";
         return MNB_EINVAL;
     }
@@ -363,6 +363,12 @@ extern "C" int mnb_net_create(const mnb_layer* L, int n, mnb_net** out) {
             net->bottom_ok = a1.kind == MNB_CONV && a1.src == 0 &&
                              bottom_supported(r0.size, net->d0, a1.C * net->nodes[0].C * a1.k * a1.k);
             if (getenv("MNB_NO_FUSED_BOTTOM")) net->bottom_ok = false;
+            if (net->bottom_ok && net->relus.size() > 1) {
+                const NetNode& on = net->nodes[net->nodes[net->relus[1]].src];
+                net->win_ok = on.kind == MNB_CONV && on.src == net->relus[0] &&
+                              win_supported(a1.C, net->nodes[0].C, a1.k, a1.stride, on.k, on.C, r0.size, net->d0) &&
+                              !getenv("MNB_NO_WIN_BOTTOM");
+            }
         }
         sync();
     } catch (...) {
@@ -1044,7 +1050,43 @@ struct Evaluator {
                     ba.gsum_out = ws.get<float>("gs_out0", (size_t)n_inst * net->max_width);
                 }
             }
-            {
+            if (src1 && net->win_ok && !pb->has_mnc && !keep_ap) {
+                // window-sparse rows: one workgroup per (instance, window position)
+                const NetNode& on = net->nodes[net->nodes[net->relus[1]].src];
+                const int n_inst = (int)ch.inst.size();
+                WinArgs wa{};
+                wa.mode = ba.mode;
+                wa.rows = ch.rows; wa.inst = ch.inst_d; wa.qid = pb->qid;
+                wa.d1 = net->relu_d[0]; wa.d0 = net->d0;
+                wa.Ci = a1.geom.Ci; wa.Hi = a1.geom.Hi; wa.Wi = a1.geom.Wi;
+                wa.C1 = a1.C; wa.Ho = a1.H; wa.Wo = a1.W; wa.k = a1.k; wa.s = a1.stride; wa.p = a1.pad;
+                wa.W1 = a1.Wd; wa.b1 = a1.bd;
+                wa.oCi = on.geom.Ci; wa.oHi = on.geom.Hi; wa.oWi = on.geom.Wi;
+                wa.oCo = on.C; wa.oHo = on.H; wa.oWo = on.W; wa.ok = on.k; wa.os = on.stride; wa.op = on.pad;
+                wa.Wobj = on.Wd; wa.bobj = net->relu_bias[1];
+                wa.l = pb->l; wa.u = pb->u; wa.S = pb->S_; wa.ld_state = pb->ld_state;
+                wa.alpha = pb->alpha; wa.beta = pb->beta; wa.ld_param = pb->ld_param; wa.n_sets = pb->n_sets;
+                wa.lo = pb->lo; wa.hi = pb->hi;
+                wa.lw = ba.lw; wa.uw = ba.uw; wa.state_off_obj = ba.state_off_obj;
+                wa.lb_out = ba.lb_out;
+                wa.adjoint = adjoint;
+                wa.asplit = ws.get<float>("w_as", (size_t)n_inst * net->d0);
+                wa.scal = ws.get<float>("w_sc", (size_t)n_inst * 4);
+                const int nwin = on.H * on.W, E = a1.C * on.k * on.k;
+                const int IH = (on.k - 1) * a1.stride + a1.k;
+                if (adjoint) {
+                    wa.part_a = ws.get<float>("w_pa", (size_t)n_inst * nwin * E);
+                    wa.part_x = ws.get<float>("w_px", (size_t)n_inst * nwin * a1.geom.Ci * IH * IH);
+                    wa.part_n = ws.get<int>("w_pn", (size_t)n_inst * nwin);
+                    wa.d_alpha = ba.d_alpha; wa.d_beta = ba.d_beta; wa.ldg = ba.ldg;
+                }
+                {
+                    const double macs = (double)on.k * on.k * a1.C * a1.geom.Ci * a1.k * a1.k;
+                    TimerScope ts(MNB_T_BOTTOM_WIN, r0n, 2.0 * M * (adjoint ? 2.0 : 1.0) * macs, 0.0);
+                    launch_bottom_win(wa, n_inst, st);
+                }
+                launch_bottom_win_reduce(wa, n_inst, st);
+            } else {
                 // fixed 16-row chunks per instance (independent of the rest of the batch)
                 const int n_inst = (int)ch.inst.size();
                 if (ch.bchunk_inst.empty()) {

@@ -345,6 +345,7 @@ __global__ __launch_bounds__(256) void k_convT_valu(const float* __restrict__ A,
 void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
                          hipStream_t st) {
     if (M <= 0) return;
+    if (launch_conv_backsub_rows(g, A, C, M, accumulate, st)) return;
     if (g.Ci < 16) {
         long total = (long)M * g.Ci * g.Hi * g.Wi;
         hipLaunchKernelGGL(k_convT_valu, dim3(cdiv(total, 256)), dim3(256), 0, st, A, C, g.W, M, g.Ci,
@@ -371,6 +372,7 @@ void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, boo
 void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
                          hipStream_t st) {
     if (M <= 0) return;
+    if (launch_conv_forward_rows(g, G, C, M, accumulate, st)) return;
     ConvFwd p;
     p.A = G; p.C = C; p.W = g.Wf; p.bias = g.b; p.ktab = g.fwd_ktab;
     p.Ci = g.Ci; p.kw = g.k; p.HiWi = g.Hi * g.Wi;

@@ -33,6 +33,12 @@ void launch_fc_backsub(const float* A, const float* W, float* C, int M, int dout
 // C[M, Ci*Hi*Wi] (+)= conv-transpose of A[M, Co*Ho*Wo]
 void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
                          hipStream_t st);
+// Row-resident MFMA forms of the two convolution products, used by launch_conv_backsub /
+// launch_conv_forward when a row fits in LDS; false (nothing launched) otherwise.
+bool launch_conv_backsub_rows(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
+                              hipStream_t st);
+bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
+                              hipStream_t st);
 
 // ---- forward products (adjoint and upper-bound evaluation) ----
 // C[M, dout] = G[M, din] * W^T + b  (accumulate: C += ..., bias added either way)
