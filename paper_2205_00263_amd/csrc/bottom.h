@@ -35,6 +35,7 @@ struct BottomArgs {
     const int* cinst; const int* cr0; const int* cr1; int n_chunk;
     const int* ichunk0; const int* ichunk1;   // [n_inst] chunk range of each instance
     float* part;
+    int box_lds;     // set by launch_bottom: the query's box is staged in LDS
 };
 
 bool bottom_supported(int d1, int d0, int n_weights);

@@ -17,9 +17,10 @@
 
 namespace mnb {
 
-constexpr int BT = 256;     // threads
-constexpr int NJ_MAX = 16;  // owned neurons of ReLU layer 0 per thread (d1 <= 4096)
-constexpr int NO = 12;      // input elements per thread (d0 <= 3072)
+constexpr int BT = 512;     // threads (8 wavefronts)
+constexpr int NWV = BT / 64;
+constexpr int NJ_MAX = 8;   // owned neurons of ReLU layer 0 per thread (d1 <= 4096)
+constexpr int NO = 6;       // input elements per thread (d0 <= 3072)
 
 // Exact n / d for 0 <= n < 2^22 and 0 < d via a float reciprocal and one correction.
 struct FastDiv {
@@ -34,8 +35,17 @@ struct FastDiv {
     }
 };
 
-// Sum of three per-thread values over the block (fixed order); two barriers.
-__device__ __forceinline__ void block_sum3(float& x, float& y, float& z, float (*red)[4]) {
+// Workgroup barrier that orders LDS accesses only: outstanding global loads (the next
+// row's prefetch) stay in flight across it.  No global data written in the row loop is
+// read back by another thread of the workgroup.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Sum of three per-thread values over the block (fixed order); one barrier.
+__device__ __forceinline__ void block_sum3(float& x, float& y, float& z, float (*red)[NWV]) {
     x = wave_sum(x);
     y = wave_sum(y);
     z = wave_sum(z);
@@ -45,10 +55,10 @@ __device__ __forceinline__ void block_sum3(float& x, float& y, float& z, float (
         red[1][w] = y;
         red[2][w] = z;
     }
-    __syncthreads();
-    x = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-    y = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-    z = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+    lds_barrier();
+    x = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) + ((red[0][4] + red[0][5]) + (red[0][6] + red[0][7]));
+    y = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) + ((red[1][4] + red[1][5]) + (red[1][6] + red[1][7]));
+    z = ((red[2][0] + red[2][1]) + (red[2][2] + red[2][3])) + ((red[2][4] + red[2][5]) + (red[2][6] + red[2][7]));
 }
 
 // KS: kernel size and stride of the first convolution as compile-time constants
@@ -59,20 +69,23 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // Ci*k*k <= 32): the transposed one as T = ahat^T W (positions x taps) plus a col2im
 // gather, the adjoint one as im2col(x*) W^T (positions x output channels).
 template <int NJ, int KK, int SS, int CO, bool MF>
-__global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
+__global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) {
     extern __shared__ float smem[];
     const int d1 = a.d1;
     const int k = KK ? KK : a.k;
     const int s = SS ? SS : a.s;
     float* s_ah = smem;                 // [d1]  ahat of the current row, then ghat
-    float* s_dp = s_ah + d1;            // [d1]  slope where a' >= 0
-    float* s_dn = s_dp + d1;            // [d1]  slope where a' < 0
-    float* s_bn = s_dn + d1;            // [d1]  intercept where a' < 0 (> 0 exactly when unstable)
-    float* s_ad = s_bn + d1;            // [d1]  S beta + (Phat^T gamma)
-    float* s_x = s_ad + d1;             // [d0]  x* of the current row
-    float* s_w = s_x + a.d0;            // [Co*Ci*k*k] first-layer weights
-    float* s_T = s_w + a.Co * a.Ci * a.k * a.k;   // [Ho*Wo][32] tap products (MF only)
-    __shared__ float red[3][4];
+    float* s_x = s_ah + d1;             // [d0]  x* of the current row
+    float* s_b1 = s_x + a.d0;           // [Co]  first-layer bias per channel
+    float* s_w = s_b1 + ((a.Co + 3) & ~3);          // [Co*Ci*k*k] first-layer weights
+    float* s_wp = s_w + ((a.Co * a.Ci * a.k * a.k + 3) & ~3);  // [16][32] weights, taps zero-padded (MF only)
+    float* s_T = s_wp + (MF ? 16 * 32 : 0);                     // [Ho*Wo][TS] tap products (MF only)
+    const int TS = a.Ci * a.k * a.k > 16 ? 32 : 16;
+    float* s_sh = s_T + (MF ? a.Ho * a.Wo * TS : 0);   // [d1] sum over rows of ghat (own j)
+    float* s_sg = s_sh + d1;                           // [d1] sum over rows of g (own j, MNC only)
+    float* s_lo = s_sg + d1;                           // [d0] input box of the query (box_lds)
+    float* s_hi = s_lo + a.d0;                         // [d0]
+    __shared__ float red[3][NWV];
 
     const int ib = a.cinst[blockIdx.x];
     const InstDesc in = a.inst[ib];
@@ -81,63 +94,85 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
     const int nw = a.Co * a.Ci * kk;
     const int HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
     for (int i = t; i < nw; i += BT) s_w[i] = a.W1[i];
-    // relaxation of ReLU layer 0 for this instance (split first, then stable, then unstable)
-    for (int j = t; j < d1; j += BT) {
-        const long so = (long)in.slot * a.ld_state + j;
-        const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + j;
-        const float l = a.l[so], u = a.u[so];
-        const int sj = (int)a.S[so];
-        float dp = 0.f, dn = 0.f, bn = 0.f;
-        if (sj == -1) {
-            dp = dn = 1.f;
-        } else if (sj == 1) {
-        } else if (l >= 0.f) {
-            dp = dn = 1.f;
-        } else if (u <= 0.f) {
-        } else {
-            dp = a.alpha[po];
-            const float w = u - l;
-            dn = u / w;
-            bn = -(u * l) / w;
+    if constexpr (MF)
+        for (int i = t; i < 16 * 32; i += BT) {
+            const int co = i >> 5, tap = i & 31;
+            s_wp[i] = tap < a.Ci * kk ? a.W1[co * a.Ci * kk + tap] : 0.f;
         }
-        s_dp[j] = dp;
-        s_dn[j] = dn;
-        s_bn[j] = bn;
-        s_ad[j] = (sj != 0 ? (float)sj * a.beta[po] : 0.f) + (a.vhat ? a.vhat[(long)ib * d1 + j] : 0.f);
+    for (int i = t; i < a.Co; i += BT) s_b1[i] = a.b1[i];
+    const float* glo = a.lo + (long)a.qid[in.slot] * a.d0;
+    const float* ghi = a.hi + (long)a.qid[in.slot] * a.d0;
+    if (a.box_lds)
+        for (int o = t; o < a.d0; o += BT) {
+            s_lo[o] = glo[o];
+            s_hi[o] = ghi[o];
+        }
+    // relaxation of ReLU layer 0 for this instance (split first, then stable, then unstable),
+    // held by the thread that owns each neuron: slope where a' >= 0, slope and intercept where
+    // a' < 0 (the intercept is > 0 exactly when unstable), S beta + (Phat^T gamma)
+    float rx_dp[NJ], rx_dn[NJ], rx_bn[NJ], rx_ad[NJ];
+    unsigned split_bits = 0;   // bit i: neuron t + i BT is split
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        const int j = t + i * BT;
+        float dp = 0.f, dn = 0.f, bn = 0.f, ad = 0.f;
+        if (j < d1) {
+            s_sh[j] = 0.f;
+            s_sg[j] = 0.f;
+            const long so = (long)in.slot * a.ld_state + j;
+            const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + j;
+            const float l = a.l[so], u = a.u[so];
+            const int sj = (int)a.S[so];
+            if (sj == -1) {
+                dp = dn = 1.f;
+            } else if (sj == 1) {
+            } else if (l >= 0.f) {
+                dp = dn = 1.f;
+            } else if (u <= 0.f) {
+            } else {
+                dp = a.alpha[po];
+                const float w = u - l;
+                dn = u / w;
+                bn = -(u * l) / w;
+            }
+            ad = (sj != 0 ? (float)sj * a.beta[po] : 0.f) + (a.vhat ? a.vhat[(long)ib * d1 + j] : 0.f);
+            if (sj != 0) split_bits |= 1u << i;
+        }
+        rx_dp[i] = dp;
+        rx_dn[i] = dn;
+        rx_bn[i] = bn;
+        rx_ad[i] = ad;
     }
     // forward convolution: per owned neuron its window origin and weight row
     const FastDiv div_HoWo(HoWo), div_Wo(a.Wo), div_HiWi(HiWi), div_Wi(a.Wi);
     const float* vrow = a.v ? a.v + (long)ib * d1 : nullptr;
-    float da[NJ], sh[NJ], sg[NJ];
+    float da[NJ];
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) da[i] = sh[i] = sg[i] = 0.f;
+    for (int i = 0; i < NJ; ++i) da[i] = 0.f;
+    const bool want_h = a.gsum_hat != nullptr;
     const float gpv = a.gp ? a.gp[ib] : 0.f;
     const int q = a.qid[in.slot];
-    const float* lo = a.lo + (long)q * a.d0;
-    const float* hi = a.hi + (long)q * a.d0;
+
     __syncthreads();
     const int lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
     const int ntap = a.Ci * kk;                  // taps (ci, ky, kx) of one output channel
     const int MT = (HoWo + 15) >> 4;             // 16-row tiles over the positions of ReLU layer 0
-    float bT[2][4], bF[8];
-    if constexpr (MF) {
-        // transposed: B[k = co][n = tap]; adjoint: B[k = tap][n = co]
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int co = ks * 4 + lk, n = nt * 16 + lr;
-                bT[nt][ks] = n < ntap ? s_w[co * ntap + n] : 0.f;
-            }
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            const int kq = ks * 4 + lk;
-            bF[ks] = kq < ntap ? s_w[lr * ntap + kq] : 0.f;
-        }
-    }
+    // MFMA B operands are read from s_wp per tile: transposed B[k = co][n = tap],
+    // adjoint B[k = tap][n = co]
 
     for (int r = a.cr0[blockIdx.x]; r < a.cr1[blockIdx.x]; ++r) {
         const RowDesc rd = a.rows[r];
+        // previous bound of the row (thread 0): each (slot, neuron) of the objective layer has
+        // exactly one row in a pass
+        float old = 0.f;
+        if (t == 0) {
+            if (a.mode == 0) {
+                const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
+                old = rd.sign > 0 ? a.lw[e] : a.uw[e];
+            } else if (a.mode == 1) {
+                old = a.best[r];
+            }
+        }
         // ---- row coefficients on the output of ReLU layer 0 (each thread its own j)
         float crow = 0.f;
         float ap[NJ];
@@ -186,21 +221,21 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                 const float p = ap[i] + (vrow ? vrow[j] : 0.f);
                 ap[i] = p;
                 const bool neg = p < 0.f;
-                const float ah = p * (neg ? s_dn[j] : s_dp[j]) + s_ad[j];
+                const float ah = p * (neg ? rx_dn[i] : rx_dp[i]) + rx_ad[i];
                 s_ah[j] = ah;
-                cpt += (neg ? p * s_bn[j] : 0.f) + ah * a.bias1[j];
+                cpt += (neg ? p * rx_bn[i] : 0.f) + ah * s_b1[div_HoWo.div(j)];
                 if (a.Ap_out) a.Ap_out[(long)r * d1 + j] = p;
             }
         }
         if (t == 0) cpt += crow - gpv;
-        __syncthreads();
+        lds_barrier();
         // ---- transposed first convolution and concretisation
         float lbp = 0.f, mag = 0.f;
         const int wst = a.Ci * kk;
         if constexpr (MF) {
             // T[pos][tap] = sum_co ahat[co][pos] W[co][tap]
             const int NTT = ntap > 16 ? 2 : 1;
-            for (int mt = wave; mt < MT; mt += 4) {
+            for (int mt = wave; mt < MT; mt += NWV) {
                 const int pos = mt * 16 + lr;
                 float av[4];
 #pragma unroll
@@ -208,15 +243,16 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                 for (int nt = 0; nt < NTT; ++nt) {
                     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], bT[nt][ks], acc, 0, 0, 0);
+                    for (int ks = 0; ks < 4; ++ks)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], s_wp[(ks * 4 + lk) * 32 + nt * 16 + lr], acc, 0, 0, 0);
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int p2 = mt * 16 + 4 * lk + v;
-                        if (p2 < HoWo) s_T[p2 * 32 + nt * 16 + lr] = acc[v];
+                        if (p2 < HoWo) s_T[p2 * TS + nt * 16 + lr] = acc[v];
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
         for (int o = t; o < a.d0; o += BT) {
             const int ci = div_HiWi.div(o);
@@ -237,7 +273,7 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                     const int x = (Xp - kx) / s;
                     if (kx >= k || x < 0 || x >= a.Wo) continue;
                     if constexpr (MF) {
-                        acc += s_T[(y * a.Wo + x) * 32 + (ci * k + ky) * k + kx];
+                        acc += s_T[(y * a.Wo + x) * TS + (ci * k + ky) * k + kx];
                         continue;
                     }
                     const float* ah = s_ah + y * a.Wo + x;
@@ -252,7 +288,14 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                     }
                 }
             }
-            const float l = lo[o], h = hi[o];
+            float l, h;
+            if (a.box_lds) {
+                l = s_lo[o];
+                h = s_hi[o];
+            } else {
+                l = glo[o];
+                h = ghi[o];
+            }
             lbp += fminf(acc * l, acc * h);
             mag += fabsf(acc) * fmaxf(fabsf(l), fabsf(h));
             const bool neg = acc < 0.f;
@@ -264,15 +307,16 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
             float lb = (lbp + cpt) - (mag + fabsf(cpt)) * 9.5367431640625e-07f;   // 2^-20 rounding margin
             if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
             if (a.mode == 0) {
+                // each (slot, neuron) of the objective layer has exactly one row in a pass
                 const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
                 if (rd.sign > 0)
-                    a.lw[e] = fmaxf(a.lw[e], lb);
+                    a.lw[e] = fmaxf(old, lb);
                 else
-                    a.uw[e] = fminf(a.uw[e], isinf(lb) ? INFINITY : -lb);
+                    a.uw[e] = fminf(old, isinf(lb) ? INFINITY : -lb);
             } else {
                 a.lb_out[r] = lb;
                 if (a.mode == 1) {
-                    const bool better = lb > a.best[r];
+                    const bool better = lb > old;
                     if (better) a.best[r] = lb;
                     a.improved[r] = better ? 1 : 0;
                 }
@@ -282,7 +326,7 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
             // ---- adjoint: first convolution of x* into s_ah (ahat is no longer read) ...
             if constexpr (MF) {
                 const int KS = (ntap + 3) >> 2;
-                for (int mt = wave; mt < MT; mt += 4) {
+                for (int mt = wave; mt < MT; mt += NWV) {
                     const int pos = mt * 16 + lr;
                     const int y = div_Wo.div(pos), x = pos - y * a.Wo;
                     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -298,7 +342,7 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                             if ((unsigned)Y < (unsigned)a.Hi && (unsigned)X < (unsigned)a.Wi)
                                 av = s_x[(ci * a.Hi + Y) * a.Wi + X];
                         }
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bF[ks], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, s_wp[lr * 32 + ks * 4 + lk], acc, 0, 0, 0);
                     }
                     const float bco = a.b1[lr];
 #pragma unroll
@@ -307,7 +351,7 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                         if (p2 < HoWo) s_ah[lr * HoWo + p2] = acc[v] + bco;
                     }
                 }
-                __syncthreads();
+                lds_barrier();
             } else
             for (int j = t; j < d1; j += BT) {
                 const int co = div_HoWo.div(j);
@@ -352,16 +396,16 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
                 if (j < d1) {
                     const float gh = s_ah[j];
                     const bool neg = ap[i] < 0.f;
-                    const float bn = s_bn[j];
-                    const float g = (neg ? s_dn[j] : s_dp[j]) * gh + (neg ? bn : 0.f);
+                    const float bn = rx_bn[i];
+                    const float g = (neg ? rx_dn[i] : rx_dp[i]) * gh + (neg ? bn : 0.f);
                     if (bn > 0.f && !neg) da[i] += ap[i] * gh;
-                    sh[i] += gh;
-                    sg[i] += g;
+                    if (want_h || ((split_bits >> i) & 1u)) s_sh[j] += gh;
+                    if (a.gsum_out) s_sg[j] += g;
                     if (a.Gout) a.Gout[(long)r * d1 + j] = g;
                 }
             }
         }
-        __syncthreads();   // red[] and s_x are rewritten by the next row
+        lds_barrier();   // red[] and s_x are rewritten by the next row
     }
     if (!a.adjoint) return;
     // partial sums of this chunk: alpha only where the neuron is unstable, the ghat sum only
@@ -372,9 +416,9 @@ __global__ __launch_bounds__(BT) void k_bottom(BottomArgs a) {
     for (int i = 0; i < NJ; ++i) {
         const int j = t + i * BT;
         if (j < d1) {
-            if (s_bn[j] > 0.f) pt[j] = da[i];
-            if (a.gsum_hat || a.S[(long)in.slot * a.ld_state + j] != 0) pt[d1 + j] = sh[i];
-            if (a.gsum_out) pt[2 * d1 + j] = sg[i];
+            if (rx_bn[i] > 0.f) pt[j] = da[i];
+            if (want_h || ((split_bits >> i) & 1u)) pt[d1 + j] = s_sh[j];
+            if (a.gsum_out) pt[2 * d1 + j] = s_sg[j];
         }
     }
 }
@@ -407,44 +451,49 @@ __global__ void k_bottom_reduce(BottomArgs a) {
 
 bool bottom_supported(int d1, int d0, int n_weights) {
     return d1 <= NJ_MAX * BT && d0 <= NO * BT && n_weights <= 4096 &&
-           (5 * d1 + d0 + n_weights) * sizeof(float) <= 150 * 1024;
+           (3 * d1 + d0 + n_weights + 64) * sizeof(float) <= 150 * 1024;
 }
 
 template <int KK, int SS, int CO, bool MF>
 static void launch_bottom_k(const BottomArgs& a, int n_blk, size_t lds, hipStream_t st) {
     const int nj = cdiv(a.d1, BT);
-    if (nj <= 4)
+    if (nj <= 2)
+        hipLaunchKernelGGL((k_bottom<2, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
+    else if (nj <= 4)
         hipLaunchKernelGGL((k_bottom<4, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
-    else if (nj <= 8)
-        hipLaunchKernelGGL((k_bottom<8, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
-    else if (nj <= 12)
-        hipLaunchKernelGGL((k_bottom<12, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
+    else if (nj <= 6)
+        hipLaunchKernelGGL((k_bottom<6, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
     else
-        hipLaunchKernelGGL((k_bottom<16, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<8, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
 }
 
 void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
     if (n_inst <= 0) return;
     MNB_CHECK(bottom_supported(a.d1, a.d0, a.Co * a.Ci * a.k * a.k) && a.k <= 3 * a.s && (a.s >= 2 || a.k <= 3),
               MNB_EDEVICE, "bottom kernel: unsupported shape");
-    const size_t base = (size_t)(5 * a.d1 + a.d0 + a.Co * a.Ci * a.k * a.k);
+    const size_t base = (size_t)(3 * a.d1 + a.d0 + ((a.Co + 3) & ~3) + ((a.Co * a.Ci * a.k * a.k + 3) & ~3));
+    const size_t ts = a.Ci * a.k * a.k > 16 ? 32 : 16;
     const int nb = a.n_chunk;
     if (nb <= 0) return;
     const bool mf = a.Co == 16 && a.Ci * a.k * a.k <= 32 &&
-                    (base + (size_t)a.Ho * a.Wo * 32) * sizeof(float) <= 150 * 1024 && !getenv("MNB_BOTTOM_VALU");
-    const size_t lds = (base + (mf ? (size_t)a.Ho * a.Wo * 32 : 0)) * sizeof(float);
+                    (base + (size_t)a.Ho * a.Wo * ts + 16 * 32) * sizeof(float) <= 150 * 1024 && !getenv("MNB_BOTTOM_VALU");
+    size_t lds = (base + (mf ? (size_t)a.Ho * a.Wo * ts + 16 * 32 : 0)) * sizeof(float);
+    // the query's box in LDS when it fits beside the rest
+    BottomArgs b = a;
+    b.box_lds = lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
+    if (b.box_lds) lds += 2 * (size_t)a.d0 * sizeof(float);
     if (mf && a.k == 4 && a.s == 2)
-        launch_bottom_k<4, 2, 16, true>(a, nb, lds, st);
+        launch_bottom_k<4, 2, 16, true>(b, nb, lds, st);
     else if (mf && a.k == 3 && a.s == 2)
-        launch_bottom_k<3, 2, 16, true>(a, nb, lds, st);
+        launch_bottom_k<3, 2, 16, true>(b, nb, lds, st);
     else if (mf)
-        launch_bottom_k<0, 0, 16, true>(a, nb, lds, st);
+        launch_bottom_k<0, 0, 16, true>(b, nb, lds, st);
     else if (a.k == 4 && a.s == 2 && a.Co == 16)
-        launch_bottom_k<4, 2, 16, false>(a, nb, lds, st);
+        launch_bottom_k<4, 2, 16, false>(b, nb, lds, st);
     else if (a.k == 3 && a.s == 2 && a.Co == 16)
-        launch_bottom_k<3, 2, 16, false>(a, nb, lds, st);
+        launch_bottom_k<3, 2, 16, false>(b, nb, lds, st);
     else
-        launch_bottom_k<0, 0, 0, false>(a, nb, lds, st);
+        launch_bottom_k<0, 0, 0, false>(b, nb, lds, st);
     MNB_HIP(hipGetLastError());
 }
 
