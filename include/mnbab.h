@@ -203,7 +203,8 @@ int mnb_sync(void);
  * and concretise the bytes they must move (coefficient rows read/written);
  * MNB_T_BOTTOM (fused first-layer fold + transposed convolution +
  * concretisation + adjoint convolution) 4 * rows * (multiply-adds of the first
- * convolution) flops and 4 * rows * d1 bytes; MNB_T_BOTTOM_WIN (its
+ * convolution) flops and, per row, 4 d1 bytes for each coefficient row read or
+ * gradient / a' row written plus d0 x* bytes; MNB_T_BOTTOM_WIN (its
  * window-sparse form for rows whose objective is ReLU layer 1) 2 * rows *
  * (window positions x first-layer channels x taps) flops, doubled with the
  * adjoint. */

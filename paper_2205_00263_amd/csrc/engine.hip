@@ -1121,8 +1121,12 @@ struct Evaluator {
                 ba.n_chunk = nc;
                 if (adjoint) ba.part = ws.get<float>("bpart", (size_t)nc * 3 * net->relu_d[0]);
                 {
+                    // algorithmic bytes: coefficient rows read (unless built from the filter),
+                    // gradient rows and a' rows written, x* bits written
+                    const double rowb = (double)M * net->relu_d[0] * 4.0;
                     TimerScope ts(MNB_T_BOTTOM, r0n, 2.0 * M * (adjoint ? 2.0 : 1.0) * a1.macs_per_row,
-                                  (double)M * net->relu_d[0] * 4.0 * (src1 ? 0.0 : 1.0) + (double)M * net->d0);
+                                  rowb * ((src1 ? 0.0 : 1.0) + (ba.Gout ? 1.0 : 0.0) + (ba.Ap_out ? 1.0 : 0.0)) +
+                                      (ba.xbits ? (double)M * net->d0 : 0.0));
                     launch_bottom(ba, n_inst, st);
                 }
                 launch_bottom_reduce(ba, n_inst, st);
