@@ -79,7 +79,7 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
     float* s_b1 = s_x + a.d0;           // [Co]  first-layer bias per channel
     float* s_w = s_b1 + ((a.Co + 3) & ~3);          // [Co*Ci*k*k] first-layer weights
     float* s_wp = s_w + ((a.Co * a.Ci * a.k * a.k + 3) & ~3);  // [16][32] weights, taps zero-padded (MF only)
-    float* s_T = s_wp + (MF ? 16 * 32 : 0);                     // [Ho*Wo][TS] tap products (MF only)
+    float* s_T = s_wp + (MF ? 16 * 32 : 0);                     // [TS][Ho*Wo] tap products, tap-major (MF only)
     const int TS = a.Ci * a.k * a.k > 16 ? 32 : 16;
     float* s_sh = s_T + (MF ? a.Ho * a.Wo * TS : 0);   // [d1] sum over rows of ghat (own j)
     float* s_sg = s_sh + d1;                           // [d1] sum over rows of g (own j, MNC only)
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int p2 = mt * 16 + 4 * lk + v;
-                        if (p2 < HoWo) s_T[p2 * TS + nt * 16 + lr] = acc[v];
+                        if (p2 < HoWo) s_T[(nt * 16 + lr) * HoWo + p2] = acc[v];   // tap-major
                     }
                 }
             }
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
                     const int x = (Xp - kx) / s;
                     if (kx >= k || x < 0 || x >= a.Wo) continue;
                     if constexpr (MF) {
-                        acc += s_T[(y * a.Wo + x) * TS + (ci * k + ky) * k + kx];
+                        acc += s_T[((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x];
                         continue;
                     }
                     const float* ah = s_ah + y * a.Wo + x;
