@@ -1200,6 +1200,7 @@ struct Evaluator {
         aa.g_alpha = g_alpha; aa.g_beta = g_beta; aa.ldg = pb->ld_param;
         const int obj = ch.obj_layer < 0 ? pb->R : ch.obj_layer;
         aa.n_ab = obj < pb->R ? net->relu_off[obj] : net->total_d;
+        aa.l = pb->l; aa.u = pb->u; aa.S = pb->S_; aa.ld_state = pb->ld_state;
         aa.gamma = pb->has_mnc ? pb->gamma : nullptr;
         aa.m_gamma = m_gamma; aa.v_gamma = v_gamma; aa.g_gamma = g_gamma; aa.ld_gamma = pb->ld_gamma;
         aa.n_gamma = pb->has_mnc ? obj * pb->e_cap : 0;

@@ -277,6 +277,15 @@ __global__ __launch_bounds__(256) void k_gemm(P p) {
 template <class P>
 static void run_gemm(const P& p, hipStream_t st) {
     dim3 blk(256);
+    // tile shape only changes how outputs are grouped into workgroups, never the order in
+    // which an output element accumulates over K, so it may follow the grid size
+    const long big = (long)cdiv(p.M, 128) * cdiv(p.N, 128);
+    if (p.N > 64 && big < 512) {
+        dim3 grid(cdiv(p.M, 64), cdiv(p.N, 64));
+        hipLaunchKernelGGL((k_gemm<64, 64, 2, P>), grid, blk, 0, st, p);
+        MNB_HIP(hipGetLastError());
+        return;
+    }
     if (p.N <= 16) {
         dim3 grid(cdiv(p.M, 256), cdiv(p.N, 16));
         hipLaunchKernelGGL((k_gemm<256, 16, 4, P>), grid, blk, 0, st, p);
@@ -342,10 +351,97 @@ __global__ __launch_bounds__(256) void k_convT_valu(const float* __restrict__ A,
     *out = acc ? *out + sum : sum;
 }
 
+// Transposed convolution into very few channels (Ci <= 4, the first layer of CIFAR
+// networks): one workgroup per (row, 16x16 output tile) stages the coefficient window the
+// tile depends on, 8 output channels of the layer at a time, into LDS; each thread owns one
+// output pixel and accumulates all Ci input channels, so every coefficient is read once from
+// global memory per tile and reused for all taps and channels from LDS.
+constexpr int TCT = 16;     // output tile edge
+constexpr int TCO = 8;      // layer output channels staged per step
+template <int CI>
+__global__ __launch_bounds__(256) void k_convT_small(const float* __restrict__ A, float* __restrict__ C,
+                                                     const float* __restrict__ W, int Hi, int Wi, int Co,
+                                                     int Ho, int Wo, int k, int s, int p, int acc, int tiles_x,
+                                                     int WY, int WX) {
+    extern __shared__ float sm[];
+    float* s_w = sm;                       // [Co][CI][k][k]
+    float* s_a = sm + Co * CI * k * k;     // [TCO][WY][WX] coefficient window
+    const int t = threadIdx.x;
+    const int r = blockIdx.y;
+    const int tile = blockIdx.x, ty0 = (tile / tiles_x) * TCT, tx0 = (tile % tiles_x) * TCT;
+    const int Y = ty0 + t / TCT, X = tx0 + t % TCT;
+    // window origin on the layer output: smallest y that any pixel of the tile reaches
+    const int y0 = (ty0 + p - (k - 1)) >= 0 ? (ty0 + p - (k - 1)) / s : -((-(ty0 + p - (k - 1)) + s - 1) / s);
+    const int x0 = (tx0 + p - (k - 1)) >= 0 ? (tx0 + p - (k - 1)) / s : -((-(tx0 + p - (k - 1)) + s - 1) / s);
+    for (int i = t; i < Co * CI * k * k; i += 256) s_w[i] = W[i];
+    const float* Ar = A + (long)r * Co * Ho * Wo;
+    float out[CI];
+#pragma unroll
+    for (int c = 0; c < CI; ++c) out[c] = 0.f;
+    const int HoWo = Ho * Wo, win = WY * WX;
+    for (int c0 = 0; c0 < Co; c0 += TCO) {
+        const int nco = Co - c0 < TCO ? Co - c0 : TCO;
+        __syncthreads();   // previous window consumed (and weights visible on the first pass)
+        for (int i = t; i < nco * win; i += 256) {
+            const int co = i / win, rem = i - co * win, wy = rem / WX, wx = rem - wy * WX;
+            const int y = y0 + wy, x = x0 + wx;
+            s_a[i] = (y >= 0 && y < Ho && x >= 0 && x < Wo) ? Ar[(long)(c0 + co) * HoWo + y * Wo + x] : 0.f;
+        }
+        __syncthreads();
+        if (Y < Hi && X < Wi) {
+            const int Yp = Y + p, Xp = X + p;
+            for (int ky = Yp % s; ky < k; ky += s) {
+                const int wy = (Yp - ky) / s - y0;
+                for (int kx = Xp % s; kx < k; kx += s) {
+                    const int wx = (Xp - kx) / s - x0;
+                    const float* ap = s_a + wy * WX + wx;
+                    const float* wp = s_w + ((long)c0 * CI * k + ky) * k + kx;   // [co][ci][ky][kx]
+                    for (int co = 0; co < nco; ++co) {
+                        const float av = ap[co * win];
+#pragma unroll
+                        for (int c = 0; c < CI; ++c) out[c] += av * wp[(co * CI + c) * k * k];
+                    }
+                }
+            }
+        }
+    }
+    if (Y < Hi && X < Wi) {
+        float* Cr = C + (long)r * CI * Hi * Wi + Y * Wi + X;
+#pragma unroll
+        for (int c = 0; c < CI; ++c) {
+            float* q = Cr + (long)c * Hi * Wi;
+            *q = acc ? *q + out[c] : out[c];
+        }
+    }
+}
+
+static bool launch_convT_small(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st) {
+    if (g.Ci > 4 || g.k > 5 || g.s > 2) return false;
+    const int tiles_y = cdiv(g.Hi, TCT), tiles_x = cdiv(g.Wi, TCT);
+    // window rows: y from ceil((ty0 + p - (k-1)) / s) to (ty0 + TCT - 1 + p) / s
+    const int WY = (TCT - 1 + g.k - 1) / g.s + 2, WX = WY;
+    const size_t lds = ((size_t)g.Co * g.Ci * g.k * g.k + (size_t)TCO * WY * WX) * sizeof(float);
+    if (lds > 64 * 1024 || M > 65535) return false;
+    const dim3 grid(tiles_y * tiles_x, M);
+    switch (g.Ci) {
+        case 1: hipLaunchKernelGGL(k_convT_small<1>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
+                                   g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+        case 2: hipLaunchKernelGGL(k_convT_small<2>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
+                                   g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+        case 3: hipLaunchKernelGGL(k_convT_small<3>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
+                                   g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+        default: hipLaunchKernelGGL(k_convT_small<4>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
+                                    g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+    }
+    MNB_HIP(hipGetLastError());
+    return true;
+}
+
 void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
                          hipStream_t st) {
     if (M <= 0) return;
     if (launch_conv_backsub_rows(g, A, C, M, accumulate, st)) return;
+    if (launch_convT_small(g, A, C, M, accumulate, st)) return;
     if (g.Ci < 16) {
         long total = (long)M * g.Ci * g.Hi * g.Wi;
         hipLaunchKernelGGL(k_convT_valu, dim3(cdiv(total, 256)), dim3(256), 0, st, A, C, g.W, M, g.Ci,

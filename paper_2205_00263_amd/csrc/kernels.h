@@ -120,6 +120,8 @@ struct AdamArgs {
     float* m_alpha; float* v_alpha; float* m_beta; float* v_beta;   // [nb, n_sets, ld_param]
     const float* g_alpha; const float* g_beta; long ldg;            // [n_inst, ldg]
     int n_ab;              // alpha/beta entries of the set (prefix of the layer space)
+    // current bounds and splits: alpha moves only on unstable neurons, beta only on split ones
+    const float* l; const float* u; const int8_t* S; long ld_state;
     float* gamma; float* m_gamma; float* v_gamma; const float* g_gamma; long ld_gamma; int n_gamma;
     float lr, b1, b2, eps, bc1, bc2;
 };

@@ -364,22 +364,31 @@ __global__ void k_adam(AdamArgs a) {
     const long mo = ((long)in.b * a.n_sets + in.set) * a.ld_param + k;
     const long go = (long)blockIdx.y * a.ldg + k;
     if (k < a.n_ab) {
-        // alpha
-        float g = a.g_alpha[go];
-        float m = a.b1 * a.m_alpha[mo] + (1.f - a.b1) * g;
-        float v = a.b2 * a.v_alpha[mo] + (1.f - a.b2) * g * g;
-        a.m_alpha[mo] = m;
-        a.v_alpha[mo] = v;
-        float p = a.alpha[po] + a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
-        a.alpha[po] = fminf(fmaxf(p, 0.f), 1.f);
-        // beta
-        g = a.g_beta[go];
-        m = a.b1 * a.m_beta[mo] + (1.f - a.b1) * g;
-        v = a.b2 * a.v_beta[mo] + (1.f - a.b2) * g * g;
-        a.m_beta[mo] = m;
-        a.v_beta[mo] = v;
-        p = a.beta[po] + a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
-        a.beta[po] = fmaxf(p, 0.f);
+        // The alpha gradient is zero unless the neuron is unstable and unsplit, the beta
+        // gradient zero unless it is split.  A stable neuron stays stable (bounds are only
+        // intersected), so its alpha no longer enters any bound; a beta with zero gradient and
+        // zero moments does not move.  Only those entries are updated.
+        const long so = (long)in.slot * a.ld_state + k;
+        const int sj = (int)a.S[so];
+        if (sj == 0) {
+            if (a.l[so] < 0.f && a.u[so] > 0.f) {
+                const float g = a.g_alpha[go];
+                const float m = a.b1 * a.m_alpha[mo] + (1.f - a.b1) * g;
+                const float v = a.b2 * a.v_alpha[mo] + (1.f - a.b2) * g * g;
+                a.m_alpha[mo] = m;
+                a.v_alpha[mo] = v;
+                const float p = a.alpha[po] + a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+                a.alpha[po] = fminf(fmaxf(p, 0.f), 1.f);
+            }
+        } else {
+            const float g = a.g_beta[go];
+            const float m = a.b1 * a.m_beta[mo] + (1.f - a.b1) * g;
+            const float v = a.b2 * a.v_beta[mo] + (1.f - a.b2) * g * g;
+            a.m_beta[mo] = m;
+            a.v_beta[mo] = v;
+            const float p = a.beta[po] + a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+            a.beta[po] = fmaxf(p, 0.f);
+        }
     }
     if (a.gamma && k < a.n_gamma) {
         const long pg = ((long)in.slot * a.n_sets + in.set) * a.ld_gamma + k;
