@@ -68,28 +68,66 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // MF: the two first-layer convolutions run on v_mfma_f32_16x16x4_f32 (needs CO == 16 and
 // Ci*k*k <= 32): the transposed one as T = ahat^T W (positions x taps) plus a col2im
 // gather, the adjoint one as im2col(x*) W^T (positions x output channels).
-template <int NJ, int KK, int SS, int CO, bool MF>
+// SRC1: rows built from the objective convolution's filter (src_mode 1), a separate
+// instantiation so that the common case carries none of its registers.
+// RXL (up to 6 owned neurons per thread): the instance's relaxation of ReLU layer 0 lives
+// in LDS as one float4 per neuron instead of in registers, which leaves the registers for
+// the next row's prefetched coefficients.
+template <int NJ, int KK, int SS, int CO, bool MF, bool SRC1>
 __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) {
-    extern __shared__ float smem[];
+    constexpr bool RXL = NJ <= 6;
+    extern __shared__ float4 smem4[];
+    float4* s_rx = smem4;               // [d1] (RXL) {slope a' >= 0, slope a' < 0, intercept, S beta + Phat^T gamma}
+    float* smem = reinterpret_cast<float*>(smem4) + (RXL ? 4 * a.d1 : 0);
     const int d1 = a.d1;
     const int k = KK ? KK : a.k;
     const int s = SS ? SS : a.s;
-    float* s_ah = smem;                 // [d1]  ahat of the current row, then ghat
+    // With at most 16 taps the tap products T overwrite ahat in place: the wave that owns a
+    // 16-position tile reads all of its ahat before it writes its T.
+    const int TS = a.Ci * a.k * a.k > 16 ? 32 : 16;
+    const bool t_alias = TS == 16;
+    float* s_ah = smem;                 // [d1]  ahat of the current row, then T, then ghat
     float* s_x = s_ah + d1;             // [d0]  x* of the current row
-    float* s_b1 = s_x + a.d0;           // [Co]  first-layer bias per channel
+    int* s_xc = reinterpret_cast<int*>(s_x + a.d0);   // [d0] rows of the chunk with x*_o = hi_o (own o)
+    float* s_b1 = s_x + 2 * a.d0;       // [Co]  first-layer bias per channel
     float* s_w = s_b1 + ((a.Co + 3) & ~3);          // [Co*Ci*k*k] first-layer weights
     float* s_wp = s_w + ((a.Co * a.Ci * a.k * a.k + 3) & ~3);  // [16][32] weights, taps zero-padded (MF only)
-    float* s_T = s_wp + (MF ? 16 * 32 : 0);                     // [TS][Ho*Wo] tap products, tap-major (MF only)
-    const int TS = a.Ci * a.k * a.k > 16 ? 32 : 16;
-    float* s_sh = s_T + (MF ? a.Ho * a.Wo * TS : 0);   // [d1] sum over rows of ghat (own j)
-    float* s_sg = s_sh + d1;                           // [d1] sum over rows of g (own j, MNC only)
-    float* s_lo = s_sg + d1;                           // [d0] input box of the query (box_lds)
+    float* s_T = t_alias ? s_ah : s_wp + (MF ? 16 * 32 : 0);    // [TS][Ho*Wo] tap products, tap-major (MF only)
+    float* s_sg = s_wp + (MF ? 16 * 32 + (t_alias ? 0 : a.Ho * a.Wo * TS) : 0);   // [d1] sum of g (own j, MNC only)
+    float* s_lo = s_sg + (a.gsum_out ? d1 : 0);        // [d0] input box of the query (box_lds)
     float* s_hi = s_lo + a.d0;                         // [d0]
     __shared__ float red[3][NWV];
+    __shared__ RowDesc s_rd[BOTTOM_CHUNK_ROWS];   // the chunk's row descriptors,
+    __shared__ float s_crow[BOTTOM_CHUNK_ROWS];   // row constants
+    __shared__ float s_old[BOTTOM_CHUNK_ROWS];    // and previous bounds
 
     const int ib = a.cinst[blockIdx.x];
     const InstDesc in = a.inst[ib];
     const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+    // the chunk's rows (at most BOTTOM_CHUNK_ROWS by construction of the chunks): descriptor,
+    // constant and previous bound of each, loaded once with all loads in flight together
+    const int cr0 = a.cr0[blockIdx.x];
+    const int nr = min(a.cr1[blockIdx.x] - cr0, BOTTOM_CHUNK_ROWS);
+    for (int ri = wave; ri < nr; ri += NWV) {
+        const int r = cr0 + ri;
+        float cr = SRC1 ? 0.f : row_constant(a.c, a.cpart, a.ldcp, a.ncp, r);
+        if (lane == 0) {
+            const RowDesc rd = a.rows[r];
+            if (SRC1) cr = (float)rd.sign * a.bias_obj[rd.j];
+            float old = 0.f;
+            if (a.mode == 0) {
+                // each (slot, neuron) of the objective layer has exactly one row in a pass
+                const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
+                old = rd.sign > 0 ? a.lw[e] : a.uw[e];
+            } else if (a.mode == 1) {
+                old = a.best[r];
+            }
+            s_rd[ri] = rd;
+            s_crow[ri] = cr;
+            s_old[ri] = old;
+        }
+    }
     const int kk = k * k;
     const int nw = a.Co * a.Ci * kk;
     const int HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
@@ -100,9 +138,11 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
             s_wp[i] = tap < a.Ci * kk ? a.W1[co * a.Ci * kk + tap] : 0.f;
         }
     for (int i = t; i < a.Co; i += BT) s_b1[i] = a.b1[i];
+    for (int o = t; o < a.d0; o += BT) s_xc[o] = 0;
     const float* glo = a.lo + (long)a.qid[in.slot] * a.d0;
     const float* ghi = a.hi + (long)a.qid[in.slot] * a.d0;
-    if (a.box_lds)
+    const bool box_lds = RXL || a.box_lds;   // RXL launches always stage the box (checked by the host)
+    if (box_lds)
         for (int o = t; o < a.d0; o += BT) {
             s_lo[o] = glo[o];
             s_hi[o] = ghi[o];
@@ -110,15 +150,14 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
     // relaxation of ReLU layer 0 for this instance (split first, then stable, then unstable),
     // held by the thread that owns each neuron: slope where a' >= 0, slope and intercept where
     // a' < 0 (the intercept is > 0 exactly when unstable), S beta + (Phat^T gamma)
-    float rx_dp[NJ], rx_dn[NJ], rx_bn[NJ], rx_ad[NJ];
-    unsigned split_bits = 0;   // bit i: neuron t + i BT is split
+    constexpr int NR = RXL ? 1 : NJ;
+    float rx_dp[NR], rx_dn[NR], rx_bn[NR], rx_ad[NR];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         const int j = t + i * BT;
         float dp = 0.f, dn = 0.f, bn = 0.f, ad = 0.f;
         if (j < d1) {
-            s_sh[j] = 0.f;
-            s_sg[j] = 0.f;
+            if (a.gsum_out) s_sg[j] = 0.f;
             const long so = (long)in.slot * a.ld_state + j;
             const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + j;
             const float l = a.l[so], u = a.u[so];
@@ -136,55 +175,55 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
                 bn = -(u * l) / w;
             }
             ad = (sj != 0 ? (float)sj * a.beta[po] : 0.f) + (a.vhat ? a.vhat[(long)ib * d1 + j] : 0.f);
-            if (sj != 0) split_bits |= 1u << i;
         }
-        rx_dp[i] = dp;
-        rx_dn[i] = dn;
-        rx_bn[i] = bn;
-        rx_ad[i] = ad;
+        if constexpr (RXL) {
+            if (j < d1) s_rx[j] = make_float4(dp, dn, bn, ad);
+        } else {
+            rx_dp[i] = dp;
+            rx_dn[i] = dn;
+            rx_bn[i] = bn;
+            rx_ad[i] = ad;
+        }
     }
+    // relaxation of owned neuron i: registers, or LDS (RXL)
+    auto relax = [&](int i) -> float4 {
+        if constexpr (RXL)
+            return s_rx[t + i * BT];
+        else
+            return make_float4(rx_dp[i], rx_dn[i], rx_bn[i], rx_ad[i]);
+    };
     // forward convolution: per owned neuron its window origin and weight row
     const FastDiv div_HoWo(HoWo), div_Wo(a.Wo), div_HiWi(HiWi), div_Wi(a.Wi);
     const float* vrow = a.v ? a.v + (long)ib * d1 : nullptr;
     float da[NJ];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) da[i] = 0.f;
-    const bool want_h = a.gsum_hat != nullptr;
     const float gpv = a.gp ? a.gp[ib] : 0.f;
-    const int q = a.qid[in.slot];
-
+    // coefficients of the next row, loaded one row ahead (the first row's before the barrier,
+    // which waits for them)
+    float nx[SRC1 ? 1 : NJ];
+    if constexpr (!SRC1) {
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) nx[i] = (t + i * BT < d1 && nr > 0) ? a.A[(long)cr0 * d1 + t + i * BT] : 0.f;
+    }
     __syncthreads();
-    const int lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
     const int ntap = a.Ci * kk;                  // taps (ci, ky, kx) of one output channel
     const int MT = (HoWo + 15) >> 4;             // 16-row tiles over the positions of ReLU layer 0
     // MFMA B operands are read from s_wp per tile: transposed B[k = co][n = tap],
     // adjoint B[k = tap][n = co]
 
-    for (int r = a.cr0[blockIdx.x]; r < a.cr1[blockIdx.x]; ++r) {
-        const RowDesc rd = a.rows[r];
-        // previous bound of the row (thread 0): each (slot, neuron) of the objective layer has
-        // exactly one row in a pass
-        float old = 0.f;
-        if (t == 0) {
-            if (a.mode == 0) {
-                const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
-                old = rd.sign > 0 ? a.lw[e] : a.uw[e];
-            } else if (a.mode == 1) {
-                old = a.best[r];
-            }
-        }
+    for (int ri = 0; ri < nr; ++ri) {
+        const int r = cr0 + ri;
+        const RowDesc rd = s_rd[ri];
         // ---- row coefficients on the output of ReLU layer 0 (each thread its own j)
-        float crow = 0.f;
         float ap[NJ];
-        if (a.src_mode == 0) {
+        if constexpr (!SRC1) {
 #pragma unroll
-            for (int i = 0; i < NJ; ++i) {
-                const int j = t + i * BT;
-                ap[i] = j < d1 ? a.A[(long)r * d1 + j] : 0.f;
-            }
-            if (t == 0) {
-                crow = a.c[r];
-                for (int kq = 0; kq < a.ncp; ++kq) crow += a.cpart[(long)r * a.ldcp + kq];
+            for (int i = 0; i < NJ; ++i) ap[i] = nx[i];
+            if (ri + 1 < nr) {
+#pragma unroll
+                for (int i = 0; i < NJ; ++i)
+                    nx[i] = t + i * BT < d1 ? a.A[(long)(r + 1) * d1 + t + i * BT] : 0.f;
             }
         } else {
             // +-e_j on the output of the objective convolution: its filter placed at j
@@ -210,24 +249,35 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
                 }
                 ap[i] = v;
             }
-            if (t == 0) crow = sgn * a.bias_obj[rd.j];
         }
-        // ---- fold of ReLU layer 0
+        // ---- fold of ReLU layer 0 (global loads and stores kept out of the per-element code,
+        // so that no element waits for another's memory operations)
+        if (vrow) {
+            float vv[NJ];
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) vv[i] = t + i * BT < d1 ? vrow[t + i * BT] : 0.f;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) ap[i] += vv[i];
+        }
         float cpt = 0.f;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
             const int j = t + i * BT;
             if (j < d1) {
-                const float p = ap[i] + (vrow ? vrow[j] : 0.f);
-                ap[i] = p;
+                const float p = ap[i];
                 const bool neg = p < 0.f;
-                const float ah = p * (neg ? rx_dn[i] : rx_dp[i]) + rx_ad[i];
+                const float4 rx = relax(i);
+                const float ah = p * (neg ? rx.y : rx.x) + rx.w;
                 s_ah[j] = ah;
-                cpt += (neg ? p * rx_bn[i] : 0.f) + ah * s_b1[div_HoWo.div(j)];
-                if (a.Ap_out) a.Ap_out[(long)r * d1 + j] = p;
+                cpt += (neg ? p * rx.z : 0.f) + ah * s_b1[div_HoWo.div(j)];
             }
         }
-        if (t == 0) cpt += crow - gpv;
+        if (a.Ap_out) {
+#pragma unroll
+            for (int i = 0; i < NJ; ++i)
+                if (t + i * BT < d1) a.Ap_out[(long)r * d1 + t + i * BT] = ap[i];
+        }
+        if (t == 0) cpt += s_crow[ri] - gpv;
         lds_barrier();
         // ---- transposed first convolution and concretisation
         float lbp = 0.f, mag = 0.f;
@@ -289,7 +339,7 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
                 }
             }
             float l, h;
-            if (a.box_lds) {
+            if (box_lds) {
                 l = s_lo[o];
                 h = s_hi[o];
             } else {
@@ -300,14 +350,15 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
             mag += fabsf(acc) * fmaxf(fabsf(l), fabsf(h));
             const bool neg = acc < 0.f;
             s_x[o] = neg ? h : l;
+            if (a.adjoint && neg) s_xc[o] += 1;
             if (a.xbits) a.xbits[(long)r * a.d0 + o] = neg ? 1 : 0;
         }
         block_sum3(lbp, mag, cpt, red);   // also publishes s_x
         if (t == 0) {
             float lb = (lbp + cpt) - (mag + fabsf(cpt)) * 9.5367431640625e-07f;   // 2^-20 rounding margin
             if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
+            const float old = s_old[ri];
             if (a.mode == 0) {
-                // each (slot, neuron) of the objective layer has exactly one row in a pass
                 const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
                 if (rd.sign > 0)
                     a.lw[e] = fmaxf(old, lb);
@@ -344,7 +395,7 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
                         }
                         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, s_wp[lr * 32 + ks * 4 + lk], acc, 0, 0, 0);
                     }
-                    const float bco = a.b1[lr];
+                    const float bco = s_b1[lr];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int p2 = mt * 16 + 4 * lk + v;
@@ -390,57 +441,101 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
                 s_ah[j] = gh;
             }
             // ... then the relaxation of ReLU layer 0 and the instance's gradient sums (own j only)
+            float gv[NJ];
 #pragma unroll
             for (int i = 0; i < NJ; ++i) {
                 const int j = t + i * BT;
+                gv[i] = 0.f;
                 if (j < d1) {
                     const float gh = s_ah[j];
                     const bool neg = ap[i] < 0.f;
-                    const float bn = rx_bn[i];
-                    const float g = (neg ? rx_dn[i] : rx_dp[i]) * gh + (neg ? bn : 0.f);
+                    const float4 rx = relax(i);
+                    const float bn = rx.z;
+                    const float g = (neg ? rx.y : rx.x) * gh + (neg ? bn : 0.f);
                     if (bn > 0.f && !neg) da[i] += ap[i] * gh;
-                    if (want_h || ((split_bits >> i) & 1u)) s_sh[j] += gh;
                     if (a.gsum_out) s_sg[j] += g;
-                    if (a.Gout) a.Gout[(long)r * d1 + j] = g;
+                    gv[i] = g;
                 }
             }
+            vmem_drain();
+            if (a.Gout) {
+#pragma unroll
+                for (int i = 0; i < NJ; ++i)
+                    if (t + i * BT < d1) a.Gout[(long)r * d1 + t + i * BT] = gv[i];
+            }
+        } else {
+            vmem_drain();
         }
         lds_barrier();   // red[] and s_x are rewritten by the next row
     }
     if (!a.adjoint) return;
-    // partial sums of this chunk: alpha only where the neuron is unstable, the ghat sum only
-    // where it is split or MNC sums are wanted, the g sum only for MNCs (the reduction reads
-    // exactly the same entries)
-    float* pt = a.part + (long)blockIdx.x * 3 * d1;
+    // partial sums of this chunk: alpha only where the neuron is unstable, the g sum only for
+    // MNCs (the reduction reads exactly the same entries), and per input element the number
+    // of rows with x* = hi, from which the reduction takes the ghat sum (ghat = W1 x* + b1 is
+    // affine in x*, and x* is a box corner)
+    float* pt = a.part + (long)blockIdx.x * (2 * d1 + a.d0);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         const int j = t + i * BT;
         if (j < d1) {
-            if (rx_bn[i] > 0.f) pt[j] = da[i];
-            if (want_h || ((split_bits >> i) & 1u)) pt[d1 + j] = s_sh[j];
-            if (a.gsum_out) pt[2 * d1 + j] = s_sg[j];
+            if (relax(i).z > 0.f) pt[j] = da[i];
+            if (a.gsum_out) pt[d1 + j] = s_sg[j];
         }
     }
+    for (int o = t; o < a.d0; o += BT) pt[2 * d1 + o] = (float)s_xc[o];
 }
 
-// Instance gradients: the chunk partials summed in chunk order.
-__global__ void k_bottom_reduce(BottomArgs a) {
+// Instance gradients: the chunk partials summed in chunk order.  The sum over the n rows of
+// ghat_j is (W1 X)_j + n b1 with X_o = m_o hi_o + (n - m_o) lo_o, m_o the number of rows
+// with x*_o = hi_o (exact); it is evaluated in double, free of the cancellation that a
+// float sum of nearly opposite row terms would suffer.
+__global__ __launch_bounds__(256) void k_bottom_reduce(BottomArgs a) {
+    extern __shared__ double s_X[];   // [d0]
     const int ib = blockIdx.y;
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= a.d1) return;
     const InstDesc in = a.inst[ib];
+    const int d1 = a.d1, d0 = a.d0;
+    const int c0 = a.ichunk0[ib], c1 = a.ichunk1[ib];
+    const double n_rows = (double)(in.r1 - in.r0);
+    const float* lo = a.lo + (long)a.qid[in.slot] * d0;
+    const float* hi = a.hi + (long)a.qid[in.slot] * d0;
+    for (int o = threadIdx.x; o < d0; o += 256) {
+        float m = 0.f;   // integer counts: exact in float
+        for (int c = c0; c < c1; ++c) m += a.part[(long)c * (2 * d1 + d0) + 2 * d1 + o];
+        s_X[o] = (double)m * (double)hi[o] + (n_rows - (double)m) * (double)lo[o];
+    }
+    __syncthreads();
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= d1) return;
     const long so = (long)in.slot * a.ld_state + j;
     const int sj = (int)a.S[so];
     // unstable exactly where the fold used the triangle (same test as the kernel)
     const float l = a.l[so], u = a.u[so];
     const bool unst = sj == 0 && !(l >= 0.f) && !(u <= 0.f) && (-(u * l) / (u - l)) > 0.f;
     const bool need_h = a.gsum_hat || sj != 0;
-    float da = 0.f, sh = 0.f, sg = 0.f;
-    for (int c = a.ichunk0[ib]; c < a.ichunk1[ib]; ++c) {
-        const float* pt = a.part + (long)c * 3 * a.d1;
+    float da = 0.f, sg = 0.f;
+    for (int c = c0; c < c1; ++c) {
+        const float* pt = a.part + (long)c * (2 * d1 + d0);
         if (unst) da += pt[j];
-        if (need_h) sh += pt[a.d1 + j];
-        if (a.gsum_out) sg += pt[2 * a.d1 + j];
+        if (a.gsum_out) sg += pt[d1 + j];
+    }
+    float sh = 0.f;
+    if (need_h) {
+        const int HoWo = a.Ho * a.Wo, kk = a.k * a.k;
+        const int co = j / HoWo, q = j - co * HoWo, y = q / a.Wo, x = q - y * a.Wo;
+        const int Y0 = a.s * y - a.p, X0 = a.s * x - a.p;
+        const float* w = a.W1 + (long)co * a.Ci * kk;
+        double acc = n_rows * (double)a.b1[co];
+        for (int ci = 0; ci < a.Ci; ++ci)
+            for (int ky = 0; ky < a.k; ++ky) {
+                const int Y = Y0 + ky;
+                if ((unsigned)Y >= (unsigned)a.Hi) continue;
+                for (int kx = 0; kx < a.k; ++kx) {
+                    const int X = X0 + kx;
+                    if ((unsigned)X >= (unsigned)a.Wi) continue;
+                    acc += (double)w[(ci * a.k + ky) * a.k + kx] * s_X[(ci * a.Hi + Y) * a.Wi + X];
+                }
+            }
+        sh = (float)acc;
     }
     const long go = (long)ib * a.ldg + j;
     a.d_alpha[go] = da;
@@ -450,37 +545,55 @@ __global__ void k_bottom_reduce(BottomArgs a) {
 }
 
 bool bottom_supported(int d1, int d0, int n_weights) {
+    // worst-case LDS without the optional MFMA buffers: relaxation and box (up to 6 owned
+    // neurons per thread), ahat, g sums, x*, x* counts, weights and bias
+    const size_t rxl = cdiv(d1, BT) <= 6 ? 4 * (size_t)d1 + 2 * (size_t)d0 : 0;
     return d1 <= NJ_MAX * BT && d0 <= NO * BT && n_weights <= 4096 &&
-           (3 * d1 + d0 + n_weights + 64) * sizeof(float) <= 150 * 1024;
+           (rxl + 2 * (size_t)d1 + 2 * (size_t)d0 + n_weights + 128) * sizeof(float) <= 150 * 1024;
+}
+
+template <int KK, int SS, int CO, bool MF, bool SRC1>
+static void launch_bottom_nj(const BottomArgs& a, int n_blk, size_t lds, hipStream_t st) {
+    const int nj = cdiv(a.d1, BT);
+    if (nj <= 2)
+        hipLaunchKernelGGL((k_bottom<2, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
+    else if (nj <= 4)
+        hipLaunchKernelGGL((k_bottom<4, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
+    else if (nj <= 6)
+        hipLaunchKernelGGL((k_bottom<6, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_bottom<8, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
 }
 
 template <int KK, int SS, int CO, bool MF>
 static void launch_bottom_k(const BottomArgs& a, int n_blk, size_t lds, hipStream_t st) {
-    const int nj = cdiv(a.d1, BT);
-    if (nj <= 2)
-        hipLaunchKernelGGL((k_bottom<2, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
-    else if (nj <= 4)
-        hipLaunchKernelGGL((k_bottom<4, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
-    else if (nj <= 6)
-        hipLaunchKernelGGL((k_bottom<6, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
+    if (a.src_mode == 0)
+        launch_bottom_nj<KK, SS, CO, MF, false>(a, n_blk, lds, st);
     else
-        hipLaunchKernelGGL((k_bottom<8, KK, SS, CO, MF>), dim3(n_blk), dim3(BT), lds, st, a);
+        launch_bottom_nj<KK, SS, CO, MF, true>(a, n_blk, lds, st);
 }
 
 void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
     if (n_inst <= 0) return;
     MNB_CHECK(bottom_supported(a.d1, a.d0, a.Co * a.Ci * a.k * a.k) && a.k <= 3 * a.s && (a.s >= 2 || a.k <= 3),
               MNB_EDEVICE, "bottom kernel: unsupported shape");
-    const size_t base = (size_t)(3 * a.d1 + a.d0 + ((a.Co + 3) & ~3) + ((a.Co * a.Ci * a.k * a.k + 3) & ~3));
+    // LDS: ahat, x*, x* sum, bias, weights (+ g sums with MNCs); MFMA path: padded weights and,
+    // above 16 taps, a separate tap-product buffer
+    const size_t base = (size_t)(a.d1 + 2 * a.d0 + ((a.Co + 3) & ~3) + ((a.Co * a.Ci * a.k * a.k + 3) & ~3) +
+                                 (a.gsum_out ? a.d1 : 0));
     const size_t ts = a.Ci * a.k * a.k > 16 ? 32 : 16;
+    const size_t mf_extra = 16 * 32 + (ts == 32 ? (size_t)a.Ho * a.Wo * ts : 0);
     const int nb = a.n_chunk;
     if (nb <= 0) return;
+    const size_t rxl = cdiv(a.d1, BT) <= 6 ? 4 * (size_t)a.d1 : 0;   // relaxation in LDS
+    MNB_CHECK((base + rxl) * sizeof(float) <= 150 * 1024, MNB_EDEVICE, "bottom kernel: LDS");
     const bool mf = a.Co == 16 && a.Ci * a.k * a.k <= 32 &&
-                    (base + (size_t)a.Ho * a.Wo * ts + 16 * 32) * sizeof(float) <= 150 * 1024 && !getenv("MNB_BOTTOM_VALU");
-    size_t lds = (base + (mf ? (size_t)a.Ho * a.Wo * ts + 16 * 32 : 0)) * sizeof(float);
+                    (base + rxl + mf_extra) * sizeof(float) <= 150 * 1024 && !getenv("MNB_BOTTOM_VALU");
+    size_t lds = (base + rxl + (mf ? mf_extra : 0)) * sizeof(float);
     // the query's box in LDS when it fits beside the rest
     BottomArgs b = a;
     b.box_lds = lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
+    MNB_CHECK(b.box_lds || !rxl, MNB_EDEVICE, "bottom kernel: LDS");
     if (b.box_lds) lds += 2 * (size_t)a.d0 * sizeof(float);
     if (mf && a.k == 4 && a.s == 2)
         launch_bottom_k<4, 2, 16, true>(b, nb, lds, st);
@@ -488,10 +601,6 @@ void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
         launch_bottom_k<3, 2, 16, true>(b, nb, lds, st);
     else if (mf)
         launch_bottom_k<0, 0, 16, true>(b, nb, lds, st);
-    else if (a.k == 4 && a.s == 2 && a.Co == 16)
-        launch_bottom_k<4, 2, 16, false>(b, nb, lds, st);
-    else if (a.k == 3 && a.s == 2 && a.Co == 16)
-        launch_bottom_k<3, 2, 16, false>(b, nb, lds, st);
     else
         launch_bottom_k<0, 0, 0, false>(b, nb, lds, st);
     MNB_HIP(hipGetLastError());
@@ -499,7 +608,7 @@ void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
 
 void launch_bottom_reduce(const BottomArgs& a, int n_inst, hipStream_t st) {
     if (!a.adjoint || n_inst <= 0 || a.n_chunk <= 0) return;
-    hipLaunchKernelGGL(k_bottom_reduce, dim3(cdiv(a.d1, 256), n_inst), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_bottom_reduce, dim3(cdiv(a.d1, 256), n_inst), dim3(256), (size_t)a.d0 * sizeof(double), st, a);
     MNB_HIP(hipGetLastError());
 }
 

@@ -112,6 +112,9 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
     __shared__ float s_x[WT];         // x* on the input window (0 outside the image)
     __shared__ float s_g[16 * 16];    // ghat [c1][pos]
     __shared__ int s_rows[64];
+    __shared__ RowDesc s_rd[64];      // the window's row descriptors,
+    __shared__ float s_cb[64];        // objective biases (signed)
+    __shared__ float s_old[64];       // and previous bounds (mode 0)
     __shared__ int s_cnt[4];
     __shared__ float red[3][4];
     const int w = blockIdx.x, ib = blockIdx.y;
@@ -149,6 +152,19 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
         __syncthreads();
     }
     nrows = nrows < 64 ? nrows : 64;
+    // per row, loaded once: descriptor, signed objective bias and previous bound (each
+    // (slot, neuron) of the objective layer has exactly one row in a pass)
+    if (t < nrows) {
+        const RowDesc rd = a.rows[s_rows[t]];
+        s_rd[t] = rd;
+        s_cb[t] = (float)rd.sign * a.bobj[rd.j];
+        float old = 0.f;
+        if (a.mode == 0) {
+            const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
+            old = rd.sign > 0 ? a.lw[e] : a.uw[e];
+        }
+        s_old[t] = old;
+    }
 
     // ---- window entry e = t: neuron (c1, Yb+dy, Xb+dx) of ReLU layer 0 and its relaxation
     const int c1 = t / P, pe = t - c1 * P, dy = pe / a.ok, dx = pe - dy * a.ok;
@@ -214,18 +230,21 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
         xi[ks] = idx;
     }
     const float b1_lane = a.b1[lr];
-    __syncthreads();   // red[] is reused by the rows
+    __syncthreads();   // red[] is reused by the rows; s_rd, s_cb, s_old are visible
+    // objective filter entry of the next row, loaded one row ahead
+    float wnext = (ev && nrows > 0) ? a.Wobj[(long)(s_rd[0].j / nwin) * E + t] : 0.f;
 
     float da = 0.f, xs = 0.f;
     for (int ri = 0; ri < nrows; ++ri) {
         const int r = s_rows[ri];
-        const RowDesc rd = a.rows[r];
-        const int co2 = rd.j / nwin;
+        const RowDesc rd = s_rd[ri];
         const float sgn = (float)rd.sign;
+        const float wcur = wnext;
+        if (ev && ri + 1 < nrows) wnext = a.Wobj[(long)(s_rd[ri + 1].j / nwin) * E + t];
         // fold of ReLU layer 0 on the window (Eq. 5); S beta is in the instance terms
         float ap = 0.f, ce = 0.f;
         if (ev) {
-            ap = sgn * a.Wobj[(long)co2 * E + t];
+            ap = sgn * wcur;
             const bool neg = ap < 0.f;
             const float ah = ap * (neg ? dn : dp);
             s_ah[c1 * 16 + pe] = ah;
@@ -262,15 +281,15 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
         s_x[t] = xq;
         win_sum3(lbp, mag, ce, red);   // also publishes s_x
         if (t == 0) {
-            const float cpt = (ce + c_split) + sgn * a.bobj[rd.j];
+            const float cpt = (ce + c_split) + s_cb[ri];
             float lb = ((L_out + lbp) + cpt) - ((M_out + mag) + fabsf(cpt)) * 9.5367431640625e-07f;   // 2^-20 margin
             if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
             if (a.mode == 0) {
                 const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
                 if (rd.sign > 0)
-                    a.lw[e] = fmaxf(a.lw[e], lb);
+                    a.lw[e] = fmaxf(s_old[ri], lb);
                 else
-                    a.uw[e] = fminf(a.uw[e], isinf(lb) ? INFINITY : -lb);
+                    a.uw[e] = fminf(s_old[ri], isinf(lb) ? INFINITY : -lb);
             } else {
                 a.lb_out[r] = lb;
             }
@@ -292,6 +311,7 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
             if (ev && bn > 0.f && !(ap < 0.f)) da += ap * s_g[c1 * 16 + pe];
             xs += xq;
         }
+        vmem_drain();      // the next row's filter entry has arrived; nothing left in flight
         __syncthreads();   // s_ah, s_T, s_x, s_g and red[] are rewritten by the next row
     }
     if (!a.adjoint) return;

@@ -37,6 +37,22 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// c_r plus the ncp partial constants of the ReLU folds (row r of cpart), summed by one
+// wavefront: lane q adds the partials q, q + 64, ..., then the lanes are combined in a fixed
+// order.  All loads are issued together; every lane returns the total.
+__device__ __forceinline__ float row_constant(const float* c, const float* cpart, int ldcp, int ncp, long r) {
+    float s = 0.f;
+    for (int kq = (int)(threadIdx.x & 63); kq < ncp; kq += 64) s += cpart[r * ldcp + kq];
+    return c[r] + wave_sum(s);
+}
+
+// Wait until every global load and store this thread issued has completed (vmcnt 0; the LDS
+// and scalar counters are left alone).  The vector-memory counter covers loads and stores
+// alike, so a row loop that loads one row ahead drains it where those loads have long
+// arrived: nothing is then outstanding at the top of the next row, and no wait there also
+// waits for the stores of the row before.
+__device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ---------------------------------------------------------------- descriptors passed to kernels
 // Per-row descriptor of a back-substitution pass: which subproblem (local index
 // into the call's slot list), which parameter set, which instance (subproblem,

@@ -1119,7 +1119,7 @@ struct Evaluator {
                 ba.ichunk0 = ch.bchunk_d + 3 * nc;
                 ba.ichunk1 = ch.bchunk_d + 3 * nc + n_inst;
                 ba.n_chunk = nc;
-                if (adjoint) ba.part = ws.get<float>("bpart", (size_t)nc * 3 * net->relu_d[0]);
+                if (adjoint) ba.part = ws.get<float>("bpart", (size_t)nc * (2 * net->relu_d[0] + net->d0));
                 {
                     // algorithmic bytes: coefficient rows read (unless built from the filter),
                     // gradient rows and a' rows written, x* bits written

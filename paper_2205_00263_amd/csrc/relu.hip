@@ -152,9 +152,9 @@ __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
         red[1][threadIdx.x >> 6] = mag;
     }
     __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const float c = row_constant(a.c, a.cpart, a.ldcp, a.ncp, r);
     if (threadIdx.x != 0) return;
-    float c = a.c[r];
-    for (int k = 0; k < a.ncp; ++k) c += a.cpart[(long)r * a.ldcp + k];
     const float tot = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) + c;
     const float m = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) + fabsf(c);
     float lb = tot - m * 9.5367431640625e-07f;   // 2^-20
