@@ -1,13 +1,15 @@
 // Fused bottom of a back-substitution pass for networks whose first layer is a
-// small convolution of the input followed by a ReLU (ConvSmall, ResNet stems).
+// small convolution of the input followed by a ReLU (generic shapes; convolutions
+// into 16 channels with at most 32 taps per channel use the MFMA kernel of
+// bottom_mf.hip instead).
 //
-// One workgroup owns one instance (subproblem, parameter set) and walks its
-// rows.  Per row, everything below the first ReLU's output stays on chip:
+// One workgroup owns one chunk of rows of one instance (subproblem, parameter set)
+// and walks its rows.  Per row, everything below the first ReLU's output stays on chip:
 //   fold of ReLU layer 0 (Eq. 5)                -> ahat in LDS, a' in registers
 //   transposed first convolution (Eq. 2)        -> a^(0) in registers
 //   concretisation over the box (Eq. 6), x*     -> lb, x* in LDS
 //   adjoint: first convolution of x* + bias, the relaxation of ReLU layer 0
-//   and the alpha/beta gradient sums of the instance (fixed row order).
+//   and the alpha gradient sums of the instance (fixed row order).
 // Rows of an intermediate-bound pass whose objective is ReLU layer 1 are built
 // directly from the objective convolution's filter (the rows +-e_j).
 #include "bottom.h"
@@ -61,39 +63,28 @@ __device__ __forceinline__ void block_sum3(float& x, float& y, float& z, float (
     z = ((red[2][0] + red[2][1]) + (red[2][2] + red[2][3])) + ((red[2][4] + red[2][5]) + (red[2][6] + red[2][7]));
 }
 
-// KS: kernel size and stride of the first convolution as compile-time constants
-// (0: taken from the arguments).
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-// MF: the two first-layer convolutions run on v_mfma_f32_16x16x4_f32 (needs CO == 16 and
-// Ci*k*k <= 32): the transposed one as T = ahat^T W (positions x taps) plus a col2im
-// gather, the adjoint one as im2col(x*) W^T (positions x output channels).
+// Generic shapes (any first-layer channel count and kernel); the first-layer convolutions
+// into 16 channels with at most 32 taps run on MFMA in bottom_mf.hip.
 // SRC1: rows built from the objective convolution's filter (src_mode 1), a separate
 // instantiation so that the common case carries none of its registers.
 // RXL (up to 6 owned neurons per thread): the instance's relaxation of ReLU layer 0 lives
 // in LDS as one float4 per neuron instead of in registers, which leaves the registers for
 // the next row's prefetched coefficients.
-template <int NJ, int KK, int SS, int CO, bool MF, bool SRC1>
+template <int NJ, bool SRC1>
 __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) {
     constexpr bool RXL = NJ <= 6;
     extern __shared__ float4 smem4[];
     float4* s_rx = smem4;               // [d1] (RXL) {slope a' >= 0, slope a' < 0, intercept, S beta + Phat^T gamma}
     float* smem = reinterpret_cast<float*>(smem4) + (RXL ? 4 * a.d1 : 0);
     const int d1 = a.d1;
-    const int k = KK ? KK : a.k;
-    const int s = SS ? SS : a.s;
-    // With at most 16 taps the tap products T overwrite ahat in place: the wave that owns a
-    // 16-position tile reads all of its ahat before it writes its T.
-    const int TS = a.Ci * a.k * a.k > 16 ? 32 : 16;
-    const bool t_alias = TS == 16;
-    float* s_ah = smem;                 // [d1]  ahat of the current row, then T, then ghat
+    const int k = a.k;
+    const int s = a.s;
+    float* s_ah = smem;                 // [d1]  ahat of the current row, then ghat
     float* s_x = s_ah + d1;             // [d0]  x* of the current row
     int* s_xc = reinterpret_cast<int*>(s_x + a.d0);   // [d0] rows of the chunk with x*_o = hi_o (own o)
     float* s_b1 = s_x + 2 * a.d0;       // [Co]  first-layer bias per channel
     float* s_w = s_b1 + ((a.Co + 3) & ~3);          // [Co*Ci*k*k] first-layer weights
-    float* s_wp = s_w + ((a.Co * a.Ci * a.k * a.k + 3) & ~3);  // [16][32] weights, taps zero-padded (MF only)
-    float* s_T = t_alias ? s_ah : s_wp + (MF ? 16 * 32 : 0);    // [TS][Ho*Wo] tap products, tap-major (MF only)
-    float* s_sg = s_wp + (MF ? 16 * 32 + (t_alias ? 0 : a.Ho * a.Wo * TS) : 0);   // [d1] sum of g (own j, MNC only)
+    float* s_sg = s_w + ((a.Co * a.Ci * a.k * a.k + 3) & ~3);   // [d1] sum of g (own j, MNC only)
     float* s_lo = s_sg + (a.gsum_out ? d1 : 0);        // [d0] input box of the query (box_lds)
     float* s_hi = s_lo + a.d0;                         // [d0]
     __shared__ float red[3][NWV];
@@ -104,7 +95,7 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
     const int ib = a.cinst[blockIdx.x];
     const InstDesc in = a.inst[ib];
     const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+    const int lane = t & 63, wave = t >> 6;
     // the chunk's rows (at most BOTTOM_CHUNK_ROWS by construction of the chunks): descriptor,
     // constant and previous bound of each, loaded once with all loads in flight together
     const int cr0 = a.cr0[blockIdx.x];
@@ -132,11 +123,6 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
     const int nw = a.Co * a.Ci * kk;
     const int HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
     for (int i = t; i < nw; i += BT) s_w[i] = a.W1[i];
-    if constexpr (MF)
-        for (int i = t; i < 16 * 32; i += BT) {
-            const int co = i >> 5, tap = i & 31;
-            s_wp[i] = tap < a.Ci * kk ? a.W1[co * a.Ci * kk + tap] : 0.f;
-        }
     for (int i = t; i < a.Co; i += BT) s_b1[i] = a.b1[i];
     for (int o = t; o < a.d0; o += BT) s_xc[o] = 0;
     const float* glo = a.lo + (long)a.qid[in.slot] * a.d0;
@@ -207,10 +193,6 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
         for (int i = 0; i < NJ; ++i) nx[i] = (t + i * BT < d1 && nr > 0) ? a.A[(long)cr0 * d1 + t + i * BT] : 0.f;
     }
     __syncthreads();
-    const int ntap = a.Ci * kk;                  // taps (ci, ky, kx) of one output channel
-    const int MT = (HoWo + 15) >> 4;             // 16-row tiles over the positions of ReLU layer 0
-    // MFMA B operands are read from s_wp per tile: transposed B[k = co][n = tap],
-    // adjoint B[k = tap][n = co]
 
     for (int ri = 0; ri < nr; ++ri) {
         const int r = cr0 + ri;
@@ -282,28 +264,6 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
         // ---- transposed first convolution and concretisation
         float lbp = 0.f, mag = 0.f;
         const int wst = a.Ci * kk;
-        if constexpr (MF) {
-            // T[pos][tap] = sum_co ahat[co][pos] W[co][tap]
-            const int NTT = ntap > 16 ? 2 : 1;
-            for (int mt = wave; mt < MT; mt += NWV) {
-                const int pos = mt * 16 + lr;
-                float av[4];
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks) av[ks] = pos < HoWo ? s_ah[(ks * 4 + lk) * HoWo + pos] : 0.f;
-                for (int nt = 0; nt < NTT; ++nt) {
-                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], s_wp[(ks * 4 + lk) * 32 + nt * 16 + lr], acc, 0, 0, 0);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int p2 = mt * 16 + 4 * lk + v;
-                        if (p2 < HoWo) s_T[(nt * 16 + lr) * HoWo + p2] = acc[v];   // tap-major
-                    }
-                }
-            }
-            lds_barrier();
-        }
         for (int o = t; o < a.d0; o += BT) {
             const int ci = div_HiWi.div(o);
             const int qq = o - ci * HiWi;
@@ -311,31 +271,20 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
             const int Yp = Yq + a.p, Xp = qq - Yq * a.Wi + a.p;
             float acc = 0.f;
 #pragma unroll
-            for (int ty = 0; ty < (KK ? (KK + SS - 1) / SS : 8); ++ty) {
+            for (int ty = 0; ty < 8; ++ty) {
                 const int ky = Yp % s + ty * s;
-                if (!KK && ky >= k) break;
+                if (ky >= k) break;
                 const int y = (Yp - ky) / s;
-                if (ky >= k || y < 0 || y >= a.Ho) continue;
+                if (y < 0 || y >= a.Ho) continue;
 #pragma unroll
-                for (int tx = 0; tx < (KK ? (KK + SS - 1) / SS : 8); ++tx) {
+                for (int tx = 0; tx < 8; ++tx) {
                     const int kx = Xp % s + tx * s;
-                    if (!KK && kx >= k) break;
+                    if (kx >= k) break;
                     const int x = (Xp - kx) / s;
-                    if (kx >= k || x < 0 || x >= a.Wo) continue;
-                    if constexpr (MF) {
-                        acc += s_T[((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x];
-                        continue;
-                    }
+                    if (x < 0 || x >= a.Wo) continue;
                     const float* ah = s_ah + y * a.Wo + x;
                     const float* w = s_w + (ci * k + ky) * k + kx;
-                    if (CO) {
-                        float part[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                        for (int co = 0; co < (CO ? CO : 1); ++co) part[co & 3] += ah[co * HoWo] * w[co * wst];
-                        acc += (part[0] + part[1]) + (part[2] + part[3]);
-                    } else {
-                        for (int co = 0; co < a.Co; ++co) acc += ah[co * HoWo] * w[co * wst];
-                    }
+                    for (int co = 0; co < a.Co; ++co) acc += ah[co * HoWo] * w[co * wst];
                 }
             }
             float l, h;
@@ -375,57 +324,19 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
         }
         if (a.adjoint) {
             // ---- adjoint: first convolution of x* into s_ah (ahat is no longer read) ...
-            if constexpr (MF) {
-                const int KS = (ntap + 3) >> 2;
-                for (int mt = wave; mt < MT; mt += NWV) {
-                    const int pos = mt * 16 + lr;
-                    const int y = div_Wo.div(pos), x = pos - y * a.Wo;
-                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int ks = 0; ks < 8; ++ks) {
-                        if (ks >= KS) break;
-                        const int kq = ks * 4 + lk;
-                        float av = 0.f;
-                        if (kq < ntap && pos < HoWo) {
-                            const int ci = kq / kk, rr = kq - ci * kk;
-                            const int ky = rr / k, kx = rr - ky * k;
-                            const int Y = s * y - a.p + ky, X = s * x - a.p + kx;
-                            if ((unsigned)Y < (unsigned)a.Hi && (unsigned)X < (unsigned)a.Wi)
-                                av = s_x[(ci * a.Hi + Y) * a.Wi + X];
-                        }
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, s_wp[lr * 32 + ks * 4 + lk], acc, 0, 0, 0);
-                    }
-                    const float bco = s_b1[lr];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int p2 = mt * 16 + 4 * lk + v;
-                        if (p2 < HoWo) s_ah[lr * HoWo + p2] = acc[v] + bco;
-                    }
-                }
-                lds_barrier();
-            } else
             for (int j = t; j < d1; j += BT) {
                 const int co = div_HoWo.div(j);
                 const int qq = j - co * HoWo;
                 const int y = div_Wo.div(qq), x = qq - y * a.Wo;
                 const int Y0 = s * y - a.p, X0 = s * x - a.p;
                 const float* w = s_w + co * a.Ci * kk;
-                float gh = a.b1[co];
+                float gh = s_b1[co];
                 if (Y0 >= 0 && X0 >= 0 && Y0 + k <= a.Hi && X0 + k <= a.Wi) {
                     const float* xp = s_x + Y0 * a.Wi + X0;
-                    for (int ci = 0; ci < a.Ci; ++ci) {
-                        if (KK) {
-#pragma unroll
-                            for (int ky = 0; ky < (KK ? KK : 1); ++ky)
-#pragma unroll
-                                for (int kx = 0; kx < (KK ? KK : 1); ++kx)
-                                    gh += w[(ci * KK + ky) * KK + kx] * xp[ci * HiWi + ky * a.Wi + kx];
-                        } else {
-                            for (int ky = 0; ky < k; ++ky)
-                                for (int kx = 0; kx < k; ++kx)
-                                    gh += w[(ci * k + ky) * k + kx] * xp[ci * HiWi + ky * a.Wi + kx];
-                        }
-                    }
+                    for (int ci = 0; ci < a.Ci; ++ci)
+                        for (int ky = 0; ky < k; ++ky)
+                            for (int kx = 0; kx < k; ++kx)
+                                gh += w[(ci * k + ky) * k + kx] * xp[ci * HiWi + ky * a.Wi + kx];
                 } else {
                     for (int ci = 0; ci < a.Ci; ++ci)
                         for (int ky = 0; ky < k; ++ky) {
@@ -552,57 +463,45 @@ bool bottom_supported(int d1, int d0, int n_weights) {
            (rxl + 2 * (size_t)d1 + 2 * (size_t)d0 + n_weights + 128) * sizeof(float) <= 150 * 1024;
 }
 
-template <int KK, int SS, int CO, bool MF, bool SRC1>
+template <bool SRC1>
 static void launch_bottom_nj(const BottomArgs& a, int n_blk, size_t lds, hipStream_t st) {
     const int nj = cdiv(a.d1, BT);
     if (nj <= 2)
-        hipLaunchKernelGGL((k_bottom<2, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<2, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
     else if (nj <= 4)
-        hipLaunchKernelGGL((k_bottom<4, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<4, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
     else if (nj <= 6)
-        hipLaunchKernelGGL((k_bottom<6, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
+        hipLaunchKernelGGL((k_bottom<6, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
     else
-        hipLaunchKernelGGL((k_bottom<8, KK, SS, CO, MF, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
-}
-
-template <int KK, int SS, int CO, bool MF>
-static void launch_bottom_k(const BottomArgs& a, int n_blk, size_t lds, hipStream_t st) {
-    if (a.src_mode == 0)
-        launch_bottom_nj<KK, SS, CO, MF, false>(a, n_blk, lds, st);
-    else
-        launch_bottom_nj<KK, SS, CO, MF, true>(a, n_blk, lds, st);
+        hipLaunchKernelGGL((k_bottom<8, SRC1>), dim3(n_blk), dim3(BT), lds, st, a);
 }
 
 void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
     if (n_inst <= 0) return;
     MNB_CHECK(bottom_supported(a.d1, a.d0, a.Co * a.Ci * a.k * a.k) && a.k <= 3 * a.s && (a.s >= 2 || a.k <= 3),
               MNB_EDEVICE, "bottom kernel: unsupported shape");
-    // LDS: ahat, x*, x* sum, bias, weights (+ g sums with MNCs); MFMA path: padded weights and,
-    // above 16 taps, a separate tap-product buffer
-    const size_t base = (size_t)(a.d1 + 2 * a.d0 + ((a.Co + 3) & ~3) + ((a.Co * a.Ci * a.k * a.k + 3) & ~3) +
-                                 (a.gsum_out ? a.d1 : 0));
-    const size_t ts = a.Ci * a.k * a.k > 16 ? 32 : 16;
-    const size_t mf_extra = 16 * 32 + (ts == 32 ? (size_t)a.Ho * a.Wo * ts : 0);
     const int nb = a.n_chunk;
     if (nb <= 0) return;
-    const size_t rxl = cdiv(a.d1, BT) <= 6 ? 4 * (size_t)a.d1 : 0;   // relaxation in LDS
+    if (bottom_mf_supported(a.Co, a.Ci, a.k, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr) &&
+        !getenv("MNB_BOTTOM_VALU")) {
+        launch_bottom_mf(a, st);
+        return;
+    }
+    // LDS: relaxation (up to 6 owned neurons per thread), ahat, x*, x* counts, bias,
+    // weights (+ g sums with MNCs), and the box when it fits
+    const size_t rxl = cdiv(a.d1, BT) <= 6 ? 4 * (size_t)a.d1 : 0;
+    const size_t base = (size_t)(a.d1 + 2 * a.d0 + ((a.Co + 3) & ~3) + ((a.Co * a.Ci * a.k * a.k + 3) & ~3) +
+                                 (a.gsum_out ? a.d1 : 0));
     MNB_CHECK((base + rxl) * sizeof(float) <= 150 * 1024, MNB_EDEVICE, "bottom kernel: LDS");
-    const bool mf = a.Co == 16 && a.Ci * a.k * a.k <= 32 &&
-                    (base + rxl + mf_extra) * sizeof(float) <= 150 * 1024 && !getenv("MNB_BOTTOM_VALU");
-    size_t lds = (base + rxl + (mf ? mf_extra : 0)) * sizeof(float);
-    // the query's box in LDS when it fits beside the rest
+    size_t lds = (base + rxl) * sizeof(float);
     BottomArgs b = a;
     b.box_lds = lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
     MNB_CHECK(b.box_lds || !rxl, MNB_EDEVICE, "bottom kernel: LDS");
     if (b.box_lds) lds += 2 * (size_t)a.d0 * sizeof(float);
-    if (mf && a.k == 4 && a.s == 2)
-        launch_bottom_k<4, 2, 16, true>(b, nb, lds, st);
-    else if (mf && a.k == 3 && a.s == 2)
-        launch_bottom_k<3, 2, 16, true>(b, nb, lds, st);
-    else if (mf)
-        launch_bottom_k<0, 0, 16, true>(b, nb, lds, st);
+    if (a.src_mode == 0)
+        launch_bottom_nj<false>(b, nb, lds, st);
     else
-        launch_bottom_k<0, 0, 0, false>(b, nb, lds, st);
+        launch_bottom_nj<true>(b, nb, lds, st);
     MNB_HIP(hipGetLastError());
 }
 

@@ -31,10 +31,25 @@ void set_error(int code, const std::string& msg);
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------- device helpers
+// v + the value of the lane `CTRL` selects (a DPP row shift or row broadcast), 0 where the
+// source lane lies outside the row or the row is masked off.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_src(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
+}
+
+// Sum over the 64 lanes of a wavefront, in a fixed order, returned to every lane.  Within each
+// 16-lane row, row shifts by 1, 2, 4 and 8 leave the row total in the row's last lane; row
+// broadcasts of lanes 15 and 31 then combine the four rows in lane 63, which is read back.
+// Every lane of the wavefront must be active.
 __device__ __forceinline__ float wave_sum(float v) {
-    // Fixed-order butterfly over the 64 lanes of a wavefront.
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_src<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_src<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_src<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_src<0x118, 0xF>(v);   // row_shr:8
+    v += dpp_src<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_src<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // c_r plus the ncp partial constants of the ReLU folds (row r of cpart), summed by one
