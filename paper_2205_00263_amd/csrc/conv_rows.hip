@@ -308,6 +308,118 @@ __global__ __launch_bounds__(RT) void k_conv_rows(ConvRowsArgs a) {
     }
 }
 
+// Transposed convolution of rows whose input grid is small (at most 32 positions, up to
+// 16 taps, stride 2): per output channel ci a GEMM T[pos][tap] = sum_co A[co][pos] W[co][ci][tap]
+// over the row's own positions (no halo or stride-phase padding), then a col2im gather of the
+// at most 4 taps reaching each output.  Each wavefront owns a row at a time; the row is the
+// MFMA A operand straight from registers (loaded one row ahead), the weights are the B
+// operand from LDS, and T goes through a double-buffered per-wavefront LDS tile.
+struct ConvTTapArgs {
+    const float* A; float* C; const float* W; long M; int acc;
+    int Ci, Hi, Wi, Co, Ho, Wo, k, s, p;
+};
+
+constexpr int TT = 512;   // threads: 8 wavefronts
+constexpr int TLD = 17;   // T row stride (positions x 16 taps, padded)
+
+template <int MT, int K4, int NQ>   // MT: 16-position tiles, K4 = Co / 4, NQ: outputs per lane per channel
+__global__ __launch_bounds__(TT) void k_convT_tap(ConvTTapArgs a) {
+    constexpr int NTO = 4;                    // taps reaching an output (kernel <= 2 x stride 2)
+    constexpr int TB = 16 * MT * TLD;         // one T tile
+    extern __shared__ float sm[];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+    const int kk = a.k * a.k, HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
+    float* s_W = sm;                                         // [Ci][Co][16] B operand, taps padded
+    float* s_T = sm + a.Ci * a.Co * 16 + wave * 2 * TB;      // [2][16 MT][TLD]
+    for (int i = t; i < a.Ci * a.Co * 16; i += TT) {
+        const int tap = i & 15, cc = i >> 4, co = cc % a.Co, ci = cc / a.Co;
+        s_W[i] = tap < kk ? a.W[((long)co * a.Ci + ci) * kk + tap] : 0.f;
+    }
+    // per owned output q = lane + 64 i of a channel: its taps' T entries (-1: none)
+    int tix[NQ][NTO];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = lane + 64 * i;
+        const bool qv = q < HiWi;
+        const int Y = qv ? q / a.Wi : 0, X = qv ? q - Y * a.Wi : 0;
+        const int Yp = Y + a.p, Xp = X + a.p;
+#pragma unroll
+        for (int u = 0; u < NTO; ++u) {
+            const int ky = Yp % a.s + (u >> 1) * a.s, kx = Xp % a.s + (u & 1) * a.s;
+            const int y = (Yp - ky) / a.s, x = (Xp - kx) / a.s;
+            const bool tv = qv && ky < a.k && kx < a.k && Yp >= ky && Xp >= kx && y < a.Ho && x < a.Wo;
+            tix[i][u] = tv ? (y * a.Wo + x) * TLD + ky * a.k + kx : -1;
+        }
+    }
+    const long stride = (long)gridDim.x * (TT / 64);
+    long r = (long)blockIdx.x * (TT / 64) + wave;
+    // A operand of the row: lane (lr, lk) holds A[co = 4 ks + lk][pos = 16 mt + lr]
+    float nx[MT][K4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < K4; ++ks) {
+            const int pos = 16 * mt + lr;
+            nx[mt][ks] = (r < a.M && pos < HoWo) ? a.A[r * a.Co * HoWo + (4 * ks + lk) * HoWo + pos] : 0.f;
+        }
+    __syncthreads();
+    const long ldC = (long)a.Ci * HiWi;
+    for (; r < a.M; r += stride) {
+        float av[MT][K4];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < K4; ++ks) av[mt][ks] = nx[mt][ks];
+        if (r + stride < a.M) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int ks = 0; ks < K4; ++ks) {
+                    const int pos = 16 * mt + lr;
+                    nx[mt][ks] = pos < HoWo ? a.A[(r + stride) * a.Co * HoWo + (4 * ks + lk) * HoWo + pos] : 0.f;
+                }
+        }
+        float* dst = a.C + r * ldC;
+        auto channel = [&](int ci) {
+            float* T = s_T + (ci & 1) * TB;
+            f4 acc[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = f4{0.f, 0.f, 0.f, 0.f};
+            const float* wb = s_W + (long)ci * a.Co * 16 + lk * 16 + lr;
+#pragma unroll
+            for (int ks = 0; ks < K4; ++ks) {
+                const float b = wb[ks * 64];   // W[co = 4 ks + lk][ci][tap = lr]
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt][ks], b, acc[mt], 0, 0, 0);
+            }
+            // lane holds T[pos = 16 mt + 4 lk + v][tap = lr]
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) T[(16 * mt + 4 * lk + v) * TLD + lr] = acc[mt][v];
+            wave_lds_sync();
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                const int q = lane + 64 * i;
+                if (q < HiWi) {
+                    float sum = 0.f;
+#pragma unroll
+                    for (int u = 0; u < NTO; ++u)
+                        if (tix[i][u] >= 0) sum += T[tix[i][u]];
+                    float* o = dst + (long)ci * HiWi + q;
+                    *o = a.acc ? *o + sum : sum;
+                }
+            }
+        };
+        // the loads of the next row have arrived by the middle of this one: wait for them
+        // there, so that nothing is outstanding at the top of the next row
+        const int half = a.Ci / 2;
+        for (int ci = 0; ci < half; ++ci) channel(ci);
+        vmem_drain();
+        for (int ci = half; ci < a.Ci; ++ci) channel(ci);
+    }
+}
+
 int row_grid(long M) {
     const long nb = (M + 3) / 4;
     return (int)(nb < 2048 ? nb : 2048);
@@ -315,8 +427,35 @@ int row_grid(long M) {
 
 }  // namespace
 
+// Tap-GEMM form of the transposed convolution for small input grids; false when the shape
+// does not fit it.
+static bool launch_convT_tap(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st) {
+    static const bool off = getenv("MNB_NO_TAP_CONVT") != nullptr;
+    const int HoWo = g.Ho * g.Wo, HiWi = g.Hi * g.Wi;
+    if (off || g.s != 2 || g.k > 4 || g.Co != 32 || HoWo > 32 || HiWi > 192 || g.Ci < 2) return false;
+    ConvTTapArgs a{};
+    a.A = A; a.C = C; a.W = g.W; a.M = M; a.acc = accumulate;
+    a.Ci = g.Ci; a.Hi = g.Hi; a.Wi = g.Wi; a.Co = g.Co; a.Ho = g.Ho; a.Wo = g.Wo; a.k = g.k; a.s = g.s; a.p = g.p;
+    const int mt = (HoWo + 15) / 16, nq = (HiWi + 63) / 64;
+    const size_t lds = ((size_t)g.Ci * g.Co * 16 + (size_t)(TT / 64) * 2 * 16 * mt * TLD) * sizeof(float);
+    if (lds > ROW_LDS_MAX) return false;
+    if (M <= 0) return true;
+    const long nb = (M + TT / 64 - 1) / (TT / 64);
+    const dim3 grid((int)(nb < 512 ? nb : 512));
+#define MNB_TT(MT_, NQ_) hipLaunchKernelGGL((k_convT_tap<MT_, 8, NQ_>), grid, dim3(TT), lds, st, a)
+    if (mt == 1) {
+        if (nq == 1) MNB_TT(1, 1); else if (nq == 2) MNB_TT(1, 2); else MNB_TT(1, 3);
+    } else {
+        if (nq == 1) MNB_TT(2, 1); else if (nq == 2) MNB_TT(2, 2); else MNB_TT(2, 3);
+    }
+#undef MNB_TT
+    MNB_HIP(hipGetLastError());
+    return true;
+}
+
 bool launch_conv_backsub_rows(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
                               hipStream_t st) {
+    if (launch_convT_tap(g, A, C, M, accumulate, st)) return true;
     static const bool off = getenv("MNB_NO_ROW_CONV") != nullptr;
     if (off || g.Ci % 16 != 0 || (g.Co != 16 && g.Co != 32 && g.Co != 64) || g.n_phase > 4) return false;
     const int rowA = g.Co * g.Ho * g.Wo;
