@@ -36,7 +36,8 @@ BATCH = 512
 SPLIT_SEED = 3002
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bottom_convsmall_traffic.json")
 # sources that fix the fused kernel and the rows each of its launches gets
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_00263_amd", "csrc", f) for f in ("bottom.hip", "bottom.h", "engine.hip")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_00263_amd", "csrc", f)
+               for f in ("bottom_mf.hip", "bottom.hip", "bottom.h", "common.h", "engine.hip")]
 
 
 def kernel_sources_sha256():
