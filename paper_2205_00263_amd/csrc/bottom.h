@@ -50,6 +50,12 @@ constexpr int BOTTOM_CHUNK_ROWS = 32;
 
 // Window-sparse variant for intermediate rows whose objective is ReLU layer 1 fed by a
 // convolution of ReLU layer 0 (no MNC): one workgroup per (instance, window position).
+// A row of a window: pass row index r (~r for an upper-bound row), objective neuron,
+// signed objective bias and the objective neuron's bound before the pass (mode 0).
+struct WinEnt {
+    int32_t r, j;
+    float cb, old;
+};
 struct WinArgs {
     int mode;        // 0: update l/u of the objective layer, 2: lb only
     const RowDesc* rows; const InstDesc* inst; const int32_t* qid;
@@ -71,6 +77,9 @@ struct WinArgs {
     // per (instance, window): alpha partials [E], x* sums minus n x*_s [Ci IH IH], row counts
     float* part_a; float* part_x; int* part_n;
     float* d_alpha; float* d_beta; long ldg;
+    // per instance and window position: first entry in win_ent ([n_inst][nwin + 1]); the
+    // entries of a window are its rows in pass order (built by launch_bottom_win)
+    int* win_ptr; WinEnt* win_ent;
 };
 
 bool win_supported(int C1, int Ci, int k, int s, int ok, int oCo, int d1, int d0);

@@ -103,20 +103,73 @@ __global__ __launch_bounds__(WT) void k_win_prep(WinArgs a) {
     }
 }
 
+// Rows of each (instance, window position) in pass order: one workgroup per instance
+// partitions the instance's rows by the window position of their objective neuron
+// (stable, so the order is the pass order and does not depend on the rest of the batch),
+// and records with each row its signed objective bias and the bound before the pass.
+__global__ __launch_bounds__(WT) void k_win_rows(WinArgs a) {
+    extern __shared__ int s_win[];   // [rows of the instance] window position of each row
+    __shared__ int s_pre[65];
+    const int ib = blockIdx.x;
+    const InstDesc in = a.inst[ib];
+    const int t = threadIdx.x;
+    const int nwin = a.oHo * a.oWo, n = in.r1 - in.r0;
+    for (int i = t; i < n; i += WT) s_win[i] = a.rows[in.r0 + i].j % nwin;
+    __syncthreads();
+    int cnt = 0;
+    if (t < nwin)
+        for (int i = 0; i < n; ++i) cnt += s_win[i] == t;
+    if (t < nwin) s_pre[t + 1] = cnt;
+    __syncthreads();
+    if (t == 0) {
+        s_pre[0] = 0;
+        for (int w = 0; w < nwin; ++w) s_pre[w + 1] += s_pre[w];
+    }
+    __syncthreads();
+    int* ptr = a.win_ptr + (long)ib * (nwin + 1);
+    if (t <= nwin) ptr[t] = in.r0 + s_pre[t];
+    if (t < nwin) {
+        int k = in.r0 + s_pre[t];
+        for (int i = 0; i < n; ++i) {
+            if (s_win[i] != t) continue;
+            const int r = in.r0 + i;
+            const RowDesc rd = a.rows[r];
+            WinEnt e;
+            e.r = rd.sign > 0 ? r : ~r;
+            e.j = rd.j;
+            e.cb = (float)rd.sign * a.bobj[rd.j];
+            e.old = 0.f;
+            if (a.mode == 0) {
+                const long o = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
+                e.old = rd.sign > 0 ? a.lw[o] : a.uw[o];
+            }
+            a.win_ent[k++] = e;
+        }
+    }
+}
+
+// Wavefront-scope ordering of a wavefront's LDS buffers.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // NT: 16-wide tap tiles of the first convolution (1: Ci k k <= 16, 2: <= 32).
+// A workgroup owns one (instance, window position); its four wavefronts take the window's
+// rows in turn (row i -> wavefront i mod 4), each row end to end without workgroup
+// barriers.  Lane (lr, lk) owns the window entries (c1 = 4 lk + v, position lr) through the
+// fold, the transposed MFMA (A operand from registers) and the adjoint MFMA, computed as
+// ghat^T = W1 im2col(x*)^T so that its output lands in the same lanes; the input-window
+// pixels lane + 64 i are owned for col2im and the box.  The alpha and x* sums of each
+// wavefront's rows are merged over the wavefronts in a fixed order at the end.
 template <int NT>
 __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
-    __shared__ float s_w[16 * 32];    // W1 [c1][tap], taps padded to 32
-    __shared__ float s_ah[16 * 16];   // ahat [c1][pos], positions padded to 16
-    __shared__ float s_T[16 * 32];    // [pos][tap] tap products of the transposed convolution
-    __shared__ float s_x[WT];         // x* on the input window (0 outside the image)
-    __shared__ float s_g[16 * 16];    // ghat [c1][pos]
-    __shared__ int s_rows[64];
-    __shared__ RowDesc s_rd[64];      // the window's row descriptors,
-    __shared__ float s_cb[64];        // objective biases (signed)
-    __shared__ float s_old[64];       // and previous bounds (mode 0)
-    __shared__ int s_cnt[4];
-    __shared__ float red[3][4];
+    constexpr int NW = WT / 64;
+    __shared__ float s_T[NW][16 * 32];   // per wavefront: T[pos][tap] of the transposed convolution
+    __shared__ float s_x[NW][WT];        // per wavefront: x* on the input window (0 outside the image)
+    __shared__ int s_tix[WT][4];         // col2im: per input-window pixel, its T entries (-1: none)
+    __shared__ WinEnt s_ent[64];         // the window's rows (at most one per objective channel)
     const int w = blockIdx.x, ib = blockIdx.y;
     const InstDesc in = a.inst[ib];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
@@ -129,195 +182,242 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
     const int Yb = a.os * wy - a.op, Xb = a.os * wx - a.op;   // window origin on ReLU layer 0
     const int Ib = a.s * Yb - a.p, Jb = a.s * Xb - a.p;       // input-window origin
     const int HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
-    for (int i = t; i < 16 * 32; i += WT) {
-        const int c1 = i >> 5, tap = i & 31;
-        s_w[i] = tap < N ? a.W1[c1 * N + tap] : 0.f;
-    }
-    s_ah[t] = 0.f;
-    __syncthreads();
+    const int* wptr = a.win_ptr + (long)ib * (nwin + 1);
+    const int e0 = wptr[w];
+    const int nrows = min(wptr[w + 1] - e0, 64);
+    if (t < nrows) s_ent[t] = a.win_ent[e0 + t];
 
-    // ---- this window's rows of the instance, in row order (at most one per output channel)
-    int nrows = 0;
-    for (int base = in.r0; base < in.r1; base += WT) {
-        const int r = base + t;
-        const bool m = r < in.r1 && (a.rows[r].j % nwin) == w;
-        const unsigned long long bal = __ballot(m);
-        if (lane == 0) s_cnt[wave] = __popcll(bal);
-        __syncthreads();
-        int off = nrows;
-        for (int v = 0; v < wave; ++v) off += s_cnt[v];
-        const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
-        if (m && pos < 64) s_rows[pos] = r;
-        nrows += (s_cnt[0] + s_cnt[1]) + (s_cnt[2] + s_cnt[3]);
-        __syncthreads();
-    }
-    nrows = nrows < 64 ? nrows : 64;
-    // per row, loaded once: descriptor, signed objective bias and previous bound (each
-    // (slot, neuron) of the objective layer has exactly one row in a pass)
-    if (t < nrows) {
-        const RowDesc rd = a.rows[s_rows[t]];
-        s_rd[t] = rd;
-        s_cb[t] = (float)rd.sign * a.bobj[rd.j];
-        float old = 0.f;
-        if (a.mode == 0) {
-            const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
-            old = rd.sign > 0 ? a.lw[e] : a.uw[e];
-        }
-        s_old[t] = old;
-    }
-
-    // ---- window entry e = t: neuron (c1, Yb+dy, Xb+dx) of ReLU layer 0 and its relaxation
-    const int c1 = t / P, pe = t - c1 * P, dy = pe / a.ok, dx = pe - dy * a.ok;
+    // ---- owned window entries (c1 = 4 lk + v, pe = lr): relaxation of ReLU layer 0 and bias
+    const int dy = lr / a.ok, dx = lr - dy * a.ok;
     const int Y = Yb + dy, X = Xb + dx;
-    const bool ev = t < E && Y >= 0 && Y < a.Ho && X >= 0 && X < a.Wo;
-    float dp = 0.f, dn = 0.f, bn = 0.f, b1e = 0.f;
-    if (ev) {
-        const int j = c1 * HoWo + Y * a.Wo + X;
-        const long so = (long)in.slot * a.ld_state + j;
-        const float l = a.l[so], u = a.u[so];
-        const int sj = (int)a.S[so];
-        if (sj == -1) {
-            dp = dn = 1.f;
-        } else if (sj == 1) {
-        } else if (l >= 0.f) {
-            dp = dn = 1.f;
-        } else if (u <= 0.f) {
-        } else {
-            dp = a.alpha[((long)in.slot * a.n_sets + in.set) * a.ld_param + j];
-            const float wd = u - l;
-            dn = u / wd;
-            bn = -(u * l) / wd;
+    const bool pin = lr < P && Y >= 0 && Y < a.Ho && X >= 0 && X < a.Wo;
+    float rdp[4], rdn[4], rbn[4], b1v[4];
+    const long so0 = (long)in.slot * a.ld_state + Y * a.Wo + X;
+    const long po0 = ((long)in.slot * a.n_sets + in.set) * a.ld_param + Y * a.Wo + X;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int c1 = 4 * lk + v;
+        float dp = 0.f, dn = 0.f, bn = 0.f;
+        if (pin) {
+            const long so = so0 + (long)c1 * HoWo;
+            const float l = a.l[so], u = a.u[so];
+            const int sj = (int)a.S[so];
+            if (sj == -1) {
+                dp = dn = 1.f;
+            } else if (sj == 1) {
+            } else if (l >= 0.f) {
+                dp = dn = 1.f;
+            } else if (u <= 0.f) {
+            } else {
+                dp = a.alpha[po0 + (long)c1 * HoWo];
+                const float wd = u - l;
+                dn = u / wd;
+                bn = -(u * l) / wd;
+            }
         }
-        b1e = a.b1[c1];
+        rdp[v] = dp;
+        rdn[v] = dn;
+        rbn[v] = bn;
+        b1v[v] = a.b1[c1];
     }
-    // ---- input-window pixel q = t: (ciq, Ib+qy, Jb+qx)
-    const int ciq = t / IH2, rq = t - ciq * IH2, qy = rq / IH, qx = rq - qy * IH;
-    const int py = Ib + qy, px = Jb + qx;
-    const bool qv = t < NPIX && py >= 0 && py < a.Hi && px >= 0 && px < a.Wi;
-    float lo_q = 0.f, hi_q = 0.f, as_q = 0.f;
-    if (qv) {
-        const long o = (long)ciq * HiWi + py * a.Wi + px;
-        const long qo = (long)a.qid[in.slot] * a.d0;
-        lo_q = a.lo[qo + o];
-        hi_q = a.hi[qo + o];
-        as_q = a.asplit[(long)ib * a.d0 + o];
+    // ---- owned input-window pixels q = lane + 64 i: (ciq, Ib + qy, Jb + qx), box and A_s
+    float lo_q[4], hi_q[4], as_q[4];
+    bool qv[4];
+    const long qo = (long)a.qid[in.slot] * a.d0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = lane + 64 * i;
+        const int ciq = q / IH2, rq = q - ciq * IH2, qy = rq / IH, qx = rq - qy * IH;
+        const int py = Ib + qy, px = Jb + qx;
+        qv[i] = q < NPIX && py >= 0 && py < a.Hi && px >= 0 && px < a.Wi;
+        lo_q[i] = hi_q[i] = as_q[i] = 0.f;
+        if (qv[i]) {
+            const long o = (long)ciq * HiWi + py * a.Wi + px;
+            lo_q[i] = a.lo[qo + o];
+            hi_q[i] = a.hi[qo + o];
+            as_q[i] = a.asplit[(long)ib * a.d0 + o];
+        }
     }
-    // split terms outside the window: the instance totals minus the window's share
-    float Lw = qv ? fminf(as_q * lo_q, as_q * hi_q) : 0.f;
-    float Mw = qv ? fabsf(as_q) * fmaxf(fabsf(lo_q), fabsf(hi_q)) : 0.f;
-    float zz = 0.f;
-    win_sum3(Lw, Mw, zz, red);
-    const float* sc = a.scal + (long)ib * 4;
-    const float L_out = sc[0] - Lw, M_out = sc[1] - Mw, c_split = sc[2];
-
-    // ---- MFMA operands held in registers
-    const int nt = wave < NT ? wave : NT - 1;
-    float bT[4];   // transposed: B[k = c1][n = tap]
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) bT[ks] = s_w[(ks * 4 + lk) * 32 + nt * 16 + lr];
-    float bF[8];   // adjoint: B[k = tap][n = c1]
-    int xi[8];     // adjoint A operand: s_x index of (pos = lr, tap = 4 ks + lk), -1 if none
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-        const int tap = ks * 4 + lk;
-        bF[ks] = s_w[lr * 32 + tap];
-        int idx = -1;
-        if (tap < N && lr < P) {
-            const int ci = tap / kk, rr = tap - ci * kk, ky = rr / a.k, kx = rr - ky * a.k;
-            const int pdy = lr / a.ok, pdx = lr - pdy * a.ok;
-            idx = (ci * IH + a.s * pdy + ky) * IH + a.s * pdx + kx;
-        }
-        xi[ks] = idx;
-    }
-    const float b1_lane = a.b1[lr];
-    __syncthreads();   // red[] is reused by the rows; s_rd, s_cb, s_old are visible
-    // objective filter entry of the next row, loaded one row ahead
-    float wnext = (ev && nrows > 0) ? a.Wobj[(long)(s_rd[0].j / nwin) * E + t] : 0.f;
-
-    float da = 0.f, xs = 0.f;
-    for (int ri = 0; ri < nrows; ++ri) {
-        const int r = s_rows[ri];
-        const RowDesc rd = s_rd[ri];
-        const float sgn = (float)rd.sign;
-        const float wcur = wnext;
-        if (ev && ri + 1 < nrows) wnext = a.Wobj[(long)(s_rd[ri + 1].j / nwin) * E + t];
-        // fold of ReLU layer 0 on the window (Eq. 5); S beta is in the instance terms
-        float ap = 0.f, ce = 0.f;
-        if (ev) {
-            ap = sgn * wcur;
-            const bool neg = ap < 0.f;
-            const float ah = ap * (neg ? dn : dp);
-            s_ah[c1 * 16 + pe] = ah;
-            ce = (neg ? ap * bn : 0.f) + ah * b1e;
-        }
-        __syncthreads();
-        // transposed first convolution on the window: T[pos][tap] = sum_c1 ahat[c1][pos] W1[c1][tap]
-        if (wave < NT) {
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(s_ah[(ks * 4 + lk) * 16 + lr], bT[ks], acc, 0, 0, 0);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) s_T[(4 * lk + v) * 32 + nt * 16 + lr] = acc[v];
-        }
-        __syncthreads();
-        // col2im onto the input window plus A_s, then concretisation over the box (Eq. 6)
-        float lbp = 0.f, mag = 0.f, xq = 0.f;
-        if (qv) {
-            float acc = as_q;
+    // col2im table (pixel t): T entries [pos][tap] of the taps that reach it, in (ky, kx) order
+    {
+        const int q = t;
+        const int ciq = q / IH2, rq = q - ciq * IH2, qy = rq / IH, qx = rq - qy * IH;
+        int u = 0;
+        if (q < NPIX)
             for (int ky = qy % a.s; ky < a.k; ky += a.s) {
                 const int pdy = (qy - ky) / a.s;
                 if (qy < ky || pdy >= a.ok) continue;
                 for (int kx = qx % a.s; kx < a.k; kx += a.s) {
                     const int pdx = (qx - kx) / a.s;
                     if (qx < kx || pdx >= a.ok) continue;
-                    acc += s_T[(pdy * a.ok + pdx) * 32 + (ciq * a.k + ky) * a.k + kx];
+                    if (u < 4) s_tix[q][u++] = (pdy * a.ok + pdx) * 32 + (ciq * a.k + ky) * a.k + kx;
                 }
             }
-            lbp = fminf(acc * lo_q, acc * hi_q);
-            mag = fabsf(acc) * fmaxf(fabsf(lo_q), fabsf(hi_q));
-            xq = acc < 0.f ? hi_q : lo_q;
+        for (; u < 4; ++u) s_tix[q][u] = -1;
+    }
+    // ---- MFMA operands held in registers: transposed B[k = c1 = 4 lk + ks][n = tap = 16 nt + lr],
+    // adjoint A[m = c1 = lr][k = tap = 4 ks + lk] and its B operand's x* index (pos = lr)
+    float bT[NT][4], aW[4 * NT];
+    int xi[4 * NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int tap = nt * 16 + lr;
+            bT[nt][ks] = tap < N ? a.W1[(4 * lk + ks) * N + tap] : 0.f;
         }
-        s_x[t] = xq;
-        win_sum3(lbp, mag, ce, red);   // also publishes s_x
-        if (t == 0) {
-            const float cpt = (ce + c_split) + s_cb[ri];
+#pragma unroll
+    for (int ks = 0; ks < 4 * NT; ++ks) {
+        const int tap = 4 * ks + lk;
+        aW[ks] = tap < N ? a.W1[lr * N + tap] : 0.f;
+        int idx = -1;
+        if (tap < N && lr < P) {
+            const int ci = tap / kk, rr = tap - ci * kk, ky = rr / a.k, kx = rr - ky * a.k;
+            idx = (ci * IH + a.s * dy + ky) * IH + a.s * dx + kx;
+        }
+        xi[ks] = idx;
+    }
+    // split terms outside the window: the instance totals minus the window's share
+    float Lw = 0.f, Mw = 0.f;   // every wavefront owns the same pixels: each sums them itself
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (qv[i]) {
+                Lw += fminf(as_q[i] * lo_q[i], as_q[i] * hi_q[i]);
+                Mw += fabsf(as_q[i]) * fmaxf(fabsf(lo_q[i]), fabsf(hi_q[i]));
+            }
+    }
+    Lw = wave_sum(Lw);
+    Mw = wave_sum(Mw);
+    const float* sc = a.scal + (long)ib * 4;
+    const float L_out = sc[0] - Lw, M_out = sc[1] - Mw, c_split = sc[2];
+    __syncthreads();   // s_tix and s_ent complete
+    // objective filter entries of the wavefront's next row, loaded one row ahead
+    float wn[4];
+    {
+        const int co2 = wave < nrows ? s_ent[wave].j / nwin : 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wn[v] = (wave < nrows && pin) ? a.Wobj[(long)co2 * E + (4 * lk + v) * P + lr] : 0.f;
+    }
+
+    float da[4] = {0.f, 0.f, 0.f, 0.f}, xs[4] = {0.f, 0.f, 0.f, 0.f};
+    float* sT = s_T[wave];
+    float* sx = s_x[wave];
+    for (int ri = wave; ri < nrows; ri += NW) {
+        const WinEnt en = s_ent[ri];
+        const bool upos = en.r >= 0;   // lower-bound row (+e_j); upper rows store ~r
+        const int r = upos ? en.r : ~en.r;
+        const float sgn = upos ? 1.f : -1.f;
+        float ap[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ap[v] = sgn * wn[v];
+        if (ri + NW < nrows) {
+            const int co2 = s_ent[ri + NW].j / nwin;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) wn[v] = pin ? a.Wobj[(long)co2 * E + (4 * lk + v) * P + lr] : 0.f;
+        }
+        // fold of ReLU layer 0 on the window (Eq. 5); S beta is in the instance terms
+        float ah[4], ce = 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const bool neg = ap[v] < 0.f;
+            ah[v] = ap[v] * (neg ? rdn[v] : rdp[v]);
+            ce += (neg ? ap[v] * rbn[v] : 0.f) + ah[v] * b1v[v];
+        }
+        // transposed first convolution on the window: T[pos][tap] = sum_c1 ahat[c1][pos] W1[c1][tap];
+        // lane holds T[pos = 4 lk + v][tap = 16 nt + lr]
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[ks], bT[nt][ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sT[(4 * lk + v) * 32 + nt * 16 + lr] = acc[v];
+        }
+        wave_sync();
+        // col2im onto the input window plus A_s, then concretisation over the box (Eq. 6)
+        float lbp = 0.f, mag = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = lane + 64 * i;
+            float xq = 0.f;
+            if (qv[i]) {
+                float acc = as_q[i];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ti = s_tix[q][u];
+                    if (ti >= 0) acc += sT[ti];
+                }
+                lbp += fminf(acc * lo_q[i], acc * hi_q[i]);
+                mag += fabsf(acc) * fmaxf(fabsf(lo_q[i]), fabsf(hi_q[i]));
+                xq = acc < 0.f ? hi_q[i] : lo_q[i];
+            }
+            sx[q] = xq;
+            xs[i] += xq;
+        }
+        lbp = wave_sum(lbp);
+        mag = wave_sum(mag);
+        ce = wave_sum(ce);
+        if (lane == 0) {
+            const float cpt = (ce + c_split) + en.cb;
             float lb = ((L_out + lbp) + cpt) - ((M_out + mag) + fabsf(cpt)) * 9.5367431640625e-07f;   // 2^-20 margin
             if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
             if (a.mode == 0) {
-                const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
-                if (rd.sign > 0)
-                    a.lw[e] = fmaxf(s_old[ri], lb);
+                const long e = (long)in.slot * a.ld_state + a.state_off_obj + en.j;
+                if (upos)
+                    a.lw[e] = fmaxf(en.old, lb);
                 else
-                    a.uw[e] = fminf(s_old[ri], isinf(lb) ? INFINITY : -lb);
+                    a.uw[e] = fminf(en.old, isinf(lb) ? INFINITY : -lb);
             } else {
                 a.lb_out[r] = lb;
             }
         }
         if (a.adjoint) {
-            // ghat on the window: im2col(x*) W1^T plus bias
-            if (wave == 0) {
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
+            // ghat^T on the window: W1 im2col(x*)^T; lane holds ghat[c1 = 4 lk + v][pos = lr]
+            wave_sync();
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int ks = 0; ks < 8; ++ks) {
-                    if (ks * 4 >= N) break;
-                    const float av = xi[ks] >= 0 ? s_x[xi[ks]] : 0.f;
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bF[ks], acc, 0, 0, 0);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) s_g[lr * 16 + 4 * lk + v] = acc[v] + b1_lane;
+            for (int ks = 0; ks < 4 * NT; ++ks) {
+                if (4 * ks >= N) break;
+                const float xv = xi[ks] >= 0 ? sx[xi[ks]] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aW[ks], xv, acc, 0, 0, 0);
             }
-            __syncthreads();
-            if (ev && bn > 0.f && !(ap < 0.f)) da += ap * s_g[c1 * 16 + pe];
-            xs += xq;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float gh = acc[v] + b1v[v];
+                if (rbn[v] > 0.f && !(ap[v] < 0.f)) da[v] += ap[v] * gh;
+            }
         }
-        vmem_drain();      // the next row's filter entry has arrived; nothing left in flight
-        __syncthreads();   // s_ah, s_T, s_x, s_g and red[] are rewritten by the next row
+        vmem_drain();   // the next row's filter entries have arrived; nothing left in flight
     }
+    // merge the wavefronts' sums in a fixed order
+    __syncthreads();
+    float* m_a = &s_T[0][0];   // [NW][256] alpha partials by entry
+    float* m_x = &s_x[0][0];   // [NW][256] x* sums by pixel
+#pragma unroll
+    for (int v = 0; v < 4; ++v) m_a[wave * 256 + (4 * lk + v) * 16 + lr] = da[v];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) m_x[wave * 256 + lane + 64 * i] = xs[i];
+    __syncthreads();
     if (!a.adjoint) return;
     const long blk = (long)ib * nwin + w;
-    if (t < E) a.part_a[blk * E + t] = da;
-    if (t < NPIX) a.part_x[blk * NPIX + t] = qv ? xs - (float)nrows * (as_q < 0.f ? hi_q : lo_q) : 0.f;
+    if (t < E) {
+        const int c1 = t / P, pe = t - c1 * P;
+        const int k2 = c1 * 16 + pe;
+        a.part_a[blk * E + t] = ((m_a[k2] + m_a[256 + k2]) + m_a[512 + k2]) + m_a[768 + k2];
+    }
+    if (t < NPIX) {
+        const float xq = ((m_x[t] + m_x[256 + t]) + m_x[512 + t]) + m_x[768 + t];
+        const int ciq = t / IH2, rq = t - ciq * IH2, qy = rq / IH, qx = rq - qy * IH;
+        const int py = Ib + qy, px = Jb + qx;
+        const bool v = py >= 0 && py < a.Hi && px >= 0 && px < a.Wi;
+        float xb = 0.f;
+        if (v) {
+            const long o = (long)ciq * HiWi + py * a.Wi + px;
+            xb = a.asplit[(long)ib * a.d0 + o] < 0.f ? a.hi[qo + o] : a.lo[qo + o];
+        }
+        a.part_x[blk * NPIX + t] = v ? xq - (float)nrows * xb : 0.f;
+    }
     if (t == 0) a.part_n[blk] = nrows;
 }
 
@@ -399,7 +499,8 @@ __global__ __launch_bounds__(WT) void k_win_reduce(WinArgs a) {
 
 bool win_supported(int C1, int Ci, int k, int s, int ok, int oCo, int d1, int d0) {
     const int IH = (ok - 1) * s + k;
-    return C1 == 16 && ok * ok <= 16 && Ci * IH * IH <= WT && Ci * k * k <= 32 && oCo <= 64 &&
+    // at most 2 x 2 first-layer taps reach an input pixel (col2im table of 4 entries)
+    return C1 == 16 && ok * ok <= 16 && Ci * IH * IH <= WT && Ci * k * k <= 32 && oCo <= 64 && (k + s - 1) / s <= 2 &&
            (size_t)(d1 + 16 * 32) * sizeof(float) <= 64 * 1024 && (size_t)(d0 + 16 * 32) * sizeof(float) <= 64 * 1024;
 }
 
@@ -412,7 +513,11 @@ void launch_bottom_win(const WinArgs& a, int n_inst, hipStream_t st) {
     const int N = a.Ci * a.k * a.k;
     hipLaunchKernelGGL(k_win_prep, dim3(n_inst), dim3(WT), (a.d1 + a.C1 * N) * sizeof(float), st, a);
     MNB_HIP(hipGetLastError());
-    const dim3 grid(a.oHo * a.oWo, n_inst);
+    const int nwin = a.oHo * a.oWo;
+    MNB_CHECK(nwin <= 64 && a.win_ptr && a.win_ent, MNB_EDEVICE, "window bottom kernel: row lists");
+    hipLaunchKernelGGL(k_win_rows, dim3(n_inst), dim3(WT), (size_t)a.oCo * nwin * sizeof(int), st, a);
+    MNB_HIP(hipGetLastError());
+    const dim3 grid(nwin, n_inst);
     if (N <= 16)
         hipLaunchKernelGGL(k_bottom_win<1>, grid, dim3(WT), 0, st, a);
     else

@@ -1071,6 +1071,8 @@ struct Evaluator {
                 wa.lb_out = ba.lb_out;
                 wa.adjoint = adjoint;
                 wa.asplit = ws.get<float>("w_as", (size_t)n_inst * net->d0);
+                wa.win_ptr = ws.get<int>("w_ptr", (size_t)n_inst * (on.H * on.W + 1));
+                wa.win_ent = ws.get<WinEnt>("w_ent", (size_t)M);
                 wa.scal = ws.get<float>("w_sc", (size_t)n_inst * 4);
                 const int nwin = on.H * on.W, E = a1.C * on.k * on.k;
                 const int IH = (on.k - 1) * a1.stride + a1.k;
