@@ -83,6 +83,8 @@ struct WinArgs {
 };
 
 bool win_supported(int C1, int Ci, int k, int s, int ok, int oCo, int d1, int d0);
+// per-window row lists of a pass (win_ptr, win_ent); needed once per pass before launch_bottom_win
+void launch_win_rows(const WinArgs& a, int n_inst, hipStream_t st);
 void launch_bottom_win(const WinArgs& a, int n_inst, hipStream_t st);
 void launch_bottom_win_reduce(const WinArgs& a, int n_inst, hipStream_t st);
 

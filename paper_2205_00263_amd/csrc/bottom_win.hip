@@ -106,7 +106,8 @@ __global__ __launch_bounds__(WT) void k_win_prep(WinArgs a) {
 // Rows of each (instance, window position) in pass order: one workgroup per instance
 // partitions the instance's rows by the window position of their objective neuron
 // (stable, so the order is the pass order and does not depend on the rest of the batch),
-// and records with each row its signed objective bias and the bound before the pass.
+// and records with each row its signed objective bias.  The lists depend on the pass's
+// rows only, so they are built once for all evaluations of a pass.
 __global__ __launch_bounds__(WT) void k_win_rows(WinArgs a) {
     extern __shared__ int s_win[];   // [rows of the instance] window position of each row
     __shared__ int s_pre[65];
@@ -139,10 +140,6 @@ __global__ __launch_bounds__(WT) void k_win_rows(WinArgs a) {
             e.j = rd.j;
             e.cb = (float)rd.sign * a.bobj[rd.j];
             e.old = 0.f;
-            if (a.mode == 0) {
-                const long o = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
-                e.old = rd.sign > 0 ? a.lw[o] : a.uw[o];
-            }
             a.win_ent[k++] = e;
         }
     }
@@ -185,7 +182,16 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
     const int* wptr = a.win_ptr + (long)ib * (nwin + 1);
     const int e0 = wptr[w];
     const int nrows = min(wptr[w + 1] - e0, 64);
-    if (t < nrows) s_ent[t] = a.win_ent[e0 + t];
+    if (t < nrows) {
+        // the objective neuron's bound before this evaluation (mode 0); each (slot, neuron) of
+        // the objective layer has exactly one row in a pass
+        WinEnt e = a.win_ent[e0 + t];
+        if (a.mode == 0) {
+            const long o = (long)in.slot * a.ld_state + a.state_off_obj + e.j;
+            e.old = e.r >= 0 ? a.lw[o] : a.uw[o];
+        }
+        s_ent[t] = e;
+    }
 
     // ---- owned window entries (c1 = 4 lk + v, pe = lr): relaxation of ReLU layer 0 and bias
     const int dy = lr / a.ok, dx = lr - dy * a.ok;
@@ -515,13 +521,19 @@ void launch_bottom_win(const WinArgs& a, int n_inst, hipStream_t st) {
     MNB_HIP(hipGetLastError());
     const int nwin = a.oHo * a.oWo;
     MNB_CHECK(nwin <= 64 && a.win_ptr && a.win_ent, MNB_EDEVICE, "window bottom kernel: row lists");
-    hipLaunchKernelGGL(k_win_rows, dim3(n_inst), dim3(WT), (size_t)a.oCo * nwin * sizeof(int), st, a);
-    MNB_HIP(hipGetLastError());
     const dim3 grid(nwin, n_inst);
     if (N <= 16)
         hipLaunchKernelGGL(k_bottom_win<1>, grid, dim3(WT), 0, st, a);
     else
         hipLaunchKernelGGL(k_bottom_win<2>, grid, dim3(WT), 0, st, a);
+    MNB_HIP(hipGetLastError());
+}
+
+void launch_win_rows(const WinArgs& a, int n_inst, hipStream_t st) {
+    const int nwin = a.oHo * a.oWo;
+    if (n_inst <= 0) return;
+    MNB_CHECK(nwin <= 64 && a.win_ptr && a.win_ent, MNB_EDEVICE, "window row lists: shape");
+    hipLaunchKernelGGL(k_win_rows, dim3(n_inst), dim3(WT), (size_t)a.oCo * nwin * sizeof(int), st, a);
     MNB_HIP(hipGetLastError());
 }
 

@@ -553,6 +553,9 @@ struct PassChunk {
     // row chunks of the fused bottom kernel (built on first use)
     std::vector<int> bchunk_inst, bchunk_r0, bchunk_r1, bchunk_first, bchunk_last;
     int* bchunk_d = nullptr;
+    // per-window row lists of the window bottom kernel (built on first use)
+    int* win_ptr_d = nullptr;
+    WinEnt* win_ent_d = nullptr;
     int M = 0;                  // rows
     const RowDesc* rows = nullptr;   // device, chunk-relative row order
     std::vector<InstDesc> inst;      // host, rows relative to the chunk
@@ -603,6 +606,11 @@ struct PassCtx {
     };
     std::vector<Ckpt> ckpts;
     Workspace* ws = nullptr;
+    // rows +-e_j on a fully connected layer's output not materialised: the first fold of the
+    // pass reads sign W[j] (fold_W, fold_b: weights and objective bias; consumed by that fold)
+    const float* fold_W = nullptr;
+    const float* fold_b = nullptr;
+    const RowDesc* fold_rows = nullptr;
 };
 
 static int fold_cols(int d) { return cdiv(d, 256) * 4; }
@@ -692,6 +700,13 @@ static void walk_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, std::m
                 fa.v = cx.v.count(m) ? cx.v[m] : nullptr;
                 fa.vhat = cx.vh.count(m) ? cx.vh[m] : nullptr;
                 fa.bias = net->relu_bias[m];
+                if (cx.fold_W) {
+                    fa.Wsrc = cx.fold_W;
+                    fa.rows = cx.fold_rows;
+                    fa.c = cx.c;
+                    fa.bias_obj = cx.fold_b;
+                    cx.fold_W = nullptr;
+                }
                 {
                     TimerScope ts(MNB_T_FOLD, n, 0.0, (double)M * nd.size * (store_ap ? 12 : 8));
                     launch_relu_fold(fa, st, cx.gp.count(m) ? cx.gp[m] : nullptr);
@@ -745,6 +760,13 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
         if (o.kind == MNB_ADD) {
             init_aff(o.src, true);
             init_aff(o.src2, false);
+        } else if (o.kind == MNB_FC && net->nodes[o.src].kind == MNB_RELU && cx.ckpt_stride <= 1) {
+            // the rows are sign W[j] on the FC input: the ReLU fold that comes first reads them
+            // from W (no checkpoint copies this coefficient before that fold)
+            coef[o.src] = pool.acquire();
+            cx.fold_W = o.Wd;
+            cx.fold_b = be;
+            cx.fold_rows = ch.rows;
         } else {
             init_aff(on, true);
         }
@@ -1071,8 +1093,15 @@ struct Evaluator {
                 wa.lb_out = ba.lb_out;
                 wa.adjoint = adjoint;
                 wa.asplit = ws.get<float>("w_as", (size_t)n_inst * net->d0);
-                wa.win_ptr = ws.get<int>("w_ptr", (size_t)n_inst * (on.H * on.W + 1));
-                wa.win_ent = ws.get<WinEnt>("w_ent", (size_t)M);
+                const bool lists = ch.win_ptr_d == nullptr;
+                if (lists) {
+                    auto& c = const_cast<PassChunk&>(ch);
+                    const std::string tg = std::to_string((long)ch.inst_d);
+                    c.win_ptr_d = ws.get<int>("wptr" + tg, (size_t)n_inst * (on.H * on.W + 1));
+                    c.win_ent_d = ws.get<WinEnt>("went" + tg, (size_t)M);
+                }
+                wa.win_ptr = ch.win_ptr_d;
+                wa.win_ent = ch.win_ent_d;
                 wa.scal = ws.get<float>("w_sc", (size_t)n_inst * 4);
                 const int nwin = on.H * on.W, E = a1.C * on.k * on.k;
                 const int IH = (on.k - 1) * a1.stride + a1.k;
@@ -1082,6 +1111,7 @@ struct Evaluator {
                     wa.part_n = ws.get<int>("w_pn", (size_t)n_inst * nwin);
                     wa.d_alpha = ba.d_alpha; wa.d_beta = ba.d_beta; wa.ldg = ba.ldg;
                 }
+                if (lists) launch_win_rows(wa, n_inst, st);
                 {
                     const double macs = (double)on.k * on.k * a1.C * a1.geom.Ci * a1.k * a1.k;
                     TimerScope ts(MNB_T_BOTTOM_WIN, r0n, 2.0 * M * (adjoint ? 2.0 : 1.0) * macs, 0.0);

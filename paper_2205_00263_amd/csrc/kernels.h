@@ -63,6 +63,10 @@ struct FoldArgs {
     // gamma projections (nullable): per instance [n_inst, d]
     const float* v; const float* vhat;
     const float* bias;    // [d] effective bias of the affine output feeding this ReLU
+    // rows +-e_j on the output of a fully connected layer (Wsrc [dout, d]) folded directly:
+    // a = sign W[j] is read from Wsrc instead of A, and c[r] = sign bias_obj[j] is written
+    // (nullable: a is read from A)
+    const float* Wsrc; const RowDesc* rows; float* c; const float* bias_obj;
 };
 void launch_relu_fold(const FoldArgs& a, hipStream_t st);
 

@@ -58,21 +58,48 @@ __global__ __launch_bounds__(256) void k_relu_fold(FoldArgs a, const float* gp) 
     const float bias = a.bias[jj];
     const float gpv = (gp && blockIdx.x == 0 && threadIdx.x == 0) ? gp[blockIdx.y] : 0.f;
     const int col = a.col_off + blockIdx.x * 4 + (threadIdx.x >> 6);
-    for (int r = in.r0; r < in.r1; ++r) {
-        float contrib = 0.f;
-        if (ok) {
-            const long e = (long)r * a.d + j;
-            const float ap = a.A[e] + vv;
-            const bool neg = ap < 0.f;
-            const float D = neg ? nr.dneg : nr.dpos;
-            const float ah = ap * D + add;
-            a.A[e] = ah;
-            if (a.Ap) a.Ap[e] = ap;
-            contrib = (neg ? ap * nr.bneg : 0.f) + ah * bias;
+    // rows in groups of FR with all of a group's loads in flight together
+    constexpr int FR = 8;
+    for (int r0 = in.r0; r0 < in.r1; r0 += FR) {
+        float av[FR];
+        if (a.Wsrc) {
+            float sg[FR];
+            int jr[FR];
+#pragma unroll
+            for (int u = 0; u < FR; ++u) {
+                const RowDesc rd = a.rows[min(r0 + u, in.r1 - 1)];
+                sg[u] = (float)rd.sign;
+                jr[u] = rd.j;
+            }
+#pragma unroll
+            for (int u = 0; u < FR; ++u) av[u] = (ok && r0 + u < in.r1) ? sg[u] * a.Wsrc[(long)jr[u] * a.d + j] : 0.f;
+            if (blockIdx.x == 0 && threadIdx.x < FR && r0 + (int)threadIdx.x < in.r1) {
+                const int u = threadIdx.x;
+                a.c[r0 + u] = sg[u] * a.bias_obj[jr[u]];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < FR; ++u) av[u] = (ok && r0 + u < in.r1) ? a.A[(long)(r0 + u) * a.d + j] : 0.f;
         }
-        contrib -= gpv;
-        contrib = wave_sum(contrib);
-        if ((threadIdx.x & 63) == 0) a.cpart[(long)r * a.ldcp + col] = contrib;
+#pragma unroll
+        for (int u = 0; u < FR; ++u) {
+            const int r = r0 + u;
+            if (r >= in.r1) break;
+            float contrib = 0.f;
+            if (ok) {
+                const long e = (long)r * a.d + j;
+                const float ap = av[u] + vv;
+                const bool neg = ap < 0.f;
+                const float D = neg ? nr.dneg : nr.dpos;
+                const float ah = ap * D + add;
+                a.A[e] = ah;
+                if (a.Ap) a.Ap[e] = ap;
+                contrib = (neg ? ap * nr.bneg : 0.f) + ah * bias;
+            }
+            contrib -= gpv;
+            contrib = wave_sum(contrib);
+            if ((threadIdx.x & 63) == 0) a.cpart[(long)r * a.ldcp + col] = contrib;
+        }
     }
 }
 
@@ -97,16 +124,27 @@ __global__ __launch_bounds__(256) void k_relu_relax(RelaxArgs a) {
     const int s = (int)a.S[so];
     NeuronRelax nr = neuron_relax(a.l[so], a.u[so], s, a.alpha[po]);
     float da = 0.f, sh = 0.f, sg = 0.f;
-    for (int r = in.r0; r < in.r1; ++r) {
-        const long e = (long)r * a.d + j;
-        const float gh = a.G[e];
-        const float ap = a.Ap[e];
-        const bool neg = ap < 0.f;
-        const float g = (neg ? nr.dneg : nr.dpos) * gh + (neg ? nr.bneg : 0.f);
-        a.G[e] = g;
-        if (nr.unstable && !neg) da += ap * gh;
-        sh += gh;
-        sg += g;
+    // rows in groups of RR with all of a group's loads in flight together; sums in row order
+    constexpr int RR = 8;
+    for (int r0 = in.r0; r0 < in.r1; r0 += RR) {
+        float ghv[RR], apv[RR];
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+            const long e = (long)min(r0 + u, in.r1 - 1) * a.d + j;
+            ghv[u] = a.G[e];
+            apv[u] = a.Ap[e];
+        }
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+            if (r0 + u >= in.r1) break;
+            const float gh = ghv[u], ap = apv[u];
+            const bool neg = ap < 0.f;
+            const float g = (neg ? nr.dneg : nr.dpos) * gh + (neg ? nr.bneg : 0.f);
+            a.G[(long)(r0 + u) * a.d + j] = g;
+            if (nr.unstable && !neg) da += ap * gh;
+            sh += gh;
+            sg += g;
+        }
     }
     const long go = (long)blockIdx.y * a.ldg + a.goff + j;
     a.d_alpha[go] = da;
