@@ -35,7 +35,8 @@ __device__ __forceinline__ void lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Sum of three per-thread values over the block (fixed order); one barrier.
+// Sum of three per-thread values over the block (fixed order), valid in thread 0 only;
+// one barrier.
 __device__ __forceinline__ void bsum3(float& x, float& y, float& z, float (*red)[MNW]) {
     x = wave_sum(x);
     y = wave_sum(y);
@@ -47,6 +48,7 @@ __device__ __forceinline__ void bsum3(float& x, float& y, float& z, float (*red)
         red[2][w] = z;
     }
     lds_sync();
+    if (threadIdx.x != 0) return;
     float v[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -60,13 +62,21 @@ __device__ __forceinline__ void bsum3(float& x, float& y, float& z, float (*red)
     z = v[2];
 }
 
-// TPW: tiles per wavefront (1 is instantiated: up to 16 tiles); KK, SS: kernel size and
-// stride as constants (0: runtime); NTT: 16-tap tiles of the first convolution (1: at most
-// 16 taps, 2: at most 32); SRC1: rows built from the objective convolution's filter;
-// O1: at most one input element per thread (d0 <= 1024), whose col2im taps and box are
-// then held in registers for the whole chunk.
+// Taps of the first convolution that reach one input element (at most 3 x 3 with a runtime shape).
+template <int KK, int SS>
+constexpr int nto_taps() { return KK ? ((KK + SS - 1) / SS) * ((KK + SS - 1) / SS) : 9; }
+
+// KK, SS: kernel size and stride as constants (0: runtime); NTT: 16-tap tiles of the first
+// convolution (1: at most 16 taps, 2: at most 32); SRC1: rows built from the objective
+// convolution's filter; O1: at most one input element per thread (d0 <= 1024), whose col2im
+// taps, box and x* count are then held in registers for the whole chunk.
+// Rows are taken two at a time (RP, for first layers of at most 16 taps with a compile-time
+// shape): the barriers, block sums and memory drain of an iteration serve both, and their
+// MFMA chains interleave.
 template <int TPW, int KK, int SS, int NTT, bool SRC1, bool O1>
 __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
+    static_assert(TPW == 1, "one tile per wavefront");
+    constexpr int RP = (NTT == 1 && KK != 0) ? 2 : 1;   // rows per iteration (registers permitting)
     constexpr int KSM = 4 * NTT;   // 4-tap steps of the adjoint product
     const int k = KK ? KK : a.k;
     const int s = SS ? SS : a.s;
@@ -74,14 +84,21 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     const int HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
     const int kk = k * k, ntap = a.Ci * kk;
     const int MT = (HoWo + 15) >> 4;
-    extern __shared__ float smem[];
-    float* s_T = smem;                                   // [16 NTT][HoWo] tap products, tap-major
-    float* s_x = s_T + 16 * NTT * HoWo;                  // [d0] x* of the current row
-    int* s_xc = reinterpret_cast<int*>(s_x + d0);        // [d0] rows of the chunk with x*_o = hi_o
-    float* s_lo = s_x + 2 * d0;                          // [d0] box (box_lds)
+    const int TSZ = 16 * NTT * HoWo;
+    extern __shared__ float4 smem4[];
+    float4* s_rx = smem4;                                // [d1] relaxation {a' >= 0 slope, a' < 0 slope, intercept, add}
+    float* smem = reinterpret_cast<float*>(smem4 + d1);
+    float* s_T = smem;                                   // [RP][16 NTT][HoWo] tap products, tap-major
+    float* s_x = s_T + RP * TSZ;                         // [RP][d0] x* of the current rows
+    int* s_xc = reinterpret_cast<int*>(s_x + RP * d0);   // [d0] rows of the chunk with x*_o = hi_o (!O1)
+    float* s_lo = s_x + (RP + 1) * d0;                   // [d0] box (box_lds)
     float* s_hi = s_lo + d0;                             // [d0]
-    float* s_sg = s_x + 2 * d0 + (a.box_lds ? 2 * d0 : 0);   // [d1] sum of g (MNC only)
-    __shared__ float red[3][MNW];
+    float* s_sg = s_x + (RP + 1) * d0 + (a.box_lds ? 2 * d0 : 0);   // [d1] sum of g (MNC only)
+    // per thread, row-invariant index tables (NTO == 4, KSM == 4): col2im taps and adjoint gathers
+    constexpr bool TAB = O1 && nto_taps<KK, SS>() == 4 && KSM == 4;
+    const int tab_off = (int)((s_sg + (a.gsum_out ? d1 : 0)) - reinterpret_cast<float*>(smem4));
+    int4* s_tab = reinterpret_cast<int4*>(smem4) + (tab_off + 3) / 4;   // [2][MBT] (TAB)
+    __shared__ float red[3 * RP][MNW];
     __shared__ RowDesc s_rd[BOTTOM_CHUNK_ROWS];
     __shared__ float s_crow[BOTTOM_CHUNK_ROWS];
     __shared__ float s_old[BOTTOM_CHUNK_ROWS];
@@ -118,9 +135,10 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) b1v[v] = a.b1[4 * lk + v];
     // O1: the owned input element o = t, its tap products in s_T (-1: none) and its box
-    constexpr int NTO = KK ? ((KK + SS - 1) / SS) * ((KK + SS - 1) / SS) : 9;
+    constexpr int NTO = nto_taps<KK, SS>();
     int tix[O1 ? NTO : 1];
     float lo_o = 0.f, hi_o = 0.f;
+    int xc_o = 0;   // O1: rows of the chunk with x*_o = hi_o for the owned element
     if constexpr (O1) {
         const bool ov = t < d0;
         const int o = ov ? t : 0;
@@ -140,9 +158,10 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
             lo_o = glo[o];
             hi_o = ghi[o];
         }
+        if constexpr (TAB) s_tab[t] = make_int4(tix[0], tix[NTO > 1 ? 1 : 0], tix[NTO > 2 ? 2 : 0], tix[NTO > 3 ? 3 : 0]);
     }
     for (int o = t; o < d0; o += MBT) {
-        s_xc[o] = 0;
+        if constexpr (!O1) s_xc[o] = 0;
         if (a.box_lds) {
             s_lo[o] = glo[o];
             s_hi[o] = ghi[o];
@@ -168,18 +187,17 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         aW[ks] = tap < ntap ? a.W1[lr * ntap + tap] : 0.f;
     }
 
-    // owned neurons: tile mt = wave + u MNW, neuron (co = 4 lk + v, pos = 16 mt + lr)
-    // relaxation of ReLU layer 0 (split first, then stable, then unstable): slope where
-    // a' >= 0, slope and intercept where a' < 0 (the intercept is > 0 exactly when
-    // unstable), S beta + (Phat^T gamma)
-    float rdp[TPW][4], rdn[TPW][4], rbn[TPW][4], rad[TPW][4];
-    int gidx[TPW][KSM];   // adjoint B operand: s_x index of (pos = 16 mt + lr, tap = 4 ks + lk), -1: none
-    const long so0 = (long)in.slot * a.ld_state;
-    const long po0 = ((long)in.slot * a.n_sets + in.set) * a.ld_param;
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        const int pos = (wave + u * MNW) * 16 + lr;
-        const bool pv = pos < HoWo;
+    // owned neurons: tile mt = wave, neuron (co = 4 lk + v, pos = 16 mt + lr); their relaxation
+    // of ReLU layer 0 (split first, then stable, then unstable) goes to LDS: slope where
+    // a' >= 0, slope and intercept where a' < 0 (the intercept is > 0 exactly when unstable),
+    // S beta + (Phat^T gamma)
+    const int mt = wave;
+    const int pos = mt * 16 + lr;
+    const bool pv = pos < HoWo;
+    int gidx[KSM];   // adjoint B operand: s_x index of (pos, tap = 4 ks + lk), -1: none
+    {
+        const long so0 = (long)in.slot * a.ld_state;
+        const long po0 = ((long)in.slot * a.n_sets + in.set) * a.ld_param;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int j = (4 * lk + v) * HoWo + pos;
@@ -200,11 +218,8 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     bn = -(uu * l) / w;
                 }
                 ad = (sj != 0 ? (float)sj * a.beta[po0 + j] : 0.f) + (a.vhat ? a.vhat[(long)ib * d1 + j] : 0.f);
+                s_rx[j] = make_float4(dp, dn, bn, ad);
             }
-            rdp[u][v] = dp;
-            rdn[u][v] = dn;
-            rbn[u][v] = bn;
-            rad[u][v] = ad;
         }
         const int y = pv ? pos / a.Wo : 0, x = pv ? pos - y * a.Wo : 0;
 #pragma unroll
@@ -216,255 +231,321 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                 const int Y = s * y - a.p + ky, X = s * x - a.p + kx;
                 if ((unsigned)Y < (unsigned)a.Hi && (unsigned)X < (unsigned)a.Wi) idx = (ci * a.Hi + Y) * a.Wi + X;
             }
-            gidx[u][ks] = idx;
+            gidx[ks] = idx;
         }
+        if constexpr (TAB) s_tab[MBT + t] = make_int4(gidx[0], gidx[KSM > 1 ? 1 : 0], gidx[KSM > 2 ? 2 : 0], gidx[KSM > 3 ? 3 : 0]);
     }
-    float da[TPW][4];
-#pragma unroll
-    for (int u = 0; u < TPW; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) da[u][v] = 0.f;
+    auto relax = [&](int v) -> float4 {
+        return pv ? s_rx[(4 * lk + v) * HoWo + pos] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    float da[4] = {0.f, 0.f, 0.f, 0.f};
     const float* vrow = a.v ? a.v + (long)ib * d1 : nullptr;
     const float gpv = a.gp ? a.gp[ib] : 0.f;
-    // coefficients of the next row, loaded one row ahead (the first row's before the barrier,
-    // which waits for them)
-    float nx[SRC1 ? 1 : TPW][4];
+    // coefficients of the next rows, loaded one iteration ahead (the first ones before the
+    // barrier, which waits for them)
+    float nx[SRC1 ? 1 : RP][4];
     if constexpr (!SRC1) {
 #pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            const int pos = (wave + u * MNW) * 16 + lr;
+        for (int b = 0; b < RP; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                nx[u][v] = (pos < HoWo && nr > 0) ? a.A[(long)cr0 * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
-        }
+                nx[b][v] = (pv && b < nr) ? a.A[(long)(cr0 + b) * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
     }
     __syncthreads();
 
-    for (int ri = 0; ri < nr; ++ri) {
-        const int r = cr0 + ri;
-        const RowDesc rd = s_rd[ri];
+    for (int ri = 0; ri < nr; ri += RP) {
+        const int nb = min(RP, nr - ri);   // rows this iteration (the second may be absent)
         // ---- row coefficients a on the owned neurons of ReLU layer 0
-        float ap[TPW][4];
+        float ap[RP][4];
         if constexpr (!SRC1) {
 #pragma unroll
-            for (int u = 0; u < TPW; ++u)
+            for (int b = 0; b < RP; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ap[u][v] = nx[u][v];
-            if (ri + 1 < nr) {
+                for (int v = 0; v < 4; ++v) ap[b][v] = nx[b][v];
+            if (ri + RP < nr) {
 #pragma unroll
-                for (int u = 0; u < TPW; ++u) {
-                    const int pos = (wave + u * MNW) * 16 + lr;
+                for (int b = 0; b < RP; ++b)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        nx[u][v] = pos < HoWo ? a.A[(long)(r + 1) * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
-                }
+                        nx[b][v] = (pv && ri + RP + b < nr) ? a.A[(long)(cr0 + ri + RP + b) * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
             }
         } else {
             // +-e_j on the output of the objective convolution: its filter placed at j
-            const float sgn = (float)rd.sign;
-            const int per = a.oHo * a.oWo;
-            const int oco = rd.j / per, opos = rd.j - oco * per;
-            const int oy = opos / a.oWo, ox = opos - oy * a.oWo;
-            const float* wrow = a.Wobj + (long)oco * a.oCi * a.ok * a.ok;
 #pragma unroll
-            for (int u = 0; u < TPW; ++u) {
-                const int pos = (wave + u * MNW) * 16 + lr;
-                const int Y = pos < HoWo ? pos / a.oWi : 0, X = pos - Y * a.oWi;
+            for (int b = 0; b < RP; ++b) {
+                const RowDesc rd = s_rd[min(ri + b, nr - 1)];
+                const float sgn = b < nb ? (float)rd.sign : 0.f;
+                const int per = a.oHo * a.oWo;
+                const int oco = rd.j / per, opos = rd.j - oco * per;
+                const int oy = opos / a.oWo, ox = opos - oy * a.oWo;
+                const float* wrow = a.Wobj + (long)oco * a.oCi * a.ok * a.ok;
+                const int Y = pv ? pos / a.oWi : 0, X = pos - Y * a.oWi;
                 const int ky = Y - a.os * oy + a.op, kx = X - a.os * ox + a.op;
-                const bool in_w = pos < HoWo && (unsigned)ky < (unsigned)a.ok && (unsigned)kx < (unsigned)a.ok;
+                const bool in_w = pv && (unsigned)ky < (unsigned)a.ok && (unsigned)kx < (unsigned)a.ok;
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    ap[u][v] = in_w ? sgn * wrow[((4 * lk + v) * a.ok + ky) * a.ok + kx] : 0.f;
+                for (int v = 0; v < 4; ++v) ap[b][v] = in_w ? sgn * wrow[((4 * lk + v) * a.ok + ky) * a.ok + kx] : 0.f;
             }
         }
         if (vrow) {
-            float vv[TPW][4];
+            float vv[4];
 #pragma unroll
-            for (int u = 0; u < TPW; ++u) {
-                const int pos = (wave + u * MNW) * 16 + lr;
+            for (int v = 0; v < 4; ++v) vv[v] = pv ? vrow[(4 * lk + v) * HoWo + pos] : 0.f;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) vv[u][v] = pos < HoWo ? vrow[(4 * lk + v) * HoWo + pos] : 0.f;
-            }
+            for (int b = 0; b < RP; ++b)
 #pragma unroll
-            for (int u = 0; u < TPW; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) ap[u][v] += vv[u][v];
+                for (int v = 0; v < 4; ++v) ap[b][v] += b < nb ? vv[v] : 0.f;
         }
-        // ---- fold of ReLU layer 0 and the transposed first convolution of each owned tile
-        float cpt = 0.f;
+        // ---- fold of ReLU layer 0 and the transposed first convolution of the owned tile
+        float cpt[RP];
+        {
+            float ah[RP][4];
 #pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            const int mt = wave + u * MNW;
-            float ah[4];
+            for (int b = 0; b < RP; ++b) cpt[b] = 0.f;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float p = ap[u][v];
-                const bool neg = p < 0.f;
-                ah[v] = p * (neg ? rdn[u][v] : rdp[u][v]) + rad[u][v];
-                cpt += (neg ? p * rbn[u][v] : 0.f) + ah[v] * b1v[v];
+                const float4 rx = relax(v);
+#pragma unroll
+                for (int b = 0; b < RP; ++b) {
+                    const float p = ap[b][v];
+                    const bool neg = p < 0.f;
+                    ah[b][v] = p * (neg ? rx.y : rx.x) + (b < nb ? rx.w : 0.f);
+                    cpt[b] += (neg ? p * rx.z : 0.f) + ah[b][v] * b1v[v];
+                }
             }
             if (mt < MT) {
 #pragma unroll
                 for (int nt = 0; nt < NTT; ++nt) {
-                    f4 acc = {0.f, 0.f, 0.f, 0.f};
+                    f4 acc[RP];
+#pragma unroll
+                    for (int b = 0; b < RP; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                     for (int ks = 0; ks < 4; ++ks)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[ks], bT[nt][ks], acc, 0, 0, 0);
+#pragma unroll
+                        for (int b = 0; b < RP; ++b)
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[b][ks], bT[nt][ks], acc[b], 0, 0, 0);
                     // lane holds T[pos = 16 mt + 4 lk + v][tap = 16 nt + lr]
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int p2 = mt * 16 + 4 * lk + v;
-                        if (p2 < HoWo) s_T[(nt * 16 + lr) * HoWo + p2] = acc[v];
+                    for (int b = 0; b < RP; ++b)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int p2 = mt * 16 + 4 * lk + v;
+                            if (p2 < HoWo) s_T[b * TSZ + (nt * 16 + lr) * HoWo + p2] = acc[b][v];
+                        }
+                }
+            }
+        }
+        if (a.Ap_out && pv) {
+#pragma unroll
+            for (int b = 0; b < RP; ++b)
+                if (b < nb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) a.Ap_out[(long)(cr0 + ri + b) * d1 + (4 * lk + v) * HoWo + pos] = ap[b][v];
+        }
+        if (t == 0)
+#pragma unroll
+            for (int b = 0; b < RP; ++b) cpt[b] += b < nb ? s_crow[ri + b] - gpv : 0.f;
+        lds_sync();
+        // ---- col2im onto the input and concretisation over the box (Eq. 6), x*
+        float lbp[RP], mag[RP];
+#pragma unroll
+        for (int b = 0; b < RP; ++b) lbp[b] = mag[b] = 0.f;
+        if constexpr (O1) {
+            if (t < d0) {
+                int tq[NTO];
+                if constexpr (TAB) {
+                    const int4 tv = s_tab[t];
+                    tq[0] = tv.x;
+                    tq[NTO > 1 ? 1 : 0] = NTO > 1 ? tv.y : tq[0];
+                    tq[NTO > 2 ? 2 : 0] = NTO > 2 ? tv.z : tq[0];
+                    tq[NTO > 3 ? 3 : 0] = NTO > 3 ? tv.w : tq[0];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NTO; ++q) tq[q] = tix[q];
+                }
+#pragma unroll
+                for (int b = 0; b < RP; ++b) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int q = 0; q < NTO; ++q)
+                        if (tq[q] >= 0) acc += s_T[b * TSZ + tq[q]];
+                    lbp[b] = fminf(acc * lo_o, acc * hi_o);
+                    mag[b] = fabsf(acc) * fmaxf(fabsf(lo_o), fabsf(hi_o));
+                    const bool neg = acc < 0.f;
+                    s_x[b * d0 + t] = neg ? hi_o : lo_o;
+                    if (b < nb) {
+                        xc_o += neg ? 1 : 0;
+                        if (a.xbits) a.xbits[(long)(cr0 + ri + b) * d0 + t] = neg ? 1 : 0;
+                    }
+                }
+            }
+        } else {
+            for (int o = t; o < d0; o += MBT) {
+                const int ci = o / HiWi, qq = o - ci * HiWi;
+                const int Yq = qq / a.Wi;
+                const int Yp = Yq + a.p, Xp = qq - Yq * a.Wi + a.p;
+                float l, h;
+                if (a.box_lds) {
+                    l = s_lo[o];
+                    h = s_hi[o];
+                } else {
+                    l = glo[o];
+                    h = ghi[o];
+                }
+#pragma unroll
+                for (int b = 0; b < RP; ++b) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int ty = 0; ty < (KK ? (KK + SS - 1) / SS : 8); ++ty) {
+                        const int ky = Yp % s + ty * s;
+                        if (!KK && ky >= k) break;
+                        const int y = (Yp - ky) / s;
+                        if (ky >= k || y < 0 || y >= a.Ho) continue;
+#pragma unroll
+                        for (int tx = 0; tx < (KK ? (KK + SS - 1) / SS : 8); ++tx) {
+                            const int kx = Xp % s + tx * s;
+                            if (!KK && kx >= k) break;
+                            const int x = (Xp - kx) / s;
+                            if (kx >= k || x < 0 || x >= a.Wo) continue;
+                            acc += s_T[b * TSZ + ((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x];
+                        }
+                    }
+                    lbp[b] += fminf(acc * l, acc * h);
+                    mag[b] += fabsf(acc) * fmaxf(fabsf(l), fabsf(h));
+                    const bool neg = acc < 0.f;
+                    s_x[b * d0 + o] = neg ? h : l;
+                    if (b < nb) {
+                        if (a.adjoint && neg) s_xc[o] += 1;
+                        if (a.xbits) a.xbits[(long)(cr0 + ri + b) * d0 + o] = neg ? 1 : 0;
                     }
                 }
             }
         }
-        if (a.Ap_out) {
+        // block sums of the RP rows' bound terms (one barrier, which also publishes s_x); the
+        // sums are valid in thread 0
+        {
+            float vals[3 * RP];
 #pragma unroll
-            for (int u = 0; u < TPW; ++u) {
-                const int pos = (wave + u * MNW) * 16 + lr;
-                if (pos < HoWo)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) a.Ap_out[(long)r * d1 + (4 * lk + v) * HoWo + pos] = ap[u][v];
+            for (int b = 0; b < RP; ++b) {
+                vals[3 * b] = wave_sum(lbp[b]);
+                vals[3 * b + 1] = wave_sum(mag[b]);
+                vals[3 * b + 2] = wave_sum(cpt[b]);
             }
-        }
-        if (t == 0) cpt += s_crow[ri] - gpv;
-        lds_sync();
-        // ---- col2im onto the input and concretisation over the box (Eq. 6), x*
-        float lbp = 0.f, mag = 0.f;
-        if constexpr (O1) {
-            if (t < d0) {
-                float acc = 0.f;
+            if (lane == 0)
 #pragma unroll
-                for (int q = 0; q < NTO; ++q)
-                    if (tix[q] >= 0) acc += s_T[tix[q]];
-                lbp = fminf(acc * lo_o, acc * hi_o);
-                mag = fabsf(acc) * fmaxf(fabsf(lo_o), fabsf(hi_o));
-                const bool neg = acc < 0.f;
-                s_x[t] = neg ? hi_o : lo_o;
-                if (a.adjoint && neg) s_xc[t] += 1;
-                if (a.xbits) a.xbits[(long)r * d0 + t] = neg ? 1 : 0;
-            }
-        } else
-        for (int o = t; o < d0; o += MBT) {
-            const int ci = o / HiWi, qq = o - ci * HiWi;
-            const int Yq = qq / a.Wi;
-            const int Yp = Yq + a.p, Xp = qq - Yq * a.Wi + a.p;
-            float acc = 0.f;
+                for (int q = 0; q < 3 * RP; ++q) red[q][wave] = vals[q];
+            lds_sync();
+            if (t == 0) {
 #pragma unroll
-            for (int ty = 0; ty < (KK ? (KK + SS - 1) / SS : 8); ++ty) {
-                const int ky = Yp % s + ty * s;
-                if (!KK && ky >= k) break;
-                const int y = (Yp - ky) / s;
-                if (ky >= k || y < 0 || y >= a.Ho) continue;
+                for (int b = 0; b < RP; ++b) {
+                    if (b >= nb) break;
+                    float tot[3];
 #pragma unroll
-                for (int tx = 0; tx < (KK ? (KK + SS - 1) / SS : 8); ++tx) {
-                    const int kx = Xp % s + tx * s;
-                    if (!KK && kx >= k) break;
-                    const int x = (Xp - kx) / s;
-                    if (kx >= k || x < 0 || x >= a.Wo) continue;
-                    acc += s_T[((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x];
-                }
-            }
-            float l, h;
-            if (a.box_lds) {
-                l = s_lo[o];
-                h = s_hi[o];
-            } else {
-                l = glo[o];
-                h = ghi[o];
-            }
-            lbp += fminf(acc * l, acc * h);
-            mag += fabsf(acc) * fmaxf(fabsf(l), fabsf(h));
-            const bool neg = acc < 0.f;
-            s_x[o] = neg ? h : l;
-            if (a.adjoint && neg) s_xc[o] += 1;
-            if (a.xbits) a.xbits[(long)r * d0 + o] = neg ? 1 : 0;
-        }
-        bsum3(lbp, mag, cpt, red);   // also publishes s_x
-        if (t == 0) {
-            float lb = (lbp + cpt) - (mag + fabsf(cpt)) * 9.5367431640625e-07f;   // 2^-20 rounding margin
-            if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
-            const float old = s_old[ri];
-            if (a.mode == 0) {
-                const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
-                if (rd.sign > 0)
-                    a.lw[e] = fmaxf(old, lb);
-                else
-                    a.uw[e] = fminf(old, isinf(lb) ? INFINITY : -lb);
-            } else {
-                a.lb_out[r] = lb;
-                if (a.mode == 1) {
-                    const bool better = lb > old;
-                    if (better) a.best[r] = lb;
-                    a.improved[r] = better ? 1 : 0;
+                    for (int q = 0; q < 3; ++q) {
+                        const float* rq = red[3 * b + q];
+                        const float h0 = ((rq[0] + rq[1]) + (rq[2] + rq[3])) + ((rq[4] + rq[5]) + (rq[6] + rq[7]));
+                        const float h1 = ((rq[8] + rq[9]) + (rq[10] + rq[11])) + ((rq[12] + rq[13]) + (rq[14] + rq[15]));
+                        tot[q] = h0 + h1;
+                    }
+                    const int r = cr0 + ri + b;
+                    const RowDesc rd = s_rd[ri + b];
+                    float lb = (tot[0] + tot[2]) - (tot[1] + fabsf(tot[2])) * 9.5367431640625e-07f;   // 2^-20 margin
+                    if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
+                    const float old = s_old[ri + b];
+                    if (a.mode == 0) {
+                        const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
+                        if (rd.sign > 0)
+                            a.lw[e] = fmaxf(old, lb);
+                        else
+                            a.uw[e] = fminf(old, isinf(lb) ? INFINITY : -lb);
+                    } else {
+                        a.lb_out[r] = lb;
+                        if (a.mode == 1) {
+                            const bool better = lb > old;
+                            if (better) a.best[r] = lb;
+                            a.improved[r] = better ? 1 : 0;
+                        }
+                    }
                 }
             }
         }
         if (a.adjoint) {
-            // ---- adjoint: ghat^T = W1 im2col(x*)^T + b1 per owned tile, then the relaxation of
-            // ReLU layer 0 and the alpha (and MNC g) sums of the owned neurons
-            float gv[TPW][4];
+            // ---- adjoint: ghat^T = W1 im2col(x*)^T + b1 on the owned tile, then the relaxation of
+            // ReLU layer 0 and the alpha (and MNC g) sums of the owned neurons, rows in order
+            f4 acc[RP];
 #pragma unroll
-            for (int u = 0; u < TPW; ++u) {
-                const int mt = wave + u * MNW;
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
-                if (mt < MT) {
+            for (int b = 0; b < RP; ++b) acc[b] = f4{0.f, 0.f, 0.f, 0.f};
+            if (mt < MT) {
+                int gq[KSM];
+                if constexpr (TAB) {
+                    const int4 gv4 = s_tab[MBT + t];
+                    gq[0] = gv4.x;
+                    gq[KSM > 1 ? 1 : 0] = KSM > 1 ? gv4.y : gq[0];
+                    gq[KSM > 2 ? 2 : 0] = KSM > 2 ? gv4.z : gq[0];
+                    gq[KSM > 3 ? 3 : 0] = KSM > 3 ? gv4.w : gq[0];
+                } else {
 #pragma unroll
-                    for (int ks = 0; ks < KSM; ++ks) {
-                        if (4 * ks >= ntap) break;
-                        const int gi = gidx[u][ks];
-                        const float xv = gi >= 0 ? s_x[gi] : 0.f;
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aW[ks], xv, acc, 0, 0, 0);
+                    for (int ks = 0; ks < KSM; ++ks) gq[ks] = gidx[ks];
+                }
+#pragma unroll
+                for (int ks = 0; ks < KSM; ++ks) {
+                    if (4 * ks >= ntap) break;
+                    const int gi = gq[ks];
+#pragma unroll
+                    for (int b = 0; b < RP; ++b) {
+                        const float xv = gi >= 0 ? s_x[b * d0 + gi] : 0.f;
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aW[ks], xv, acc[b], 0, 0, 0);
                     }
                 }
-                const int pos = mt * 16 + lr;
+            }
+            float gv[RP][4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    // lane holds ghat[co = 4 lk + v][pos = 16 mt + lr] without the bias
-                    const float gh = acc[v] + b1v[v];
-                    const float p = ap[u][v];
+            for (int v = 0; v < 4; ++v) {
+                const float4 rx = relax(v);
+#pragma unroll
+                for (int b = 0; b < RP; ++b) {
+                    // lane holds ghat[co = 4 lk + v][pos] without the bias
+                    const float gh = acc[b][v] + b1v[v];
+                    const float p = ap[b][v];
                     const bool neg = p < 0.f;
-                    const float bn = rbn[u][v];
-                    const float g = (neg ? rdn[u][v] : rdp[u][v]) * gh + (neg ? bn : 0.f);
-                    if (bn > 0.f && !neg) da[u][v] += p * gh;
-                    if (a.gsum_out && pos < HoWo) s_sg[(4 * lk + v) * HoWo + pos] += g;
-                    gv[u][v] = g;
+                    const float g = (neg ? rx.y : rx.x) * gh + (neg ? rx.z : 0.f);
+                    if (b < nb) {
+                        if (rx.z > 0.f && !neg) da[v] += p * gh;
+                        if (a.gsum_out && pv) s_sg[(4 * lk + v) * HoWo + pos] += g;
+                    }
+                    gv[b][v] = g;
                 }
             }
             vmem_drain();
-            if (a.Gout) {
+            if (a.Gout && pv) {
 #pragma unroll
-                for (int u = 0; u < TPW; ++u) {
-                    const int pos = (wave + u * MNW) * 16 + lr;
-                    if (pos < HoWo)
+                for (int b = 0; b < RP; ++b)
+                    if (b < nb)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) a.Gout[(long)r * d1 + (4 * lk + v) * HoWo + pos] = gv[u][v];
-                }
+                        for (int v = 0; v < 4; ++v) a.Gout[(long)(cr0 + ri + b) * d1 + (4 * lk + v) * HoWo + pos] = gv[b][v];
             }
         } else {
             vmem_drain();
         }
-        // next row: its T writes follow the barrier above (every col2im read is done) and its
-        // x* writes follow its first barrier (every adjoint gather of this row is done)
+        // next iteration: its T writes follow the barrier above (every col2im read is done) and
+        // its x* writes follow its first barrier (every adjoint gather of this one is done)
     }
     if (!a.adjoint) return;
     lds_sync();   // s_sg and s_xc complete
     // partial sums of this chunk: alpha only where the neuron is unstable, the g sum only for
     // MNCs, and per input element the number of rows with x* = hi
     float* pt = a.part + (long)blockIdx.x * (2 * d1 + d0);
+    if (pv)
 #pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        const int pos = (wave + u * MNW) * 16 + lr;
-        if (pos < HoWo)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int j = (4 * lk + v) * HoWo + pos;
-                if (rbn[u][v] > 0.f) pt[j] = da[u][v];
-                if (a.gsum_out) pt[d1 + j] = s_sg[j];
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int j = (4 * lk + v) * HoWo + pos;
+            if (relax(v).z > 0.f) pt[j] = da[v];
+            if (a.gsum_out) pt[d1 + j] = s_sg[j];
+        }
+    if constexpr (O1) {
+        if (t < d0) pt[2 * d1 + t] = (float)xc_o;
+    } else {
+        for (int o = t; o < d0; o += MBT) pt[2 * d1 + o] = (float)s_xc[o];
     }
-    for (int o = t; o < d0; o += MBT) pt[2 * d1 + o] = (float)s_xc[o];
 }
 
 template <int TPW, int KK, int SS, int NTT, bool O1>
@@ -490,9 +571,18 @@ void launch_mf_tpw(const BottomArgs& a, size_t lds, hipStream_t st) {
 
 }  // namespace
 
+// LDS of the MFMA bottom kernel without the box: relaxation, two rows' tap products and x*,
+// x* counts, g sums (MNC), per-thread index tables
+static size_t mf_lds(int Ci, int k, int Ho, int Wo, int d0, int d1, bool mnc) {
+    const int ntap = Ci * k * k;
+    return (4 * (size_t)d1 + 2 * (size_t)16 * (ntap > 16 ? 2 : 1) * Ho * Wo + 3 * (size_t)d0 + (mnc ? (size_t)d1 : 0) + 4 +
+            2 * 4 * (size_t)MBT) *
+           sizeof(float);
+}
+
 bool bottom_mf_supported(int Co, int Ci, int k, int Ho, int Wo, int d0, int d1, bool mnc) {
     const int HoWo = Ho * Wo, ntap = Ci * k * k;
-    const size_t lds = ((size_t)16 * (ntap > 16 ? 2 : 1) * HoWo + 2 * (size_t)d0 + (mnc ? (size_t)d1 : 0)) * sizeof(float);
+    const size_t lds = mf_lds(Ci, k, Ho, Wo, d0, d1, mnc);
     return Co == 16 && ntap <= 32 && (HoWo + 15) / 16 <= MNW && lds <= 150 * 1024;
 }
 
@@ -501,9 +591,9 @@ void launch_bottom_mf(const BottomArgs& a, hipStream_t st) {
     MNB_CHECK(bottom_mf_supported(a.Co, a.Ci, a.k, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr) && a.d1 == 16 * HoWo,
               MNB_EDEVICE, "bottom kernel (MFMA): unsupported shape");
     const int ntt = ntap > 16 ? 2 : 1;
-    size_t lds = ((size_t)16 * ntt * HoWo + 2 * (size_t)a.d0 + (a.gsum_out ? (size_t)a.d1 : 0)) * sizeof(float);
+    size_t lds = mf_lds(a.Ci, a.k, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr);
     BottomArgs b = a;
-    b.box_lds = lds + 2 * (size_t)a.d0 * sizeof(float) <= 80 * 1024;
+    b.box_lds = lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
     if (b.box_lds) lds += 2 * (size_t)a.d0 * sizeof(float);
     if (ntt == 1 && a.k == 4 && a.s == 2)
         launch_mf_tpw<4, 2, 1>(b, lds, st);
