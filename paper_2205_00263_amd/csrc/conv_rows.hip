@@ -214,11 +214,13 @@ __global__ __launch_bounds__(RT) void k_conv_rows(ConvRowsArgs a) {
     extern __shared__ float sm[];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
     float* s_W = sm;                              // [Co][KW]
-    float* s_row = sm + (long)a.Co * a.KW + wave * a.RP;
+    float* s_b = sm + (long)a.Co * a.KW;          // [Co] bias
+    float* s_row = s_b + ((a.Co + 3) & ~3) + wave * a.RP;
     for (int i = t; i < a.Co * a.K; i += RT) {
         const int co = i / a.K;
         s_W[co * a.KW + (i - co * a.K)] = a.Wf[i];
     }
+    for (int i = t; i < a.Co; i += RT) s_b[i] = a.bias[i];
     for (int i = lane; i < a.RP; i += 64) s_row[i] = 0.f;
     __syncthreads();
     const int HoWo = a.Ho * a.Wo, HpWq = a.Hp * a.Wq, HiWi = a.Hi * a.Wi;
@@ -284,14 +286,17 @@ __global__ __launch_bounds__(RT) void k_conv_rows(ConvRowsArgs a) {
                                 for (int j = 0; j < NT; ++j)
                                     acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][m], bv[c][j], acc[m][j], 0, 0, 0);
                     }
-                // D: lane holds co = ct + 16 m + 4 lk + v at position (n0 + j) * 16 + lr
+                // D: lane holds co = ct + 16 m + 4 lk + v at position (n0 + j) * 16 + lr.  The next
+                // row's loads have arrived by now: wait for them before the stores, so that
+                // nothing is outstanding when the next row is staged
+                vmem_drain();
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int co = ct + m * 16 + 4 * lk + v;
                         if (co >= a.Co) continue;
-                        const float b = a.bias[co];
+                        const float b = s_b[co];
 #pragma unroll
                         for (int j = 0; j < NT; ++j) {
                             const int n = (n0 + j) * 16 + lr;
@@ -526,7 +531,7 @@ bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M
     a.RP = (g.Ci * a.Hp * a.Wq + 3) & ~3;
     a.K = g.k * g.k * g.Ci;
     a.KW = a.K + 4;
-    const size_t lds = ((size_t)g.Co * a.KW + 4 * (size_t)a.RP) * sizeof(float);
+    const size_t lds = ((size_t)g.Co * a.KW + ((g.Co + 3) & ~3) + 4 * (size_t)a.RP) * sizeof(float);
     if (lds > ROW_LDS_MAX) return false;
     if (M <= 0) return true;
     const dim3 grid(row_grid(M));
