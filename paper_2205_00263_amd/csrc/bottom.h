@@ -42,7 +42,7 @@ bool bottom_supported(int d1, int d0, int n_weights);
 void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st);
 // MFMA variant for first-layer convolutions into 16 channels with at most 32 taps per channel
 // (launch_bottom dispatches to it)
-bool bottom_mf_supported(int Co, int Ci, int k, int Ho, int Wo, int d0, int d1, bool mnc);
+bool bottom_mf_supported(int Co, int Ci, int k, int s, int Ho, int Wo, int d0, int d1, bool mnc);
 void launch_bottom_mf(const BottomArgs& a, hipStream_t st);
 // instance gradients from the chunk partials (after launch_bottom with adjoint)
 void launch_bottom_reduce(const BottomArgs& a, int n_inst, hipStream_t st);

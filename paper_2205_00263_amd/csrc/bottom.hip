@@ -482,7 +482,7 @@ void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
               MNB_EDEVICE, "bottom kernel: unsupported shape");
     const int nb = a.n_chunk;
     if (nb <= 0) return;
-    if (bottom_mf_supported(a.Co, a.Ci, a.k, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr) &&
+    if (bottom_mf_supported(a.Co, a.Ci, a.k, a.s, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr) &&
         !getenv("MNB_BOTTOM_VALU")) {
         launch_bottom_mf(a, st);
         return;

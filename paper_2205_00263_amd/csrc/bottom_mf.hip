@@ -63,8 +63,11 @@ __device__ __forceinline__ void bsum3(float& x, float& y, float& z, float (*red)
 }
 
 // Taps of the first convolution that reach one input element (at most 3 x 3 with a runtime shape).
-template <int KK, int SS>
-constexpr int nto_taps() { return KK ? ((KK + SS - 1) / SS) * ((KK + SS - 1) / SS) : 9; }
+constexpr int nto_taps(int KK, int SS) { return KK ? ((KK + SS - 1) / SS) * ((KK + SS - 1) / SS) : 9; }
+// Rows per iteration: two for first layers of at most 16 taps with a compile-time shape.
+constexpr int mf_rows(int KK, int NTT) { return (NTT == 1 && KK != 0) ? 2 : 1; }
+// Per-thread index tables in LDS (one input element per thread, 4 taps and 4 adjoint steps).
+constexpr bool mf_tab(bool O1, int KK, int SS, int NTT) { return O1 && nto_taps(KK, SS) == 4 && NTT == 1; }
 
 // KK, SS: kernel size and stride as constants (0: runtime); NTT: 16-tap tiles of the first
 // convolution (1: at most 16 taps, 2: at most 32); SRC1: rows built from the objective
@@ -76,7 +79,7 @@ constexpr int nto_taps() { return KK ? ((KK + SS - 1) / SS) * ((KK + SS - 1) / S
 template <int TPW, int KK, int SS, int NTT, bool SRC1, bool O1>
 __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     static_assert(TPW == 1, "one tile per wavefront");
-    constexpr int RP = (NTT == 1 && KK != 0) ? 2 : 1;   // rows per iteration (registers permitting)
+    constexpr int RP = mf_rows(KK, NTT);   // rows per iteration (registers permitting)
     constexpr int KSM = 4 * NTT;   // 4-tap steps of the adjoint product
     const int k = KK ? KK : a.k;
     const int s = SS ? SS : a.s;
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     float* s_hi = s_lo + d0;                             // [d0]
     float* s_sg = s_x + (RP + 1) * d0 + (a.box_lds ? 2 * d0 : 0);   // [d1] sum of g (MNC only)
     // per thread, row-invariant index tables (NTO == 4, KSM == 4): col2im taps and adjoint gathers
-    constexpr bool TAB = O1 && nto_taps<KK, SS>() == 4 && KSM == 4;
+    constexpr bool TAB = mf_tab(O1, KK, SS, NTT);
     const int tab_off = (int)((s_sg + (a.gsum_out ? d1 : 0)) - reinterpret_cast<float*>(smem4));
     int4* s_tab = reinterpret_cast<int4*>(smem4) + (tab_off + 3) / 4;   // [2][MBT] (TAB)
     __shared__ float red[3 * RP][MNW];
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) b1v[v] = a.b1[4 * lk + v];
     // O1: the owned input element o = t, its tap products in s_T (-1: none) and its box
-    constexpr int NTO = nto_taps<KK, SS>();
+    constexpr int NTO = nto_taps(KK, SS);
     int tix[O1 ? NTO : 1];
     float lo_o = 0.f, hi_o = 0.f;
     int xc_o = 0;   // O1: rows of the chunk with x*_o = hi_o for the owned element
@@ -571,27 +574,38 @@ void launch_mf_tpw(const BottomArgs& a, size_t lds, hipStream_t st) {
 
 }  // namespace
 
-// LDS of the MFMA bottom kernel without the box: relaxation, two rows' tap products and x*,
-// x* counts, g sums (MNC), per-thread index tables
-static size_t mf_lds(int Ci, int k, int Ho, int Wo, int d0, int d1, bool mnc) {
-    const int ntap = Ci * k * k;
-    return (4 * (size_t)d1 + 2 * (size_t)16 * (ntap > 16 ? 2 : 1) * Ho * Wo + 3 * (size_t)d0 + (mnc ? (size_t)d1 : 0) + 4 +
-            2 * 4 * (size_t)MBT) *
+// Compile-time shape (KK, SS) and tap tiles of the instantiation launch_bottom_mf picks.
+static void mf_shape(int Ci, int k, int s, int& KK, int& SS, int& ntt) {
+    ntt = Ci * k * k > 16 ? 2 : 1;
+    KK = SS = 0;
+    if (ntt == 1 && k == 4 && s == 2) KK = 4, SS = 2;
+    if (ntt == 2 && k == 3 && s == 2) KK = 3, SS = 2;
+}
+
+// LDS of the MFMA bottom kernel without the box: relaxation, the rows' tap products and x*,
+// x* counts, g sums (MNC), per-thread index tables (as the kernel lays them out)
+static size_t mf_lds(int Ci, int k, int s, int Ho, int Wo, int d0, int d1, bool mnc) {
+    int KK, SS, ntt;
+    mf_shape(Ci, k, s, KK, SS, ntt);
+    const size_t rp = mf_rows(KK, ntt);
+    const bool tab = mf_tab(d0 <= MBT, KK, SS, ntt);
+    return (4 * (size_t)d1 + rp * 16 * ntt * Ho * Wo + (rp + 1) * d0 + (mnc ? (size_t)d1 : 0) +
+            (tab ? 4 + 2 * 4 * (size_t)MBT : 0)) *
            sizeof(float);
 }
 
-bool bottom_mf_supported(int Co, int Ci, int k, int Ho, int Wo, int d0, int d1, bool mnc) {
+bool bottom_mf_supported(int Co, int Ci, int k, int s, int Ho, int Wo, int d0, int d1, bool mnc) {
     const int HoWo = Ho * Wo, ntap = Ci * k * k;
-    const size_t lds = mf_lds(Ci, k, Ho, Wo, d0, d1, mnc);
+    const size_t lds = mf_lds(Ci, k, s, Ho, Wo, d0, d1, mnc);
     return Co == 16 && ntap <= 32 && (HoWo + 15) / 16 <= MNW && lds <= 150 * 1024;
 }
 
 void launch_bottom_mf(const BottomArgs& a, hipStream_t st) {
     const int HoWo = a.Ho * a.Wo, ntap = a.Ci * a.k * a.k;
-    MNB_CHECK(bottom_mf_supported(a.Co, a.Ci, a.k, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr) && a.d1 == 16 * HoWo,
+    MNB_CHECK(bottom_mf_supported(a.Co, a.Ci, a.k, a.s, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr) && a.d1 == 16 * HoWo,
               MNB_EDEVICE, "bottom kernel (MFMA): unsupported shape");
     const int ntt = ntap > 16 ? 2 : 1;
-    size_t lds = mf_lds(a.Ci, a.k, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr);
+    size_t lds = mf_lds(a.Ci, a.k, a.s, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr);
     BottomArgs b = a;
     b.box_lds = lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
     if (b.box_lds) lds += 2 * (size_t)a.d0 * sizeof(float);
