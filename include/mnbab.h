@@ -216,6 +216,28 @@ int mnb_timer_begin(int kind, int node);
  * summed algorithmic flops and bytes of the timed launches. */
 int mnb_timer_end(int64_t* launches, double* ms, double* flops, double* bytes);
 
+/* ------------------------------------------------------------------ kernel variants */
+/* Not an operation of the method: several kernels compute the same products
+ * (Eq. 2, Eq. 5, Eq. 6 and their adjoints) to FP32 rounding, and the library
+ * picks the fastest for each layer shape.  A set bit forces the more general
+ * variant of one step for all later calls in this process (the mask is
+ * process-wide; set it only between calls, not while another thread is in the
+ * library):
+ *   MNB_VAR_VALU_BOTTOM      fused first layer on the VALU kernel instead of MFMA
+ *   MNB_VAR_NO_TAP_CONVT     transposed convolution of small grids by stride phases
+ *   MNB_VAR_NO_PAIR_CONV     forward convolution with one wavefront per row
+ *   MNB_VAR_NO_ROW_CONV      convolutions through the LDS-staged gather GEMMs
+ *   MNB_VAR_NO_WINDOW        window rows of ReLU layer 1 through the fused kernel
+ *   MNB_VAR_NO_FUSED_BOTTOM  first layer by the generic back-substitution and concretisation
+ * The initial mask comes from the environment variables MNB_BOTTOM_VALU,
+ * MNB_NO_TAP_CONVT, MNB_NO_PAIR_CONV, MNB_NO_ROW_CONV, MNB_NO_WIN_BOTTOM and
+ * MNB_NO_FUSED_BOTTOM (set: bit on).  mnb_set_kernel_variants returns the
+ * previous mask; neither call fails. */
+enum { MNB_VAR_VALU_BOTTOM = 1, MNB_VAR_NO_TAP_CONVT = 2, MNB_VAR_NO_PAIR_CONV = 4, MNB_VAR_NO_ROW_CONV = 8,
+       MNB_VAR_NO_WINDOW = 16, MNB_VAR_NO_FUSED_BOTTOM = 32 };
+int mnb_set_kernel_variants(int mask);
+int mnb_get_kernel_variants(void);
+
 /* ------------------------------------------------------------------ serving */
 /* A verification query for the server: box, spec and MNC sets as in
  * bound_init, plus a per-query wall-clock budget. */

@@ -4,5 +4,6 @@ The compute path is the HIP library libmnbab.so (include/mnbab.h); this
 package is its Python binding.  Importing it does not load the library; the
 first call does, and fails loudly if the library has not been built.
 """
-from .api import KernelTimer, Net, Problem, Server, mnc_to_csr, set_index, use_torch_plumbing  # noqa: F401
+from .api import (VARIANTS, KernelTimer, Net, Problem, Server, get_kernel_variants, mnc_to_csr,  # noqa: F401
+                  set_index, set_kernel_variants, use_torch_plumbing)
 from ._lib import MnbError, lib  # noqa: F401

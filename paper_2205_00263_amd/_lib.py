@@ -80,6 +80,8 @@ _SIGS = {
     "mnb_kernel_conv_forward": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]),
     "mnb_sync": (C.c_int, []),
     "mnb_timer_begin": (C.c_int, [C.c_int, C.c_int]),
+    "mnb_set_kernel_variants": (C.c_int, [C.c_int]),
+    "mnb_get_kernel_variants": (C.c_int, []),
     "mnb_timer_end": (C.c_int, [ip64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mnb_server_cfg_default": (None, [C.POINTER(ServerCfg)]),
     "mnb_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(ServerCfg), C.POINTER(C.c_void_p)]),

@@ -13,7 +13,8 @@ import numpy as np
 from . import _lib
 from ._lib import check, lib
 
-__all__ = ["Net", "Problem", "use_torch_plumbing", "mnc_to_csr", "set_index"]
+__all__ = ["Net", "Problem", "use_torch_plumbing", "mnc_to_csr", "set_index", "set_kernel_variants",
+           "get_kernel_variants", "VARIANTS"]
 
 
 def _f32(a):
@@ -133,6 +134,21 @@ class Net:
     @staticmethod
     def sync():
         check(lib().mnb_sync())
+
+
+# kernel variants (mnb_set_kernel_variants): bits forcing the more general kernel of a step
+VARIANTS = {"valu_bottom": 1, "no_tap_convt": 2, "no_pair_conv": 4, "no_row_conv": 8, "no_window": 16,
+            "no_fused_bottom": 32}
+
+
+def set_kernel_variants(mask):
+    """Force the general kernels selected by `mask` (bits of VARIANTS) for later calls; returns the
+    previous mask.  All variants compute the same bounds to FP32 rounding."""
+    return int(lib().mnb_set_kernel_variants(int(mask)))
+
+
+def get_kernel_variants():
+    return int(lib().mnb_get_kernel_variants())
 
 
 def mnc_to_csr(P, Phat, p):

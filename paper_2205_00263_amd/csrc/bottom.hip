@@ -483,7 +483,7 @@ void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
     const int nb = a.n_chunk;
     if (nb <= 0) return;
     if (bottom_mf_supported(a.Co, a.Ci, a.k, a.s, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr) &&
-        !getenv("MNB_BOTTOM_VALU")) {
+        !(kernel_variants() & MNB_VAR_VALU_BOTTOM)) {
         launch_bottom_mf(a, st);
         return;
     }

@@ -68,6 +68,9 @@ __device__ __forceinline__ float row_constant(const float* c, const float* cpart
 // waits for the stores of the row before.
 __device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Kernel variants forced by mnb_set_kernel_variants (bits MNB_VAR_* of mnbab.h).
+int kernel_variants();
+
 // ---------------------------------------------------------------- descriptors passed to kernels
 // Per-row descriptor of a back-substitution pass: which subproblem (local index
 // into the call's slot list), which parameter set, which instance (subproblem,

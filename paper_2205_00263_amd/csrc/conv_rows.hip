@@ -14,6 +14,7 @@
 //   forward    (k_conv_rows):  D[co][pos] = sum over (ky, kx, ci) of
 //       Wf[co][(ky, kx, ci)] * G_row[ci][s y - p + ky][s x - p + kx] + b[co]
 #include "kernels.h"
+#include "../../include/mnbab.h"
 
 #include <stdlib.h>
 
@@ -425,6 +426,136 @@ __global__ __launch_bounds__(TT) void k_convT_tap(ConvTTapArgs a) {
     }
 }
 
+// Forward convolution with two wavefronts per row (32 output channels): each wavefront of a
+// pair stages half of the row into the pair's LDS buffer and computes 16 of the output
+// channels, so a workgroup of eight wavefronts holds four rows and the CU twice as many
+// wavefronts as with one row per wavefront.  Per row the K-reduction order is that of
+// k_conv_rows (taps, then channel groups).
+__device__ __forceinline__ void block_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int PT = 512;   // threads: 4 pairs of wavefronts
+
+template <int NT, int C4, int PF>   // C4 = Ci / 4; PF: float4 per lane for half a row
+__global__ __launch_bounds__(PT, 4) void k_conv_pair(ConvRowsArgs a) {
+    constexpr int NP = PT / 128;
+    extern __shared__ float sm[];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, pair = wave >> 1, half = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    float* s_W = sm;                              // [Co][KW]
+    float* s_b = sm + (long)a.Co * a.KW;          // [Co] bias
+    float* s_row = s_b + ((a.Co + 3) & ~3) + pair * a.RP;
+    for (int i = t; i < a.Co * a.K; i += PT) {
+        const int co = i / a.K;
+        s_W[co * a.KW + (i - co * a.K)] = a.Wf[i];
+    }
+    for (int i = t; i < a.Co; i += PT) s_b[i] = a.bias[i];
+    for (int i = lane + 64 * half; i < a.RP; i += 128) s_row[i] = 0.f;
+    const int HoWo = a.Ho * a.Wo, HpWq = a.Hp * a.Wq, HiWi = a.Hi * a.Wi;
+    const int rowG = a.Ci * HiWi;
+    const long ldC = (long)a.Co * HoWo;
+    const int ntile = (HoWo + 15) >> 4;
+    const bool dense = a.p == 0 && a.Hp == a.Hi && a.Wq == a.Wi;   // padded layout == row layout
+    const int n4 = rowG >> 2, n4h = (n4 + 1) >> 1;
+    const int q0 = half * n4h, q1 = min(n4, q0 + n4h);              // this wavefront's float4 range
+    const long stride = (long)gridDim.x * NP;
+    const long rb = (long)blockIdx.x * NP;
+    // iterations of the workgroup (every wavefront takes part in every barrier)
+    const long niter = a.M > rb ? (a.M - rb + stride - 1) / stride : 0;
+    const long r0 = rb + pair;
+    f4 v[PF];
+    auto fetch = [&](long r) {
+        const f4* s4 = reinterpret_cast<const f4*>(a.G + (r < a.M ? r : 0) * rowG);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = q0 + lane + 64 * u;
+            v[u] = (r < a.M && i < q1) ? s4[i] : f4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    fetch(r0);
+    __syncthreads();
+    for (long it = 0; it < niter; ++it) {
+        const long r = r0 + it * stride;
+        // stage this wavefront's half of the row
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = q0 + lane + 64 * u;
+            if (i < q1) {
+                if (dense) {
+                    *reinterpret_cast<f4*>(s_row + 4 * i) = v[u];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int e = 4 * i + q, c = e / HiWi, rem = e - c * HiWi, y = rem / a.Wi, x = rem - y * a.Wi;
+                        s_row[c * HpWq + (y + a.p) * a.Wq + x + a.p] = v[u][q];
+                    }
+                }
+            }
+        }
+        block_lds_sync();   // the pair's row is complete
+        fetch(r + stride);
+        if (r < a.M) {
+            float* dst = a.C + r * ldC;
+            const int co_w = 16 * half + lr;   // A operand row: output channel
+            const float* wrow = s_W + (long)co_w * a.KW + lk;   // + 4 ks (K ordered (ky, kx, ci))
+            const float* rl = s_row + lk * HpWq;
+            for (int n0 = 0; n0 < ntile; n0 += NT) {
+                int pb[NT];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    int n = (n0 + j) * 16 + lr;
+                    n = n < HoWo ? n : HoWo - 1;
+                    const int y = n / a.Wo, x = n - y * a.Wo;
+                    pb[j] = a.s * y * a.Wq + a.s * x;
+                }
+                f4 acc[NT];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int ky = 0; ky < a.k; ++ky)
+                    for (int kx = 0; kx < a.k; ++kx) {
+                        const int kb = (ky * a.k + kx) * a.Ci;
+                        const float* rt = rl + ky * a.Wq + kx;
+                        float av[C4], bv[C4][NT];
+#pragma unroll
+                        for (int c = 0; c < C4; ++c) {
+                            av[c] = wrow[kb + 4 * c];
+#pragma unroll
+                            for (int j = 0; j < NT; ++j) bv[c][j] = rt[4 * c * HpWq + pb[j]];
+                        }
+#pragma unroll
+                        for (int c = 0; c < C4; ++c)
+#pragma unroll
+                            for (int j = 0; j < NT; ++j)
+                                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c][j], acc[j], 0, 0, 0);
+                    }
+                // D: lane holds co = 16 half + 4 lk + v at position (n0 + j) * 16 + lr; the next
+                // row's loads have arrived by now: wait for them before the stores
+                vmem_drain();
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    const int co = 16 * half + 4 * lk + vv;
+                    const float b = s_b[co];
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        const int n = (n0 + j) * 16 + lr;
+                        if (n < HoWo) {
+                            float* q = dst + (long)co * HoWo + n;
+                            const float val = acc[j][vv] + b;
+                            *q = a.acc ? *q + val : val;
+                        }
+                    }
+                }
+            }
+        } else {
+            vmem_drain();
+        }
+        block_lds_sync();   // both wavefronts are done with the row before the next is staged
+    }
+}
+
 int row_grid(long M) {
     const long nb = (M + 3) / 4;
     return (int)(nb < 2048 ? nb : 2048);
@@ -435,7 +566,7 @@ int row_grid(long M) {
 // Tap-GEMM form of the transposed convolution for small input grids; false when the shape
 // does not fit it.
 static bool launch_convT_tap(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st) {
-    static const bool off = getenv("MNB_NO_TAP_CONVT") != nullptr;
+    const bool off = (kernel_variants() & (MNB_VAR_NO_TAP_CONVT | MNB_VAR_NO_ROW_CONV)) != 0;
     const int HoWo = g.Ho * g.Wo, HiWi = g.Hi * g.Wi;
     if (off || g.s != 2 || g.k > 4 || g.Co != 32 || HoWo > 32 || HiWi > 192 || g.Ci < 2) return false;
     ConvTTapArgs a{};
@@ -461,7 +592,7 @@ static bool launch_convT_tap(const ConvGeom& g, const float* A, float* C, int M,
 bool launch_conv_backsub_rows(const ConvGeom& g, const float* A, float* C, int M, bool accumulate,
                               hipStream_t st) {
     if (launch_convT_tap(g, A, C, M, accumulate, st)) return true;
-    static const bool off = getenv("MNB_NO_ROW_CONV") != nullptr;
+    const bool off = (kernel_variants() & MNB_VAR_NO_ROW_CONV) != 0;
     if (off || g.Ci % 16 != 0 || (g.Co != 16 && g.Co != 32 && g.Co != 64) || g.n_phase > 4) return false;
     const int rowA = g.Co * g.Ho * g.Wo;
     if (rowA % 4 != 0 || rowA > 4096 || ((uintptr_t)A & 15) != 0) return false;
@@ -518,7 +649,7 @@ bool launch_conv_backsub_rows(const ConvGeom& g, const float* A, float* C, int M
 
 bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
                               hipStream_t st) {
-    static const bool off = getenv("MNB_NO_ROW_CONV") != nullptr;
+    const bool off = (kernel_variants() & MNB_VAR_NO_ROW_CONV) != 0;
     if (off || g.Co % 16 != 0 || (g.Ci != 16 && g.Ci != 32 && g.Ci != 64)) return false;
     const int rowG = g.Ci * g.Hi * g.Wi;
     if (rowG % 4 != 0 || rowG > 4096 || ((uintptr_t)G & 15) != 0) return false;
@@ -534,6 +665,26 @@ bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M
     const size_t lds = ((size_t)g.Co * a.KW + ((g.Co + 3) & ~3) + 4 * (size_t)a.RP) * sizeof(float);
     if (lds > ROW_LDS_MAX) return false;
     if (M <= 0) return true;
+    const bool no_pair = (kernel_variants() & MNB_VAR_NO_PAIR_CONV) != 0;
+    if (!no_pair && g.Co == 32 && (rowG / 4 + 1) / 2 <= 64 * 8) {
+        // two wavefronts per row; half a row is at most 8 float4 per lane
+        const long nb = (M + 3) / 4;
+        const dim3 grid2((int)(nb < 512 ? nb : 512));
+        const int ntile = (g.Ho * g.Wo + 15) / 16;
+        const int nt = ntile >= 2 ? 2 : 1;
+        const int c4 = g.Ci / 4;
+        const int pfn = ((rowG / 4 + 1) / 2 + 63) / 64;   // float4 per lane for half a row
+#define MNB_CP_PF(NT_, C4_)                                                                        \
+    if (pfn <= 4) hipLaunchKernelGGL((k_conv_pair<NT_, C4_, 4>), grid2, dim3(PT), lds, st, a);      \
+    else if (pfn <= 6) hipLaunchKernelGGL((k_conv_pair<NT_, C4_, 6>), grid2, dim3(PT), lds, st, a); \
+    else hipLaunchKernelGGL((k_conv_pair<NT_, C4_, 8>), grid2, dim3(PT), lds, st, a)
+        if (c4 == 4) { if (nt == 2) { MNB_CP_PF(2, 4); } else { MNB_CP_PF(1, 4); } }
+        else if (c4 == 8) { if (nt == 2) { MNB_CP_PF(2, 8); } else { MNB_CP_PF(1, 8); } }
+        else { if (nt == 2) { MNB_CP_PF(2, 16); } else { MNB_CP_PF(1, 16); } }
+#undef MNB_CP_PF
+        MNB_HIP(hipGetLastError());
+        return true;
+    }
     const dim3 grid(row_grid(M));
     const int ntile = (g.Ho * g.Wo + 15) / 16;
     const int nt = ntile >= 4 ? 4 : ntile >= 2 ? 2 : 1;

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <numeric>
 #include <set>
 
@@ -147,6 +148,27 @@ extern "C" int mnb_timer_begin(int kind, int node) {
     g_timer.running = true;
     return MNB_OK;
 }
+
+namespace {
+int initial_variants() {
+    int m = 0;
+    if (getenv("MNB_BOTTOM_VALU")) m |= MNB_VAR_VALU_BOTTOM;
+    if (getenv("MNB_NO_TAP_CONVT")) m |= MNB_VAR_NO_TAP_CONVT;
+    if (getenv("MNB_NO_PAIR_CONV")) m |= MNB_VAR_NO_PAIR_CONV;
+    if (getenv("MNB_NO_ROW_CONV")) m |= MNB_VAR_NO_ROW_CONV;
+    if (getenv("MNB_NO_WIN_BOTTOM")) m |= MNB_VAR_NO_WINDOW;
+    if (getenv("MNB_NO_FUSED_BOTTOM")) m |= MNB_VAR_NO_FUSED_BOTTOM;
+    return m;
+}
+std::atomic<int> g_variants{initial_variants()};
+}  // namespace
+
+namespace mnb {
+int kernel_variants() { return g_variants.load(std::memory_order_relaxed); }
+}  // namespace mnb
+
+extern "C" int mnb_set_kernel_variants(int mask) { return g_variants.exchange(mask); }
+extern "C" int mnb_get_kernel_variants(void) { return g_variants.load(); }
 
 extern "C" int mnb_timer_end(int64_t* launches, double* ms, double* flops, double* bytes) {
     API_BEGIN
@@ -362,12 +384,10 @@ extern "C" int mnb_net_create(const mnb_layer* L, int n, mnb_net** out) {
             const NetNode& a1 = net->nodes[r0.src];
             net->bottom_ok = a1.kind == MNB_CONV && a1.src == 0 &&
                              bottom_supported(r0.size, net->d0, a1.C * net->nodes[0].C * a1.k * a1.k);
-            if (getenv("MNB_NO_FUSED_BOTTOM")) net->bottom_ok = false;
             if (net->bottom_ok && net->relus.size() > 1) {
                 const NetNode& on = net->nodes[net->nodes[net->relus[1]].src];
                 net->win_ok = on.kind == MNB_CONV && on.src == net->relus[0] &&
-                              win_supported(a1.C, net->nodes[0].C, a1.k, a1.stride, on.k, on.C, r0.size, net->d0) &&
-                              !getenv("MNB_NO_WIN_BOTTOM");
+                              win_supported(a1.C, net->nodes[0].C, a1.k, a1.stride, on.k, on.C, r0.size, net->d0);
             }
         }
         sync();
@@ -1011,7 +1031,7 @@ struct Evaluator {
         gamma_projections(cx, ch, ws, "gproj");
         BufPool pool = make_pool(M, cx.ckpt_stride > 1 ? 6 : 3);
         const int r0n = net->relus[0];
-        const bool fused = net->bottom_ok && ch.obj_layer != 0;
+        const bool fused = net->bottom_ok && ch.obj_layer != 0 && !(kernel_variants() & MNB_VAR_NO_FUSED_BOTTOM);
         float* g_bottom = nullptr;
         if (fused) {
             // back-substitute down to the output of ReLU layer 0 (or build the rows there) and
@@ -1072,7 +1092,7 @@ struct Evaluator {
                     ba.gsum_out = ws.get<float>("gs_out0", (size_t)n_inst * net->max_width);
                 }
             }
-            if (src1 && net->win_ok && !pb->has_mnc && !keep_ap) {
+            if (src1 && net->win_ok && !pb->has_mnc && !keep_ap && !(kernel_variants() & MNB_VAR_NO_WINDOW)) {
                 // window-sparse rows: one workgroup per (instance, window position)
                 const NetNode& on = net->nodes[net->nodes[net->relus[1]].src];
                 const int n_inst = (int)ch.inst.size();

@@ -68,3 +68,23 @@ def sampled_min_sub(net, wl, S, n=20000, seed=0):
         return np.full(np.asarray(wl.C).shape[0], np.inf)
     f = vals[-1][ok] @ np.asarray(wl.C, np.float64).T + wl.c0
     return f.min(0)
+
+
+def make_subproblems(P, pb, rid, net_o, q, root, splits):
+    """Create subproblems by chained branch_split on both sides; returns (gpu ids, oracle subproblems)."""
+    ids, subs = [], []
+    for sp in splits:
+        gid, osub = rid, root
+        chain = []
+        for (m, j, sgn) in sp:
+            ch = pb.branch_split([gid], [m], [j])
+            pos, neg = obab.branch_split(net_o, osub, m, j)
+            keep = 0 if sgn > 0 else 1
+            chain.append(int(ch[1 - keep]))
+            gid = int(ch[keep])
+            osub = pos if sgn > 0 else neg
+        if chain:
+            pb.release(chain)
+        ids.append(gid)
+        subs.append(osub)
+    return np.array(ids), subs

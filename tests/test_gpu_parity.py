@@ -8,7 +8,7 @@ from oracle import bab as obab
 from oracle import net as onet
 from oracle import optimize as oo
 
-from _common import assert_parity, oracle_query, root_unstable, sampled_min, sampled_min_sub
+from _common import assert_parity, make_subproblems, oracle_query, root_unstable, sampled_min, sampled_min_sub
 
 pytestmark = pytest.mark.gpu
 
@@ -133,26 +133,6 @@ def test_bound_init_matches_oracle(cfg, scale):
 
 
 # --------------------------------------------------------------------------- splits, T = 0 (config 1)
-def _make_subproblems(P, pb, rid, net_o, q, root, splits):
-    """Create subproblems by chained branch_split on both sides; returns (gpu ids, oracle subproblems)."""
-    ids, subs = [], []
-    for sp in splits:
-        gid, osub = rid, root
-        chain = []
-        for (m, j, sgn) in sp:
-            ch = pb.branch_split([gid], [m], [j])
-            pos, neg = obab.branch_split(net_o, osub, m, j)
-            keep = 0 if sgn > 0 else 1
-            chain.append(int(ch[1 - keep]))
-            gid = int(ch[keep])
-            osub = pos if sgn > 0 else neg
-        if chain:
-            pb.release(chain)
-        ids.append(gid)
-        subs.append(osub)
-    return np.array(ids), subs
-
-
 @pytest.mark.parametrize("scale,n_sub", [("small", 16), ("full", 64)])
 def test_config1_splits_T0(scale, n_sub):
     P = _P()
@@ -163,7 +143,7 @@ def test_config1_splits_T0(scale, n_sub):
     pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=4 * n_sub + 8)
     rid, lb0, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
     splits = W.make_split_sets(root_unstable(net_o, root), n_sub, 1, 4, seed=3001)
-    ids, subs = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+    ids, subs = make_subproblems(P, pb, rid, net_o, q, root, splits)
     lb, ub = pb.bound_optimize(ids, steps=0)
     ref = np.array([oo.bound_optimize(q, s, steps=0).lb for s in subs])
     assert_parity(lb, ref, "T=0 lb")
@@ -240,7 +220,7 @@ def test_optimize_matches_oracle(cfg, n_sub, steps):
     pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=4 * n_sub + 8)
     rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
     splits = W.make_split_sets(root_unstable(net_o, root), n_sub, 1, 3, seed=77 + cfg)
-    ids, subs = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+    ids, subs = make_subproblems(P, pb, rid, net_o, q, root, splits)
     lb, ub = pb.bound_optimize(ids, steps=steps, lr=0.1)
     ref = np.array([oo.bound_optimize(q, s, steps=steps, lr=0.1).lb for s in subs])
     print("gpu", lb[:2], "oracle", ref[:2], flush=True)
@@ -269,7 +249,7 @@ def test_checkpointed_adjoint_is_bitwise_identical(cfg, stride):
         net = P.Net(wl.nodes)
         pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=64)
         rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
-        ids, _ = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+        ids, _ = make_subproblems(P, pb, rid, net_o, q, root, splits)
         lb, ub = pb.bound_optimize(ids, steps=4, ckpt_stride=st)
         alphas = np.stack([pb.get_params(i, 0)[0] for i in ids])
         out.append((lb, ub, alphas))
@@ -290,7 +270,7 @@ def test_chunked_passes_are_bitwise_identical():
         net = P.Net(wl.nodes)
         pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=128)
         rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
-        ids, _ = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+        ids, _ = make_subproblems(P, pb, rid, net_o, q, root, splits)
         out.append(pb.bound_optimize(ids, steps=3, mem_budget=budget))
     np.testing.assert_array_equal(out[0][0], out[1][0])
     np.testing.assert_array_equal(out[0][1], out[1][1])
@@ -308,7 +288,7 @@ def test_batch_composition_does_not_change_results():
     for mode in ("alone", "batch"):
         pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=128)
         rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
-        ids, _ = _make_subproblems(P, pb, rid, net_o, q, root, splits)
+        ids, _ = make_subproblems(P, pb, rid, net_o, q, root, splits)
         if mode == "alone":
             res[mode] = np.stack([pb.bound_optimize([i], steps=3)[0][0] for i in ids])
         else:
