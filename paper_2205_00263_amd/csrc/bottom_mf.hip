@@ -27,6 +27,7 @@ namespace {
 
 constexpr int MBT = 1024;        // threads (16 wavefronts, one 16-position tile each)
 constexpr int MNW = MBT / 64;
+static_assert(BOTTOM_CHUNK_ROWS <= 2 * MNW, "the prologue reads two rows per wavefront");
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void lds_sync() {
@@ -106,73 +107,14 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     __shared__ float s_crow[BOTTOM_CHUNK_ROWS];
     __shared__ float s_old[BOTTOM_CHUNK_ROWS];
 
-    const int ib = a.cinst[blockIdx.x];
-    const InstDesc in = a.inst[ib];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
-    // the chunk's rows (at most BOTTOM_CHUNK_ROWS by construction of the chunks): descriptor,
-    // constant and previous bound of each, loaded once with all loads in flight together
+    // The prologue's loads are issued in four dependent levels, each level's loads in flight
+    // together: chunk -> instance -> (the chunk's rows, query, relaxation inputs, first
+    // coefficients) -> (box, the rows' previous bounds).  Only one workgroup fits on a CU, so
+    // nothing else hides this latency.
+    const int ib = a.cinst[blockIdx.x];
     const int cr0 = a.cr0[blockIdx.x];
     const int nr = min(a.cr1[blockIdx.x] - cr0, BOTTOM_CHUNK_ROWS);
-    for (int ri = wave; ri < nr; ri += MNW) {
-        const int r = cr0 + ri;
-        float cr = SRC1 ? 0.f : row_constant(a.c, a.cpart, a.ldcp, a.ncp, r);
-        if (lane == 0) {
-            const RowDesc rd = a.rows[r];
-            if (SRC1) cr = (float)rd.sign * a.bias_obj[rd.j];
-            float old = 0.f;
-            if (a.mode == 0) {
-                // each (slot, neuron) of the objective layer has exactly one row in a pass
-                const long e = (long)in.slot * a.ld_state + a.state_off_obj + rd.j;
-                old = rd.sign > 0 ? a.lw[e] : a.uw[e];
-            } else if (a.mode == 1) {
-                old = a.best[r];
-            }
-            s_rd[ri] = rd;
-            s_crow[ri] = cr;
-            s_old[ri] = old;
-        }
-    }
-    const float* glo = a.lo + (long)a.qid[in.slot] * d0;
-    const float* ghi = a.hi + (long)a.qid[in.slot] * d0;
-    float b1v[4];   // bias of the owned channels 4 lk + v
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b1v[v] = a.b1[4 * lk + v];
-    // O1: the owned input element o = t, its tap products in s_T (-1: none) and its box
-    constexpr int NTO = nto_taps(KK, SS);
-    int tix[O1 ? NTO : 1];
-    float lo_o = 0.f, hi_o = 0.f;
-    int xc_o = 0;   // O1: rows of the chunk with x*_o = hi_o for the owned element
-    if constexpr (O1) {
-        const bool ov = t < d0;
-        const int o = ov ? t : 0;
-        const int ci = o / HiWi, qq = o - ci * HiWi;
-        const int Yq = qq / a.Wi;
-        const int Yp = Yq + a.p, Xp = qq - Yq * a.Wi + a.p;
-        const int nty = (k + s - 1) / s;
-#pragma unroll
-        for (int q = 0; q < NTO; ++q) {
-            const int ty = q / (KK ? (KK + SS - 1) / SS : 3), tx = q - ty * (KK ? (KK + SS - 1) / SS : 3);
-            const int ky = Yp % s + ty * s, kx = Xp % s + tx * s;
-            const int y = (Yp - ky) / s, x = (Xp - kx) / s;
-            const bool tv = ov && ty < nty && tx < nty && ky < k && kx < k && Yp >= ky && Xp >= kx && y < a.Ho && x < a.Wo;
-            tix[q] = tv ? ((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x : -1;
-        }
-        if (ov) {
-            lo_o = glo[o];
-            hi_o = ghi[o];
-        }
-        if constexpr (TAB) s_tab[t] = make_int4(tix[0], tix[NTO > 1 ? 1 : 0], tix[NTO > 2 ? 2 : 0], tix[NTO > 3 ? 3 : 0]);
-    }
-    for (int o = t; o < d0; o += MBT) {
-        if constexpr (!O1) s_xc[o] = 0;
-        if (a.box_lds) {
-            s_lo[o] = glo[o];
-            s_hi[o] = ghi[o];
-        }
-    }
-    if (a.gsum_out)
-        for (int j = t; j < d1; j += MBT) s_sg[j] = 0.f;
-
     // first-layer weights as MFMA operands held for the whole chunk:
     // transposed product B[k = co][n = tap] with co = 4 lk + ks, tap = 16 nt + lr;
     // adjoint product A[m = co][k = tap] with co = lr, tap = 4 ks + lk
@@ -189,41 +131,170 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         const int tap = 4 * ks + lk;
         aW[ks] = tap < ntap ? a.W1[lr * ntap + tap] : 0.f;
     }
+    float b1v[4];   // bias of the owned channels 4 lk + v
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b1v[v] = a.b1[4 * lk + v];
+    const InstDesc in = a.inst[ib];
 
-    // owned neurons: tile mt = wave, neuron (co = 4 lk + v, pos = 16 mt + lr); their relaxation
-    // of ReLU layer 0 (split first, then stable, then unstable) goes to LDS: slope where
-    // a' >= 0, slope and intercept where a' < 0 (the intercept is > 0 exactly when unstable),
-    // S beta + (Phat^T gamma)
+    // owned neurons: tile mt = wave, neuron (co = 4 lk + v, pos = 16 mt + lr)
     const int mt = wave;
     const int pos = mt * 16 + lr;
     const bool pv = pos < HoWo;
-    int gidx[KSM];   // adjoint B operand: s_x index of (pos, tap = 4 ks + lk), -1: none
-    {
-        const long so0 = (long)in.slot * a.ld_state;
-        const long po0 = ((long)in.slot * a.n_sets + in.set) * a.ld_param;
+    // the chunk's rows (at most BOTTOM_CHUNK_ROWS = 2 MNW by construction of the chunks):
+    // descriptor, constant and the first 64 constant partials of rows wave and wave + MNW
+    // (wave-uniform row index, so the descriptors come through scalar loads)
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    RowDesc rdq[2];
+    float crq[2] = {0.f, 0.f}, cpq[2] = {0.f, 0.f};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int j = (4 * lk + v) * HoWo + pos;
-            float dp = 0.f, dn = 0.f, bn = 0.f, ad = 0.f;
-            if (pv) {
-                const float l = a.l[so0 + j], uu = a.u[so0 + j];
-                const int sj = (int)a.S[so0 + j];
-                if (sj == -1) {
-                    dp = dn = 1.f;
-                } else if (sj == 1) {
-                } else if (l >= 0.f) {
-                    dp = dn = 1.f;
-                } else if (uu <= 0.f) {
-                } else {
-                    dp = a.alpha[po0 + j];
-                    const float w = uu - l;
-                    dn = uu / w;
-                    bn = -(uu * l) / w;
-                }
-                ad = (sj != 0 ? (float)sj * a.beta[po0 + j] : 0.f) + (a.vhat ? a.vhat[(long)ib * d1 + j] : 0.f);
-                s_rx[j] = make_float4(dp, dn, bn, ad);
+    for (int q = 0; q < 2; ++q) {
+        const int ri = wv + q * MNW;
+        if (ri < nr) {
+            const long r = cr0 + ri;
+            rdq[q] = a.rows[r];
+            if constexpr (!SRC1) {
+                crq[q] = a.c[r];
+                if (lane < a.ncp) cpq[q] = a.cpart[r * a.ldcp + lane];
             }
         }
+    }
+    const int qv = a.qid[in.slot];
+    // relaxation inputs of the owned neurons (all loaded, used by case below)
+    const long so0 = (long)in.slot * a.ld_state;
+    const long po0 = ((long)in.slot * a.n_sets + in.set) * a.ld_param;
+    float rl[4], ru[4], ral[4], rbe[4], rvh[4];
+    int rs[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int j = (4 * lk + v) * HoWo + pos;
+        rl[v] = ru[v] = ral[v] = rbe[v] = rvh[v] = 0.f;
+        rs[v] = 0;
+        if (pv) {
+            rl[v] = a.l[so0 + j];
+            ru[v] = a.u[so0 + j];
+            rs[v] = (int)a.S[so0 + j];
+            ral[v] = a.alpha[po0 + j];
+            rbe[v] = a.beta[po0 + j];
+            if (a.vhat) rvh[v] = a.vhat[(long)ib * d1 + j];
+        }
+    }
+    // coefficients of the next rows, loaded one iteration ahead (the first ones before the
+    // barrier that ends the prologue, which waits for them)
+    float nx[SRC1 ? 1 : RP][4];
+    if constexpr (!SRC1) {
+#pragma unroll
+        for (int b = 0; b < RP; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                nx[b][v] = (pv && b < nr) ? a.A[(long)(cr0 + b) * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
+    }
+    // box: O1, the owned input element o = t; otherwise staged in LDS (box_lds)
+    const float* glo = a.lo + (long)qv * d0;
+    const float* ghi = a.hi + (long)qv * d0;
+    float lo_o = 0.f, hi_o = 0.f;
+    int xc_o = 0;   // O1: rows of the chunk with x*_o = hi_o for the owned element
+    if constexpr (O1) {
+        if (t < d0) {
+            lo_o = glo[t];
+            hi_o = ghi[t];
+        }
+    } else {
+        for (int o = t; o < d0; o += MBT) {
+            s_xc[o] = 0;
+            if (a.box_lds) {
+                s_lo[o] = glo[o];
+                s_hi[o] = ghi[o];
+            }
+        }
+    }
+    // previous bound of each row: of its objective neuron (each (slot, neuron) of the objective
+    // layer has exactly one row in a pass), or the best bound so far of a spec row
+    float oldq[2] = {0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int ri = wv + q * MNW;
+        if (ri < nr) {
+            const RowDesc rd = rdq[q];
+            if (a.mode == 0) {
+                const long e = so0 + a.state_off_obj + rd.j;
+                const float* src = rd.sign > 0 ? a.lw : a.uw;
+                oldq[q] = src[e];
+            } else if (a.mode == 1) {
+                oldq[q] = a.best[cr0 + ri];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int ri = wv + q * MNW;
+        if (ri < nr) {
+            const RowDesc rd = rdq[q];
+            float cr;
+            if constexpr (SRC1) {
+                cr = (float)rd.sign * a.bias_obj[rd.j];
+            } else {
+                // constant partials beyond the first 64 (rare), then the wave sum in lane order
+                float sp = cpq[q];
+                for (int kq = lane + 64; kq < a.ncp; kq += 64) sp += a.cpart[(long)(cr0 + ri) * a.ldcp + kq];
+                cr = crq[q] + wave_sum(sp);
+            }
+            if (lane == 0) {
+                s_rd[ri] = rd;
+                s_crow[ri] = cr;
+                s_old[ri] = oldq[q];
+            }
+        }
+    }
+    if (a.gsum_out)
+        for (int j = t; j < d1; j += MBT) s_sg[j] = 0.f;
+
+    // relaxation of ReLU layer 0 on the owned neurons (split first, then stable, then unstable)
+    // to LDS: slope where a' >= 0, slope and intercept where a' < 0 (the intercept is > 0
+    // exactly when unstable), S beta + (Phat^T gamma)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        if (!pv) continue;
+        const float l = rl[v], uu = ru[v];
+        const int sj = rs[v];
+        float dp = 0.f, dn = 0.f, bn = 0.f;
+        if (sj == -1) {
+            dp = dn = 1.f;
+        } else if (sj == 1) {
+        } else if (l >= 0.f) {
+            dp = dn = 1.f;
+        } else if (uu <= 0.f) {
+        } else {
+            dp = ral[v];
+            const float w = uu - l;
+            dn = uu / w;
+            bn = -(uu * l) / w;
+        }
+        const float ad = (sj != 0 ? (float)sj * rbe[v] : 0.f) + rvh[v];
+        s_rx[(4 * lk + v) * HoWo + pos] = make_float4(dp, dn, bn, ad);
+    }
+    // O1: col2im taps of the owned input element (s_T offsets, -1: none)
+    constexpr int NTO = nto_taps(KK, SS);
+    int tix[O1 ? NTO : 1];
+    if constexpr (O1) {
+        const bool ov = t < d0;
+        const int o = ov ? t : 0;
+        const int ci = o / HiWi, qq = o - ci * HiWi;
+        const int Yq = qq / a.Wi;
+        const int Yp = Yq + a.p, Xp = qq - Yq * a.Wi + a.p;
+        const int nty = (k + s - 1) / s;
+#pragma unroll
+        for (int q = 0; q < NTO; ++q) {
+            const int ty = q / (KK ? (KK + SS - 1) / SS : 3), tx = q - ty * (KK ? (KK + SS - 1) / SS : 3);
+            const int ky = Yp % s + ty * s, kx = Xp % s + tx * s;
+            const int y = (Yp - ky) / s, x = (Xp - kx) / s;
+            const bool tv = ov && ty < nty && tx < nty && ky < k && kx < k && Yp >= ky && Xp >= kx && y < a.Ho && x < a.Wo;
+            tix[q] = tv ? ((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x : -1;
+        }
+        if constexpr (TAB) s_tab[t] = make_int4(tix[0], tix[NTO > 1 ? 1 : 0], tix[NTO > 2 ? 2 : 0], tix[NTO > 3 ? 3 : 0]);
+    }
+    // adjoint B operand: s_x index of (pos, tap = 4 ks + lk), -1: none
+    int gidx[KSM];
+    {
         const int y = pv ? pos / a.Wo : 0, x = pv ? pos - y * a.Wo : 0;
 #pragma unroll
         for (int ks = 0; ks < KSM; ++ks) {
@@ -244,16 +315,6 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     float da[4] = {0.f, 0.f, 0.f, 0.f};
     const float* vrow = a.v ? a.v + (long)ib * d1 : nullptr;
     const float gpv = a.gp ? a.gp[ib] : 0.f;
-    // coefficients of the next rows, loaded one iteration ahead (the first ones before the
-    // barrier, which waits for them)
-    float nx[SRC1 ? 1 : RP][4];
-    if constexpr (!SRC1) {
-#pragma unroll
-        for (int b = 0; b < RP; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                nx[b][v] = (pv && b < nr) ? a.A[(long)(cr0 + b) * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
-    }
     __syncthreads();
 
     for (int ri = 0; ri < nr; ri += RP) {
@@ -607,7 +668,8 @@ void launch_bottom_mf(const BottomArgs& a, hipStream_t st) {
     const int ntt = ntap > 16 ? 2 : 1;
     size_t lds = mf_lds(a.Ci, a.k, a.s, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr);
     BottomArgs b = a;
-    b.box_lds = lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
+    // with one input element per thread (d0 <= MBT) the box is held in registers instead
+    b.box_lds = a.d0 > MBT && lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
     if (b.box_lds) lds += 2 * (size_t)a.d0 * sizeof(float);
     if (ntt == 1 && a.k == 4 && a.s == 2)
         launch_mf_tpw<4, 2, 1>(b, lds, st);

@@ -179,51 +179,35 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
     const int Yb = a.os * wy - a.op, Xb = a.os * wx - a.op;   // window origin on ReLU layer 0
     const int Ib = a.s * Yb - a.p, Jb = a.s * Xb - a.p;       // input-window origin
     const int HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
+    // The prologue's loads are issued in dependent levels, each level's loads in flight
+    // together: instance and window range -> (entries, relaxation inputs, box, weights) ->
+    // the entries' previous bounds.
     const int* wptr = a.win_ptr + (long)ib * (nwin + 1);
     const int e0 = wptr[w];
     const int nrows = min(wptr[w + 1] - e0, 64);
-    if (t < nrows) {
-        // the objective neuron's bound before this evaluation (mode 0); each (slot, neuron) of
-        // the objective layer has exactly one row in a pass
-        WinEnt e = a.win_ent[e0 + t];
-        if (a.mode == 0) {
-            const long o = (long)in.slot * a.ld_state + a.state_off_obj + e.j;
-            e.old = e.r >= 0 ? a.lw[o] : a.uw[o];
-        }
-        s_ent[t] = e;
-    }
+    WinEnt ent{};
+    if (t < nrows) ent = a.win_ent[e0 + t];
 
     // ---- owned window entries (c1 = 4 lk + v, pe = lr): relaxation of ReLU layer 0 and bias
     const int dy = lr / a.ok, dx = lr - dy * a.ok;
     const int Y = Yb + dy, X = Xb + dx;
     const bool pin = lr < P && Y >= 0 && Y < a.Ho && X >= 0 && X < a.Wo;
-    float rdp[4], rdn[4], rbn[4], b1v[4];
     const long so0 = (long)in.slot * a.ld_state + Y * a.Wo + X;
     const long po0 = ((long)in.slot * a.n_sets + in.set) * a.ld_param + Y * a.Wo + X;
+    float rl[4], ru[4], ral[4], b1v[4];
+    int rs[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int c1 = 4 * lk + v;
-        float dp = 0.f, dn = 0.f, bn = 0.f;
+        rl[v] = ru[v] = ral[v] = 0.f;
+        rs[v] = 0;
         if (pin) {
             const long so = so0 + (long)c1 * HoWo;
-            const float l = a.l[so], u = a.u[so];
-            const int sj = (int)a.S[so];
-            if (sj == -1) {
-                dp = dn = 1.f;
-            } else if (sj == 1) {
-            } else if (l >= 0.f) {
-                dp = dn = 1.f;
-            } else if (u <= 0.f) {
-            } else {
-                dp = a.alpha[po0 + (long)c1 * HoWo];
-                const float wd = u - l;
-                dn = u / wd;
-                bn = -(u * l) / wd;
-            }
+            rl[v] = a.l[so];
+            ru[v] = a.u[so];
+            rs[v] = (int)a.S[so];
+            ral[v] = a.alpha[po0 + (long)c1 * HoWo];
         }
-        rdp[v] = dp;
-        rdn[v] = dn;
-        rbn[v] = bn;
         b1v[v] = a.b1[c1];
     }
     // ---- owned input-window pixels q = lane + 64 i: (ciq, Ib + qy, Jb + qx), box and A_s
@@ -283,6 +267,44 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
         }
         xi[ks] = idx;
     }
+    if (t < nrows) {
+        // the objective neuron's bound before this evaluation (mode 0); each (slot, neuron) of
+        // the objective layer has exactly one row in a pass
+        if (a.mode == 0) {
+            const long o = (long)in.slot * a.ld_state + a.state_off_obj + ent.j;
+            const float* src = ent.r >= 0 ? a.lw : a.uw;
+            ent.old = src[o];
+        }
+        s_ent[t] = ent;
+    }
+    // objective filter entries of the wavefront's first row, loaded ahead like the later ones
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    float wn[4];
+    {
+        const int co2 = wv < nrows ? a.win_ent[e0 + wv].j / nwin : 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wn[v] = (wv < nrows && pin) ? a.Wobj[(long)co2 * E + (4 * lk + v) * P + lr] : 0.f;
+    }
+    float rdp[4], rdn[4], rbn[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float l = rl[v], u = ru[v];
+        const int sj = rs[v];
+        float dp = 0.f, dn = 0.f, bn = 0.f;
+        if (!pin || sj == 1) {
+        } else if (sj == -1 || l >= 0.f) {
+            dp = dn = 1.f;
+        } else if (u <= 0.f) {
+        } else {
+            dp = ral[v];
+            const float wd = u - l;
+            dn = u / wd;
+            bn = -(u * l) / wd;
+        }
+        rdp[v] = dp;
+        rdn[v] = dn;
+        rbn[v] = bn;
+    }
     // split terms outside the window: the instance totals minus the window's share
     float Lw = 0.f, Mw = 0.f;   // every wavefront owns the same pixels: each sums them itself
     {
@@ -298,13 +320,6 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
     const float* sc = a.scal + (long)ib * 4;
     const float L_out = sc[0] - Lw, M_out = sc[1] - Mw, c_split = sc[2];
     __syncthreads();   // s_tix and s_ent complete
-    // objective filter entries of the wavefront's next row, loaded one row ahead
-    float wn[4];
-    {
-        const int co2 = wave < nrows ? s_ent[wave].j / nwin : 0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) wn[v] = (wave < nrows && pin) ? a.Wobj[(long)co2 * E + (4 * lk + v) * P + lr] : 0.f;
-    }
 
     float da[4] = {0.f, 0.f, 0.f, 0.f}, xs[4] = {0.f, 0.f, 0.f, 0.f};
     float* sT = s_T[wave];
