@@ -22,6 +22,13 @@ Readings where the paper is loose (each listed in the design notes):
 * on a residual join the coefficient is passed unchanged to both operands and
   the contributions meeting at a common producer are summed (linearity).
 
+Optional rounding margin (`margin`, default 0 = the exact bound of Eq. 6): a
+sound FP32 implementation lowers every concretised bound by
+margin * (sum_j |a_j| max(|lo_j|, |hi_j|) + |c|) to cover its own rounding; with
+the margin set, this oracle computes that bound in FP64, so that nets deep
+enough for the loosened intermediate bounds to compound can be compared with
+such an implementation element by element.
+
 Parameter arrays may be shared by all rows of a set (shape [d]) or per row
 (shape [R, d]); numpy broadcasting covers both.
 """
@@ -101,16 +108,20 @@ def relu_backsub(a, st: ReluState, alpha, beta, mnc: Mnc | None = None, gamma=No
     return ahat, dc, rec
 
 
-def concretize(a0, c, lo, hi):
-    """Eq. 6 over the box: lb = sum_j min(a_j lo_j, a_j hi_j) + c; x*_j = hi_j if a_j < 0 else lo_j."""
+def concretize(a0, c, lo, hi, margin=0.0):
+    """Eq. 6 over the box: lb = sum_j min(a_j lo_j, a_j hi_j) + c; x*_j = hi_j if a_j < 0 else lo_j.
+
+    With margin > 0, lb is lowered by margin * (sum_j |a_j| max(|lo_j|, |hi_j|) + |c|)."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
     lb = np.sum(np.minimum(a0 * lo, a0 * hi), axis=1) + c
+    if margin:
+        lb = lb - margin * (np.abs(a0) @ np.maximum(np.abs(lo), np.abs(hi)) + np.abs(c))
     xstar = np.where(a0 < 0, hi, lo)
     return lb, xstar
 
 
-def backsub(net, start, c0, states, params, mncs=None, lo=None, hi=None):
+def backsub(net, start, c0, states, params, mncs=None, lo=None, hi=None, margin=0.0):
     """Back-substitute rows from `start` down to the input and concretise.
 
     start  : dict node -> [R, size(node)] coefficients on that node's output
@@ -120,6 +131,7 @@ def backsub(net, start, c0, states, params, mncs=None, lo=None, hi=None):
     states : dict relu-node -> ReluState
     params : dict relu-node -> dict(alpha=, beta=, gamma=)
     mncs   : dict relu-node -> Mnc (optional)
+    margin : rounding margin of the concretisation (see concretize)
     Returns dict(lb, xstar, a0, c, records) with records[relu-node] as in relu_backsub.
     """
     mncs = mncs or {}
@@ -150,7 +162,7 @@ def backsub(net, start, c0, states, params, mncs=None, lo=None, hi=None):
     a0 = coef.pop(0)
     out = {"a0": a0, "c": c, "records": records}
     if lo is not None:
-        out["lb"], out["xstar"] = concretize(a0, c, lo, hi)
+        out["lb"], out["xstar"] = concretize(a0, c, lo, hi, margin)
     return out
 
 

@@ -110,8 +110,9 @@ def project(pset):
 class Query:
     """One verification problem: net, box, spec rows and optional MNC sets."""
 
-    def __init__(self, net, lo, hi, C, c0, mncs=None):
+    def __init__(self, net, lo, hi, C, c0, mncs=None, margin=0.0):
         self.net = net
+        self.margin = float(margin)   # rounding margin of every concretisation (0: exact Eq. 6)
         self.lo = np.asarray(lo, dtype=np.float64)
         self.hi = np.asarray(hi, dtype=np.float64)
         self.C = np.asarray(C, dtype=np.float64)
@@ -206,15 +207,15 @@ def root_pass(q: Query):
                 params = {k: {"alpha": heuristic_alpha(s), "beta": np.zeros(s.l.shape)}
                           for k, s in states.items()}
                 lo_out = backsub(net, neuron_start(net, i, js, +1), np.zeros(len(js)),
-                                 states, params, None, q.lo, q.hi)
+                                 states, params, None, q.lo, q.hi, q.margin)
                 up_out = backsub(net, neuron_start(net, i, js, -1), np.zeros(len(js)),
-                                 states, params, None, q.lo, q.hi)
+                                 states, params, None, q.lo, q.hi, q.margin)
                 l[js] = np.maximum(l[js], lo_out["lb"])
                 u[js] = np.minimum(u[js], -up_out["lb"])
         states[i] = ReluState(l, u)
     params = {k: {"alpha": heuristic_alpha(s), "beta": np.zeros(s.l.shape)}
               for k, s in states.items()}
-    out = backsub(net, spec_start(net, q.C), q.c0, states, params, None, q.lo, q.hi)
+    out = backsub(net, spec_start(net, q.C), q.c0, states, params, None, q.lo, q.hi, q.margin)
     ub = spec_ub(q, out["xstar"])
     sub = Subproblem(states, init_sets(net, states, q.mncs), out["lb"].copy(), ub,
                      recompute_from=len(net.relus))
@@ -268,12 +269,12 @@ def bound_optimize(q: Query, sub: Subproblem, steps=20, lr=0.1, beta1=0.9, beta2
                 continue
             for s in (1, -1):
                 outs[(m, s)] = backsub(net, neuron_start(net, i, js, s), np.zeros(len(js)),
-                                       sub.states, sub.sets[(m, s)], q.mncs, q.lo, q.hi)
+                                       sub.states, sub.sets[(m, s)], q.mncs, q.lo, q.hi, q.margin)
             st = sub.states[i]
             st.l[js] = np.maximum(st.l[js], outs[(m, 1)]["lb"])
             st.u[js] = np.minimum(st.u[js], -outs[(m, -1)]["lb"])
         outs["final"] = backsub(net, spec_start(net, q.C), q.c0, sub.states, sub.sets["final"],
-                                q.mncs, q.lo, q.hi)
+                                q.mncs, q.lo, q.hi, q.margin)
         lb = outs["final"]["lb"]
         better = lb > best
         best = np.where(better, lb, best)

@@ -24,9 +24,9 @@ def assert_parity(gpu, ref, what=""):
                             f"ref={ref.ravel()[np.argmax(err)]}"
 
 
-def oracle_query(wl, mncs=None):
+def oracle_query(wl, mncs=None, margin=0.0):
     net = onet.Net(wl.nodes)
-    return net, oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, mncs)
+    return net, oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, mncs, margin)
 
 
 def mnc_layers(net, mncs):
@@ -88,3 +88,31 @@ def make_subproblems(P, pb, rid, net_o, q, root, splits):
         ids.append(gid)
         subs.append(osub)
     return np.array(ids), subs
+
+
+def make_batch(pb, rid, splits):
+    """GPU subproblems of a batch from the root by chained branch_split, one call per split depth
+    (the way the benchmark builds its batch); returns the ids in split-set order."""
+    cur = np.full(len(splits), rid, np.int64)
+    depth = max(len(s) for s in splits)
+    for t in range(depth):
+        idx = [b for b, s in enumerate(splits) if len(s) > t]
+        kids = pb.branch_split(cur[idx], [splits[b][t][0] for b in idx], [splits[b][t][1] for b in idx])
+        drop = []
+        for k, b in enumerate(idx):
+            keep = 0 if splits[b][t][2] > 0 else 1
+            if t > 0:
+                drop.append(cur[b])
+            cur[b] = kids[2 * k + keep]
+            drop.append(kids[2 * k + 1 - keep])
+        pb.release(drop)
+    return cur
+
+
+def oracle_subproblem(net_o, root, split):
+    """The oracle's subproblem for one split set (chained branch_split from the root)."""
+    s = root
+    for (m, j, sg) in split:
+        pos, neg = obab.branch_split(net_o, s, m, j)
+        s = pos if sg > 0 else neg
+    return s

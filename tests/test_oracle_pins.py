@@ -95,6 +95,43 @@ def test_concretisation_matches_hoelder_without_clipping():
     np.testing.assert_allclose(np.einsum("rj,rj->r", a0, xs) + c, lb, atol=1e-12)
 
 
+def test_rounding_margin_closed_form():
+    """One affine layer under the spec: no intermediate bound, so the root bound is Eq. 6 in closed
+    form (a = C W, c = C b + c0) lowered by margin * (sum_j |a_j| max(|lo_j|, |hi_j|) + |c|)."""
+    rng = np.random.default_rng(8)
+    W1 = rng.normal(size=(3, 6)).astype(np.float32)
+    b1 = rng.normal(size=3).astype(np.float32)
+    nodes = [{"kind": "input", "shape": (1, 1, 6)}, {"kind": "fc", "src": 0, "W": W1, "b": b1}]
+    lo = rng.uniform(-1, 0, 6)
+    hi = lo + rng.uniform(0.1, 1, 6)
+    C, c0 = rng.normal(size=(2, 3)), rng.normal(size=2)
+    m = 2.0 ** -20
+    net = onet.Net(nodes)
+    root, _ = oo.root_pass(oo.Query(net, lo, hi, C, c0, margin=m))
+    a, c = C @ W1.astype(np.float64), C @ b1.astype(np.float64) + c0
+    exact = np.minimum(a * lo, a * hi).sum(1) + c
+    want = exact - m * (np.abs(a) @ np.maximum(np.abs(lo), np.abs(hi)) + np.abs(c))
+    np.testing.assert_allclose(root.lb, want, rtol=0, atol=1e-12)
+    assert np.all(root.lb < exact)
+
+
+def test_rounding_margin_only_loosens():
+    """On a residual net the margin lowers every lower bound and raises every upper bound (the
+    intermediate bounds compound), and a zero margin is the exact pass bit for bit."""
+    wl = W.make_workload(4, scale="small")
+    net = onet.Net(wl.nodes)
+    ex, _ = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0))
+    z, _ = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, margin=0.0))
+    mg, _ = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, margin=2.0 ** -12))
+    assert np.array_equal(z.lb, ex.lb)
+    assert np.all(mg.lb < ex.lb)
+    for i in net.relus:
+        assert np.all(mg.states[i].l <= ex.states[i].l) and np.all(mg.states[i].u >= ex.states[i].u)
+        assert np.array_equal(z.states[i].l, ex.states[i].l)
+    # past the first ReLU layer (an interval), some intermediate bound moves
+    assert any(np.any(mg.states[i].l < ex.states[i].l) for i in net.relus[1:])
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_exact_when_no_relu_is_unstable(seed):
     nodes = W.tiny_fc(seed, (4, 6, 5, 3))
