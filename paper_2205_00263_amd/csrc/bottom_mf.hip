@@ -30,10 +30,26 @@ constexpr int MNW = MBT / 64;
 static_assert(BOTTOM_CHUNK_ROWS <= 2 * MNW, "the prologue reads two rows per wavefront");
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// One dword per lane from global memory straight into LDS (global_load_lds_dword): lane l's
+// value lands at byte lds + 4 l of LDS; lds must be wave-uniform.  Written as asm so that the
+// compiler, which otherwise makes every later LDS access and barrier wait for such loads,
+// does not track it: the load has no destination register, only the issuing wavefront reads
+// what it writes, and it does so after mf_drain().  M0 (the LDS base of the load) is not used
+// by any compiler-generated code of this kernel.
+__device__ __forceinline__ void load_to_lds(const float* g, const float* lds) {
+    const unsigned la = (unsigned)(size_t)lds;
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dword %0, off" ::"v"(g), "s"(la) : "memory");
+}
+
+// Every load and store of this wavefront complete (vmcnt 0), loads into LDS included; no memory
+// access moves across it.
+__device__ __forceinline__ void mf_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Workgroup barrier for LDS data: this wavefront's LDS instructions are complete before the
+// barrier.  Unlike a release fence, it does not wait for the wavefront's loads into LDS
+// (s_pf), which only that wavefront reads, after its own vmcnt drain.
 __device__ __forceinline__ void lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // Sum of three per-thread values over the block (fixed order), valid in thread 0 only;
@@ -69,6 +85,9 @@ constexpr int nto_taps(int KK, int SS) { return KK ? ((KK + SS - 1) / SS) * ((KK
 constexpr int mf_rows(int KK, int NTT) { return (NTT == 1 && KK != 0) ? 2 : 1; }
 // Per-thread index tables in LDS (one input element per thread, 4 taps and 4 adjoint steps).
 constexpr bool mf_tab(bool O1, int KK, int SS, int NTT) { return O1 && nto_taps(KK, SS) == 4 && NTT == 1; }
+// Next rows prefetched straight into LDS: with one input element per thread (no global loads
+// left in the row loop that would wait behind them) and rows read from A.
+constexpr bool mf_pf_lds(bool SRC1, bool O1) { return O1 && !SRC1; }
 
 // KK, SS: kernel size and stride as constants (0: runtime); NTT: 16-tap tiles of the first
 // convolution (1: at most 16 taps, 2: at most 32); SRC1: rows built from the objective
@@ -81,6 +100,7 @@ template <int TPW, int KK, int SS, int NTT, bool SRC1, bool O1>
 __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     static_assert(TPW == 1, "one tile per wavefront");
     constexpr int RP = mf_rows(KK, NTT);   // rows per iteration (registers permitting)
+    constexpr bool PFL = mf_pf_lds(SRC1, O1);   // next rows prefetched into LDS (else registers)
     constexpr int KSM = 4 * NTT;   // 4-tap steps of the adjoint product
     const int k = KK ? KK : a.k;
     const int s = SS ? SS : a.s;
@@ -88,16 +108,20 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     const int HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
     const int kk = k * k, ntap = a.Ci * kk;
     const int MT = (HoWo + 15) >> 4;
-    const int TSZ = 16 * NTT * HoWo;
+    // tap products T[tap][pos]: per tap a stride of HP = 16 MT + 1 positions; position 16 MT of
+    // tap 0 is never written and holds zero (the target of col2im taps that do not exist)
+    const int HP = 16 * MT + 1, TZ = 16 * MT;
+    const int TSZ = 16 * NTT * HP;
+    const int XS = d0 + 1;   // x* rows: d0 elements and a zero (the target of absent adjoint taps)
     extern __shared__ float4 smem4[];
     float4* s_rx = smem4;                                // [d1] relaxation {a' >= 0 slope, a' < 0 slope, intercept, add}
     float* smem = reinterpret_cast<float*>(smem4 + d1);
-    float* s_T = smem;                                   // [RP][16 NTT][HoWo] tap products, tap-major
-    float* s_x = s_T + RP * TSZ;                         // [RP][d0] x* of the current rows
-    int* s_xc = reinterpret_cast<int*>(s_x + RP * d0);   // [d0] rows of the chunk with x*_o = hi_o (!O1)
-    float* s_lo = s_x + (RP + 1) * d0;                   // [d0] box (box_lds)
+    float* s_T = smem;                                   // [RP][16 NTT][HP] tap products, tap-major
+    float* s_x = s_T + RP * TSZ;                         // [RP][XS] x* of the current rows
+    int* s_xc = reinterpret_cast<int*>(s_x + RP * XS);   // [d0] rows of the chunk with x*_o = hi_o (!O1)
+    float* s_lo = s_x + RP * XS + d0;                    // [d0] box (box_lds)
     float* s_hi = s_lo + d0;                             // [d0]
-    float* s_sg = s_x + (RP + 1) * d0 + (a.box_lds ? 2 * d0 : 0);   // [d1] sum of g (MNC only)
+    float* s_sg = s_x + RP * XS + d0 + (a.box_lds ? 2 * d0 : 0);   // [d1] sum of g (MNC only)
     // per thread, row-invariant index tables (NTO == 4, KSM == 4): col2im taps and adjoint gathers
     constexpr bool TAB = mf_tab(O1, KK, SS, NTT);
     const int tab_off = (int)((s_sg + (a.gsum_out ? d1 : 0)) - reinterpret_cast<float*>(smem4));
@@ -106,6 +130,9 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     __shared__ RowDesc s_rd[BOTTOM_CHUNK_ROWS];
     __shared__ float s_crow[BOTTOM_CHUNK_ROWS];
     __shared__ float s_old[BOTTOM_CHUNK_ROWS];
+    // next rows' coefficients, per wavefront [b][v][lane] (a separate array, so that the
+    // compiler sees that no other LDS access touches what the loads into LDS write)
+    __shared__ float s_pf[PFL ? MNW * RP * 256 : 1];
 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
     // The prologue's loads are issued in four dependent levels, each level's loads in flight
@@ -131,9 +158,10 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         const int tap = 4 * ks + lk;
         aW[ks] = tap < ntap ? a.W1[lr * ntap + tap] : 0.f;
     }
-    float b1v[4];   // bias of the owned channels 4 lk + v
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b1v[v] = a.b1[4 * lk + v];
+    // bias of the first convolution (16 channels; lane group lk owns channels 4 lk .. 4 lk + 3),
+    // read from LDS where used
+    __shared__ float4 s_b1[4];
+    if (t < 16) reinterpret_cast<float*>(s_b1)[t] = a.b1[t];
     const InstDesc in = a.inst[ib];
 
     // owned neurons: tile mt = wave, neuron (co = 4 lk + v, pos = 16 mt + lr)
@@ -179,14 +207,28 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         }
     }
     // coefficients of the next rows, loaded one iteration ahead (the first ones before the
-    // barrier that ends the prologue, which waits for them)
-    float nx[SRC1 ? 1 : RP][4];
+    // barrier that ends the prologue): with PFL straight into the wavefront's LDS slots
+    // s_pf[wave][b][v][lane], otherwise into registers.  Every lane loads, so that no load sits
+    // in a branch: lanes without a position read position 0 of their channel and rows past the
+    // chunk's end the chunk's last row; neither value reaches a result, since a lane without a
+    // position has a zero relaxation and a row past the end is neither summed nor stored.
+    const int pc = pv ? pos : 0;
+    float* pfw = s_pf + (PFL ? wv * (RP * 256) : 0);
+    float nx[PFL || SRC1 ? 1 : RP][4];
     if constexpr (!SRC1) {
+        if (nr > 0) {
 #pragma unroll
-        for (int b = 0; b < RP; ++b)
+            for (int b = 0; b < RP; ++b) {
+                const float* rowp = a.A + (long)(cr0 + min(b, nr - 1)) * d1;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                nx[b][v] = (pv && b < nr) ? a.A[(long)(cr0 + b) * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
+                for (int v = 0; v < 4; ++v) {
+                    if constexpr (PFL)
+                        load_to_lds(rowp + (4 * lk + v) * HoWo + pc, pfw + (b * 4 + v) * 64);
+                    else
+                        nx[b][v] = rowp[(4 * lk + v) * HoWo + pc];
+                }
+            }
+        }
     }
     // box: O1, the owned input element o = t; otherwise staged in LDS (box_lds)
     const float* glo = a.lo + (long)qv * d0;
@@ -247,6 +289,10 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     }
     if (a.gsum_out)
         for (int j = t; j < d1; j += MBT) s_sg[j] = 0.f;
+    if (t < RP) {
+        s_T[t * TSZ + TZ] = 0.f;
+        s_x[t * XS + d0] = 0.f;
+    }
 
     // relaxation of ReLU layer 0 on the owned neurons (split first, then stable, then unstable)
     // to LDS: slope where a' >= 0, slope and intercept where a' < 0 (the intercept is > 0
@@ -272,7 +318,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         const float ad = (sj != 0 ? (float)sj * rbe[v] : 0.f) + rvh[v];
         s_rx[(4 * lk + v) * HoWo + pos] = make_float4(dp, dn, bn, ad);
     }
-    // O1: col2im taps of the owned input element (s_T offsets, -1: none)
+    // O1: col2im taps of the owned input element (s_T offsets, TZ (a zero): none)
     constexpr int NTO = nto_taps(KK, SS);
     int tix[O1 ? NTO : 1];
     if constexpr (O1) {
@@ -288,18 +334,18 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
             const int ky = Yp % s + ty * s, kx = Xp % s + tx * s;
             const int y = (Yp - ky) / s, x = (Xp - kx) / s;
             const bool tv = ov && ty < nty && tx < nty && ky < k && kx < k && Yp >= ky && Xp >= kx && y < a.Ho && x < a.Wo;
-            tix[q] = tv ? ((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x : -1;
+            tix[q] = tv ? ((ci * k + ky) * k + kx) * HP + y * a.Wo + x : TZ;
         }
         if constexpr (TAB) s_tab[t] = make_int4(tix[0], tix[NTO > 1 ? 1 : 0], tix[NTO > 2 ? 2 : 0], tix[NTO > 3 ? 3 : 0]);
     }
-    // adjoint B operand: s_x index of (pos, tap = 4 ks + lk), -1: none
+    // adjoint B operand: s_x index of (pos, tap = 4 ks + lk), d0 (a zero): none
     int gidx[KSM];
     {
         const int y = pv ? pos / a.Wo : 0, x = pv ? pos - y * a.Wo : 0;
 #pragma unroll
         for (int ks = 0; ks < KSM; ++ks) {
             const int tap = 4 * ks + lk;
-            int idx = -1;
+            int idx = d0;
             if (pv && tap < ntap) {
                 const int ci = tap / kk, rr = tap - ci * kk, ky = rr / k, kx = rr - ky * k;
                 const int Y = s * y - a.p + ky, X = s * x - a.p + kx;
@@ -315,6 +361,9 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     float da[4] = {0.f, 0.f, 0.f, 0.f};
     const float* vrow = a.v ? a.v + (long)ib * d1 : nullptr;
     const float gpv = a.gp ? a.gp[ib] : 0.f;
+    // every prologue load complete, in a form the compiler sees (the loop issues no loads it
+    // tracks, so it then places no waits inside the loop)
+    vmem_drain();
     __syncthreads();
 
     for (int ri = 0; ri < nr; ri += RP) {
@@ -325,13 +374,24 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
 #pragma unroll
             for (int b = 0; b < RP; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ap[b][v] = nx[b][v];
+                for (int v = 0; v < 4; ++v) ap[b][v] = PFL ? pfw[(b * 4 + v) * 64 + lane] : nx[PFL ? 0 : b][v];
             if (ri + RP < nr) {
+                // the slots are read before they are reloaded
+                if constexpr (PFL) __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
 #pragma unroll
-                for (int b = 0; b < RP; ++b)
+                for (int b = 0; b < RP; ++b) {
+                    const float* rowp = a.A + (long)(cr0 + min(ri + RP + b, nr - 1)) * d1;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        nx[b][v] = (pv && ri + RP + b < nr) ? a.A[(long)(cr0 + ri + RP + b) * d1 + (4 * lk + v) * HoWo + pos] : 0.f;
+                    for (int v = 0; v < 4; ++v) {
+                        if constexpr (PFL)
+                            load_to_lds(rowp + (4 * lk + v) * HoWo + pc, pfw + (b * 4 + v) * 64);
+                        else
+                            nx[PFL ? 0 : b][v] = rowp[(4 * lk + v) * HoWo + pc];
+                    }
+                }
+                // register prefetch: keep the loads here, a full iteration ahead of their use
+                // (the compiler would otherwise sink them next to it)
+                if constexpr (!PFL) asm volatile("" ::: "memory");
             }
         } else {
             // +-e_j on the output of the objective convolution: its filter placed at j
@@ -363,6 +423,8 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         float cpt[RP];
         {
             float ah[RP][4];
+            const float4 b1q = s_b1[lk];
+            const float b1g[4] = {b1q.x, b1q.y, b1q.z, b1q.w};
 #pragma unroll
             for (int b = 0; b < RP; ++b) cpt[b] = 0.f;
 #pragma unroll
@@ -373,7 +435,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     const float p = ap[b][v];
                     const bool neg = p < 0.f;
                     ah[b][v] = p * (neg ? rx.y : rx.x) + (b < nb ? rx.w : 0.f);
-                    cpt[b] += (neg ? p * rx.z : 0.f) + ah[b][v] * b1v[v];
+                    cpt[b] += (neg ? p * rx.z : 0.f) + ah[b][v] * b1g[v];
                 }
             }
             if (mt < MT) {
@@ -393,7 +455,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int p2 = mt * 16 + 4 * lk + v;
-                            if (p2 < HoWo) s_T[b * TSZ + (nt * 16 + lr) * HoWo + p2] = acc[b][v];
+                            s_T[b * TSZ + (nt * 16 + lr) * HP + p2] = acc[b][v];
                         }
                 }
             }
@@ -431,11 +493,11 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     float acc = 0.f;
 #pragma unroll
                     for (int q = 0; q < NTO; ++q)
-                        if (tq[q] >= 0) acc += s_T[b * TSZ + tq[q]];
+                        acc += s_T[b * TSZ + tq[q]];
                     lbp[b] = fminf(acc * lo_o, acc * hi_o);
                     mag[b] = fabsf(acc) * fmaxf(fabsf(lo_o), fabsf(hi_o));
                     const bool neg = acc < 0.f;
-                    s_x[b * d0 + t] = neg ? hi_o : lo_o;
+                    s_x[b * XS + t] = neg ? hi_o : lo_o;
                     if (b < nb) {
                         xc_o += neg ? 1 : 0;
                         if (a.xbits) a.xbits[(long)(cr0 + ri + b) * d0 + t] = neg ? 1 : 0;
@@ -470,13 +532,13 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                             if (!KK && kx >= k) break;
                             const int x = (Xp - kx) / s;
                             if (kx >= k || x < 0 || x >= a.Wo) continue;
-                            acc += s_T[b * TSZ + ((ci * k + ky) * k + kx) * HoWo + y * a.Wo + x];
+                            acc += s_T[b * TSZ + ((ci * k + ky) * k + kx) * HP + y * a.Wo + x];
                         }
                     }
                     lbp[b] += fminf(acc * l, acc * h);
                     mag[b] += fabsf(acc) * fmaxf(fabsf(l), fabsf(h));
                     const bool neg = acc < 0.f;
-                    s_x[b * d0 + o] = neg ? h : l;
+                    s_x[b * XS + o] = neg ? h : l;
                     if (b < nb) {
                         if (a.adjoint && neg) s_xc[o] += 1;
                         if (a.xbits) a.xbits[(long)(cr0 + ri + b) * d0 + o] = neg ? 1 : 0;
@@ -484,8 +546,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                 }
             }
         }
-        // block sums of the RP rows' bound terms (one barrier, which also publishes s_x); the
-        // sums are valid in thread 0
+        // block sums of the RP rows' bound terms (one barrier, which also publishes s_x)
         {
             float vals[3 * RP];
 #pragma unroll
@@ -498,21 +559,23 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
 #pragma unroll
                 for (int q = 0; q < 3 * RP; ++q) red[q][wave] = vals[q];
             lds_sync();
-            if (t == 0) {
-#pragma unroll
-                for (int b = 0; b < RP; ++b) {
-                    if (b >= nb) break;
-                    float tot[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const float* rq = red[3 * b + q];
-                        const float h0 = ((rq[0] + rq[1]) + (rq[2] + rq[3])) + ((rq[4] + rq[5]) + (rq[6] + rq[7]));
-                        const float h1 = ((rq[8] + rq[9]) + (rq[10] + rq[11])) + ((rq[12] + rq[13]) + (rq[14] + rq[15]));
-                        tot[q] = h0 + h1;
-                    }
+            // the last wavefront (no position tile for most shapes) finishes the sums: lane q
+            // adds red[q] in a fixed order, lane b the bound of row b
+            if (wave == MNW - 1) {
+                float tot = 0.f;
+                if (lane < 3 * RP) {
+                    const float* rq = red[lane];
+                    const float h0 = ((rq[0] + rq[1]) + (rq[2] + rq[3])) + ((rq[4] + rq[5]) + (rq[6] + rq[7]));
+                    const float h1 = ((rq[8] + rq[9]) + (rq[10] + rq[11])) + ((rq[12] + rq[13]) + (rq[14] + rq[15]));
+                    tot = h0 + h1;
+                }
+                const int b = lane;
+                const int src = min(3 * b, 3 * RP - 3);
+                const float t0 = __shfl(tot, src), t1 = __shfl(tot, src + 1), t2 = __shfl(tot, src + 2);
+                if (b < nb) {
                     const int r = cr0 + ri + b;
                     const RowDesc rd = s_rd[ri + b];
-                    float lb = (tot[0] + tot[2]) - (tot[1] + fabsf(tot[2])) * 9.5367431640625e-07f;   // 2^-20 margin
+                    float lb = (t0 + t2) - (t1 + fabsf(t2)) * 9.5367431640625e-07f;   // 2^-20 margin
                     if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
                     const float old = s_old[ri + b];
                     if (a.mode == 0) {
@@ -556,19 +619,21 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     const int gi = gq[ks];
 #pragma unroll
                     for (int b = 0; b < RP; ++b) {
-                        const float xv = gi >= 0 ? s_x[b * d0 + gi] : 0.f;
+                        const float xv = s_x[b * XS + gi];
                         acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aW[ks], xv, acc[b], 0, 0, 0);
                     }
                 }
             }
             float gv[RP][4];
+            const float4 b1q = s_b1[lk];
+            const float b1g[4] = {b1q.x, b1q.y, b1q.z, b1q.w};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float4 rx = relax(v);
 #pragma unroll
                 for (int b = 0; b < RP; ++b) {
                     // lane holds ghat[co = 4 lk + v][pos] without the bias
-                    const float gh = acc[b][v] + b1v[v];
+                    const float gh = acc[b][v] + b1g[v];
                     const float p = ap[b][v];
                     const bool neg = p < 0.f;
                     const float g = (neg ? rx.y : rx.x) * gh + (neg ? rx.z : 0.f);
@@ -579,16 +644,19 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     gv[b][v] = g;
                 }
             }
-            vmem_drain();
+            if constexpr (PFL) mf_drain(); else vmem_drain();
             if (a.Gout && pv) {
 #pragma unroll
                 for (int b = 0; b < RP; ++b)
                     if (b < nb)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) a.Gout[(long)(cr0 + ri + b) * d1 + (4 * lk + v) * HoWo + pos] = gv[b][v];
+                        for (int v = 0; v < 4; ++v) {
+                            float* growp = a.Gout + (long)(cr0 + ri + b) * d1;
+                            growp[(4 * lk + v) * HoWo + pos] = gv[b][v];
+                        }
             }
         } else {
-            vmem_drain();
+            if constexpr (PFL) mf_drain(); else vmem_drain();
         }
         // next iteration: its T writes follow the barrier above (every col2im read is done) and
         // its x* writes follow its first barrier (every adjoint gather of this one is done)
@@ -650,15 +718,25 @@ static size_t mf_lds(int Ci, int k, int s, int Ho, int Wo, int d0, int d1, bool 
     mf_shape(Ci, k, s, KK, SS, ntt);
     const size_t rp = mf_rows(KK, ntt);
     const bool tab = mf_tab(d0 <= MBT, KK, SS, ntt);
-    return (4 * (size_t)d1 + rp * 16 * ntt * Ho * Wo + (rp + 1) * d0 + (mnc ? (size_t)d1 : 0) +
+    const size_t hp = 16 * (size_t)((Ho * Wo + 15) / 16) + 1;   // padded tap stride of T
+    return (4 * (size_t)d1 + rp * 16 * ntt * hp + rp * ((size_t)d0 + 1) + d0 + (mnc ? (size_t)d1 : 0) +
             (tab ? 4 + 2 * 4 * (size_t)MBT : 0)) *
            sizeof(float);
+}
+
+// Dynamic LDS the kernel may take next to its static arrays (with the LDS prefetch: its slots,
+// 4 KB per row of an iteration, and under 2 KB of descriptors and sums) within the CU's 160 KB.
+static size_t mf_dyn_limit(int Ci, int k, int s, int d0) {
+    int KK, SS, ntt;
+    mf_shape(Ci, k, s, KK, SS, ntt);
+    if (!mf_pf_lds(false, d0 <= MBT)) return 150 * 1024;
+    return 160 * 1024 - (size_t)MNW * mf_rows(KK, ntt) * 256 * sizeof(float) - 2048;
 }
 
 bool bottom_mf_supported(int Co, int Ci, int k, int s, int Ho, int Wo, int d0, int d1, bool mnc) {
     const int HoWo = Ho * Wo, ntap = Ci * k * k;
     const size_t lds = mf_lds(Ci, k, s, Ho, Wo, d0, d1, mnc);
-    return Co == 16 && ntap <= 32 && (HoWo + 15) / 16 <= MNW && lds <= 150 * 1024;
+    return Co == 16 && ntap <= 32 && (HoWo + 15) / 16 <= MNW && lds <= mf_dyn_limit(Ci, k, s, d0);
 }
 
 void launch_bottom_mf(const BottomArgs& a, hipStream_t st) {
@@ -669,7 +747,7 @@ void launch_bottom_mf(const BottomArgs& a, hipStream_t st) {
     size_t lds = mf_lds(a.Ci, a.k, a.s, a.Ho, a.Wo, a.d0, a.d1, a.gsum_out != nullptr);
     BottomArgs b = a;
     // with one input element per thread (d0 <= MBT) the box is held in registers instead
-    b.box_lds = a.d0 > MBT && lds + 2 * (size_t)a.d0 * sizeof(float) <= 150 * 1024;
+    b.box_lds = a.d0 > MBT && lds + 2 * (size_t)a.d0 * sizeof(float) <= mf_dyn_limit(a.Ci, a.k, a.s, a.d0);
     if (b.box_lds) lds += 2 * (size_t)a.d0 * sizeof(float);
     if (ntt == 1 && a.k == 4 && a.s == 2)
         launch_mf_tpw<4, 2, 1>(b, lds, st);
