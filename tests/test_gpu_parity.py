@@ -1,4 +1,6 @@
 """GPU path vs the FP64 oracle, element by element, through the C ABI (needs an MI355X)."""
+import copy
+
 import numpy as np
 import pytest
 
@@ -8,7 +10,8 @@ from oracle import bab as obab
 from oracle import net as onet
 from oracle import optimize as oo
 
-from _common import assert_parity, make_subproblems, oracle_query, root_unstable, sampled_min, sampled_min_sub
+from _common import (assert_parity, make_batch, make_subproblems, oracle_query, oracle_subproblem, root_unstable,
+                     sampled_min, sampled_min_sub)
 
 pytestmark = pytest.mark.gpu
 
@@ -233,6 +236,60 @@ def test_optimize_matches_oracle(cfg, n_sub, steps):
     ref_ub = np.array([s.ub for s in subs])
     close = np.abs(ub - ref_ub) <= 1e-3 * np.maximum(1.0, np.abs(ref_ub))
     assert close.mean() >= 0.9, close.mean()
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 4])
+def test_teacher_forced_20_steps_match_oracle(cfg):
+    """Fixed-parameter parity along a whole 20-step optimisation: the oracle evaluates the GPU's own
+    parameter iterates (read back after bound_optimize with steps = t, t = 0..20, each on a fresh
+    copy of the subproblem; the trajectory is deterministic, so these are the iterates of one
+    20-step run), with its own intersection of the recomputed intermediate bounds.  Every step
+    is then compared at identical parameters, free of Adam's sensitivity to rounding order."""
+    P = _P()
+    T = 20
+    wl = W.make_workload(cfg, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=4 * (T + 1) + 8)
+    rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    split = W.make_split_sets(root_unstable(net_o, root), 1, 1, 3, seed=500 + cfg)[0]
+    ids = make_batch(pb, rid, [split] * (T + 1))
+    osub = oracle_subproblem(net_o, root, split)
+    layers = oo.recompute_layers(net_o, osub)
+    keys = ["final"] + [(m, s) for m in layers for s in (1, -1)]
+    offs = np.cumsum([0] + [net_o.sizes[i] for i in net_o.relus])
+    teacher, lbs = [], []
+    for t in range(T + 1):
+        lb, _ = pb.bound_optimize([ids[t]], steps=t, lr=0.1)
+        lbs.append(lb[0])
+        sets = {}
+        for k in keys:
+            a, b, _ = pb.get_params(ids[t], P.set_index(k))
+            sk = copy.deepcopy(osub.sets[k])
+            for n, i in enumerate(net_o.relus):
+                if i in sk:
+                    sk[i]["alpha"] = a[offs[n]:offs[n + 1]].astype(np.float64)
+                    sk[i]["beta"] = b[offs[n]:offs[n + 1]].astype(np.float64)
+            sets[k] = sk
+        teacher.append(sets)
+    lb0 = osub.lb.copy()
+    trace = []
+    oo.bound_optimize(q, osub, steps=T, lr=0.1, trace=trace, teacher=teacher)
+    best = np.full(q.n_spec, -np.inf)
+    for t in range(T + 1):
+        best = np.maximum(best, trace[t]["lb"])
+        assert_parity(lbs[t], np.maximum(best, lb0), f"cfg{cfg} after {t} steps")
+    for m in layers:
+        i = net_o.relus[m]
+        l, u, _ = pb.get_bounds(ids[T], m)
+        assert_parity(l, trace[T]["l"][i], f"cfg{cfg} layer {m} l after {T} steps")
+        assert_parity(u, trace[T]["u"][i], f"cfg{cfg} layer {m} u after {T} steps")
+    print(f"cfg{cfg}: split {split}, lb after 0 / {T} steps {lbs[0].min():.5f} / {lbs[T].min():.5f}", flush=True)
+    # free-running: the oracle's own 20-step trajectory (these seeds cross no kink of the
+    # relaxation, where the two trajectories could part legitimately)
+    free = oo.bound_optimize(q, oracle_subproblem(net_o, root, split), steps=T, lr=0.1).lb
+    assert_parity(lbs[T], free, f"cfg{cfg} free-running {T} steps")
 
 
 # --------------------------------------------------------------------------- checkpointed adjoint
