@@ -400,23 +400,11 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
 // ghat_j is (W1 X)_j + n b1 with X_o = m_o hi_o + (n - m_o) lo_o, m_o the number of rows
 // with x*_o = hi_o (exact); it is evaluated in double, free of the cancellation that a
 // float sum of nearly opposite row terms would suffer.
-__global__ __launch_bounds__(256) void k_bottom_reduce(BottomArgs a) {
-    extern __shared__ double s_X[];   // [d0]
-    const int ib = blockIdx.y;
-    const InstDesc in = a.inst[ib];
+// One neuron j of ReLU layer 0 for instance ib: alpha, beta and the optional g / ghat sums.
+__device__ __forceinline__ void bottom_reduce_neuron(const BottomArgs& a, int ib, const InstDesc& in, int j,
+                                                     double n_rows, const double* s_X) {
     const int d1 = a.d1, d0 = a.d0;
     const int c0 = a.ichunk0[ib], c1 = a.ichunk1[ib];
-    const double n_rows = (double)(in.r1 - in.r0);
-    const float* lo = a.lo + (long)a.qid[in.slot] * d0;
-    const float* hi = a.hi + (long)a.qid[in.slot] * d0;
-    for (int o = threadIdx.x; o < d0; o += 256) {
-        float m = 0.f;   // integer counts: exact in float
-        for (int c = c0; c < c1; ++c) m += a.part[(long)c * (2 * d1 + d0) + 2 * d1 + o];
-        s_X[o] = (double)m * (double)hi[o] + (n_rows - (double)m) * (double)lo[o];
-    }
-    __syncthreads();
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= d1) return;
     const long so = (long)in.slot * a.ld_state + j;
     const int sj = (int)a.S[so];
     // unstable exactly where the fold used the triangle (same test as the kernel)
@@ -424,6 +412,7 @@ __global__ __launch_bounds__(256) void k_bottom_reduce(BottomArgs a) {
     const bool unst = sj == 0 && !(l >= 0.f) && !(u <= 0.f) && (-(u * l) / (u - l)) > 0.f;
     const bool need_h = a.gsum_hat || sj != 0;
     float da = 0.f, sg = 0.f;
+#pragma unroll 4
     for (int c = c0; c < c1; ++c) {
         const float* pt = a.part + (long)c * (2 * d1 + d0);
         if (unst) da += pt[j];
@@ -453,6 +442,28 @@ __global__ __launch_bounds__(256) void k_bottom_reduce(BottomArgs a) {
     a.d_beta[go] = (float)sj * sh;
     if (a.gsum_hat) a.gsum_hat[(long)ib * a.d1 + j] = sh;
     if (a.gsum_out) a.gsum_out[(long)ib * a.d1 + j] = sg;
+}
+
+// One workgroup per instance: the sum of x* over the instance's rows is formed once (from the
+// chunks' counts of x* = hi), then every neuron's gradients.
+constexpr int RDT = 1024;
+__global__ __launch_bounds__(RDT) void k_bottom_reduce(BottomArgs a) {
+    extern __shared__ double s_X[];   // [d0]
+    const int ib = blockIdx.x;
+    const InstDesc in = a.inst[ib];
+    const int d1 = a.d1, d0 = a.d0;
+    const int c0 = a.ichunk0[ib], c1 = a.ichunk1[ib];
+    const double n_rows = (double)(in.r1 - in.r0);
+    const float* lo = a.lo + (long)a.qid[in.slot] * d0;
+    const float* hi = a.hi + (long)a.qid[in.slot] * d0;
+    for (int o = threadIdx.x; o < d0; o += RDT) {
+        float m = 0.f;   // integer counts: exact in float
+#pragma unroll 4
+        for (int c = c0; c < c1; ++c) m += a.part[(long)c * (2 * d1 + d0) + 2 * d1 + o];
+        s_X[o] = (double)m * (double)hi[o] + (n_rows - (double)m) * (double)lo[o];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < d1; j += RDT) bottom_reduce_neuron(a, ib, in, j, n_rows, s_X);
 }
 
 bool bottom_supported(int d1, int d0, int n_weights) {
@@ -507,7 +518,7 @@ void launch_bottom(const BottomArgs& a, int n_inst, hipStream_t st) {
 
 void launch_bottom_reduce(const BottomArgs& a, int n_inst, hipStream_t st) {
     if (!a.adjoint || n_inst <= 0 || a.n_chunk <= 0) return;
-    hipLaunchKernelGGL(k_bottom_reduce, dim3(cdiv(a.d1, 256), n_inst), dim3(256), (size_t)a.d0 * sizeof(double), st, a);
+    hipLaunchKernelGGL(k_bottom_reduce, dim3(n_inst), dim3(RDT), (size_t)a.d0 * sizeof(double), st, a);
     MNB_HIP(hipGetLastError());
 }
 
