@@ -58,21 +58,34 @@ __global__ __launch_bounds__(256) void k_relu_fold(FoldArgs a, const float* gp) 
     const float bias = a.bias[jj];
     const float gpv = (gp && blockIdx.x == 0 && threadIdx.x == 0) ? gp[blockIdx.y] : 0.f;
     const int col = a.col_off + blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the per-neuron values above complete, in a form the compiler sees: otherwise it waits for
+    // them (and, the counter being in order, for every store before) inside the row loop.  The
+    // empty asm keeps their loads above the wait.
+    asm volatile("" ::: "memory");
+    vmem_drain();
     // rows in groups of FR with all of a group's loads in flight together
     constexpr int FR = 8;
     for (int r0 = in.r0; r0 < in.r1; r0 += FR) {
         float av[FR];
         if (a.Wsrc) {
+            // the group's row descriptors {b, inst, j, sign} as 16-byte loads, all in flight together
+            int4 rdv[FR];
+#pragma unroll
+            for (int u = 0; u < FR; ++u) rdv[u] = reinterpret_cast<const int4*>(a.rows)[min(r0 + u, in.r1 - 1)];
             float sg[FR];
             int jr[FR];
 #pragma unroll
             for (int u = 0; u < FR; ++u) {
-                const RowDesc rd = a.rows[min(r0 + u, in.r1 - 1)];
-                sg[u] = (float)rd.sign;
-                jr[u] = rd.j;
+                sg[u] = (float)rdv[u].w;
+                jr[u] = rdv[u].z;
             }
+            // every lane loads (rows past the instance read its last row's filter, lanes past d
+            // column 0), so that the loads are in flight together; the value is then selected
 #pragma unroll
-            for (int u = 0; u < FR; ++u) av[u] = (ok && r0 + u < in.r1) ? sg[u] * a.Wsrc[(long)jr[u] * a.d + j] : 0.f;
+            for (int u = 0; u < FR; ++u) {
+                const float w = a.Wsrc[(long)jr[u] * a.d + jj];
+                av[u] = (ok && r0 + u < in.r1) ? sg[u] * w : 0.f;
+            }
             if (blockIdx.x == 0 && threadIdx.x < FR && r0 + (int)threadIdx.x < in.r1) {
                 const int u = threadIdx.x;
                 a.c[r0 + u] = sg[u] * a.bias_obj[jr[u]];
@@ -81,6 +94,9 @@ __global__ __launch_bounds__(256) void k_relu_fold(FoldArgs a, const float* gp) 
 #pragma unroll
             for (int u = 0; u < FR; ++u) av[u] = (ok && r0 + u < in.r1) ? a.A[(long)(r0 + u) * a.d + j] : 0.f;
         }
+        // the group's values complete before its first store: no later wait (which would also
+        // wait for the stores before it) is left pending inside the row steps
+        vmem_drain();
 #pragma unroll
         for (int u = 0; u < FR; ++u) {
             const int r = r0 + u;
