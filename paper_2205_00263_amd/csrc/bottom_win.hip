@@ -163,9 +163,12 @@ __device__ __forceinline__ void wave_sync() {
 template <int NT>
 __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
     constexpr int NW = WT / 64;
-    __shared__ float s_T[NW][16 * 32];   // per wavefront: T[pos][tap] of the transposed convolution
+    // per wavefront: T[pos][tap] of the transposed convolution, then one zero (never written: the
+    // target of the col2im taps that do not exist)
+    constexpr int TZ = 16 * 32;
+    __shared__ float s_T[NW][TZ + 1];
     __shared__ float s_x[NW][WT];        // per wavefront: x* on the input window (0 outside the image)
-    __shared__ int s_tix[WT][4];         // col2im: per input-window pixel, its T entries (-1: none)
+    __shared__ int s_tix[WT][4];         // col2im: per input-window pixel, its T entries (TZ: none)
     __shared__ WinEnt s_ent[64];         // the window's rows (at most one per objective channel)
     const int w = blockIdx.x, ib = blockIdx.y;
     const InstDesc in = a.inst[ib];
@@ -243,7 +246,8 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
                     if (u < 4) s_tix[q][u++] = (pdy * a.ok + pdx) * 32 + (ciq * a.k + ky) * a.k + kx;
                 }
             }
-        for (; u < 4; ++u) s_tix[q][u] = -1;
+        for (; u < 4; ++u) s_tix[q][u] = TZ;
+        if (t < NW) s_T[t][TZ] = 0.f;
     }
     // ---- MFMA operands held in registers: transposed B[k = c1 = 4 lk + ks][n = tap = 16 nt + lr],
     // adjoint A[m = c1 = lr][k = tap = 4 ks + lk] and its B operand's x* index (pos = lr)
@@ -365,10 +369,7 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
             if (qv[i]) {
                 float acc = as_q[i];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int ti = s_tix[q][u];
-                    if (ti >= 0) acc += sT[ti];
-                }
+                for (int u = 0; u < 4; ++u) acc += sT[s_tix[q][u]];
                 lbp += fminf(acc * lo_q[i], acc * hi_q[i]);
                 mag += fabsf(acc) * fmaxf(fabsf(lo_q[i]), fabsf(hi_q[i]));
                 xq = acc < 0.f ? hi_q[i] : lo_q[i];

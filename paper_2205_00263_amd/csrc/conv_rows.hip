@@ -331,17 +331,19 @@ constexpr int TLD = 17;   // T row stride (positions x 16 taps, padded)
 template <int MT, int K4, int NQ>   // MT: 16-position tiles, K4 = Co / 4, NQ: outputs per lane per channel
 __global__ __launch_bounds__(TT) void k_convT_tap(ConvTTapArgs a) {
     constexpr int NTO = 4;                    // taps reaching an output (kernel <= 2 x stride 2)
-    constexpr int TB = 16 * MT * TLD;         // one T tile
+    constexpr int TB = (16 * MT + 1) * TLD;   // one T tile: 16 MT position rows and a zero row
+    constexpr int TZ = 16 * MT * TLD;         // the zero row (never written): target of absent taps
     extern __shared__ float sm[];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
     const int kk = a.k * a.k, HoWo = a.Ho * a.Wo, HiWi = a.Hi * a.Wi;
     float* s_W = sm;                                         // [Ci][Co][16] B operand, taps padded
-    float* s_T = sm + a.Ci * a.Co * 16 + wave * 2 * TB;      // [2][16 MT][TLD]
+    float* s_T = sm + a.Ci * a.Co * 16 + wave * 2 * TB;      // [2][16 MT + 1][TLD]
+    if (lane == 0) s_T[TZ] = s_T[TB + TZ] = 0.f;
     for (int i = t; i < a.Ci * a.Co * 16; i += TT) {
         const int tap = i & 15, cc = i >> 4, co = cc % a.Co, ci = cc / a.Co;
         s_W[i] = tap < kk ? a.W[((long)co * a.Ci + ci) * kk + tap] : 0.f;
     }
-    // per owned output q = lane + 64 i of a channel: its taps' T entries (-1: none)
+    // per owned output q = lane + 64 i of a channel: its taps' T entries (TZ, a zero: none)
     int tix[NQ][NTO];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(TT) void k_convT_tap(ConvTTapArgs a) {
             const int ky = Yp % a.s + (u >> 1) * a.s, kx = Xp % a.s + (u & 1) * a.s;
             const int y = (Yp - ky) / a.s, x = (Xp - kx) / a.s;
             const bool tv = qv && ky < a.k && kx < a.k && Yp >= ky && Xp >= kx && y < a.Ho && x < a.Wo;
-            tix[i][u] = tv ? (y * a.Wo + x) * TLD + ky * a.k + kx : -1;
+            tix[i][u] = tv ? (y * a.Wo + x) * TLD + ky * a.k + kx : TZ;
         }
     }
     const long stride = (long)gridDim.x * (TT / 64);
@@ -410,8 +412,7 @@ __global__ __launch_bounds__(TT) void k_convT_tap(ConvTTapArgs a) {
                 if (q < HiWi) {
                     float sum = 0.f;
 #pragma unroll
-                    for (int u = 0; u < NTO; ++u)
-                        if (tix[i][u] >= 0) sum += T[tix[i][u]];
+                    for (int u = 0; u < NTO; ++u) sum += T[tix[i][u]];
                     float* o = dst + (long)ci * HiWi + q;
                     *o = a.acc ? *o + sum : sum;
                 }
@@ -573,7 +574,7 @@ static bool launch_convT_tap(const ConvGeom& g, const float* A, float* C, int M,
     a.A = A; a.C = C; a.W = g.W; a.M = M; a.acc = accumulate;
     a.Ci = g.Ci; a.Hi = g.Hi; a.Wi = g.Wi; a.Co = g.Co; a.Ho = g.Ho; a.Wo = g.Wo; a.k = g.k; a.s = g.s; a.p = g.p;
     const int mt = (HoWo + 15) / 16, nq = (HiWi + 63) / 64;
-    const size_t lds = ((size_t)g.Ci * g.Co * 16 + (size_t)(TT / 64) * 2 * 16 * mt * TLD) * sizeof(float);
+    const size_t lds = ((size_t)g.Ci * g.Co * 16 + (size_t)(TT / 64) * 2 * (16 * mt + 1) * TLD) * sizeof(float);
     if (lds > ROW_LDS_MAX) return false;
     if (M <= 0) return true;
     const long nb = (M + TT / 64 - 1) / (TT / 64);
