@@ -214,6 +214,9 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     // position has a zero relaxation and a row past the end is neither summed nor stored.
     const int pc = pv ? pos : 0;
     float* pfw = s_pf + (PFL ? wv * (RP * 256) : 0);
+    // wavefronts without a position tile (16 tiles for ConvSmall's 11) take no LDS prefetch: their
+    // coefficients are zero (they feed no MFMA and no store)
+    const bool pfw_on = wv < MT;
     float nx[PFL || SRC1 ? 1 : RP][4];
     if constexpr (!SRC1) {
         if (nr > 0) {
@@ -222,10 +225,11 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                 const float* rowp = a.A + (long)(cr0 + min(b, nr - 1)) * d1;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    if constexpr (PFL)
-                        load_to_lds(rowp + (4 * lk + v) * HoWo + pc, pfw + (b * 4 + v) * 64);
-                    else
+                    if constexpr (PFL) {
+                        if (pfw_on) load_to_lds(rowp + (4 * lk + v) * HoWo + pc, pfw + (b * 4 + v) * 64);
+                    } else {
                         nx[b][v] = rowp[(4 * lk + v) * HoWo + pc];
+                    }
                 }
             }
         }
@@ -374,7 +378,8 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
 #pragma unroll
             for (int b = 0; b < RP; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ap[b][v] = PFL ? pfw[(b * 4 + v) * 64 + lane] : nx[PFL ? 0 : b][v];
+                for (int v = 0; v < 4; ++v)
+                    ap[b][v] = PFL ? (pfw_on ? pfw[(b * 4 + v) * 64 + lane] : 0.f) : nx[PFL ? 0 : b][v];
             if (ri + RP < nr) {
                 // the slots are read before they are reloaded
                 if constexpr (PFL) __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
@@ -383,10 +388,11 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     const float* rowp = a.A + (long)(cr0 + min(ri + RP + b, nr - 1)) * d1;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        if constexpr (PFL)
-                            load_to_lds(rowp + (4 * lk + v) * HoWo + pc, pfw + (b * 4 + v) * 64);
-                        else
+                        if constexpr (PFL) {
+                            if (pfw_on) load_to_lds(rowp + (4 * lk + v) * HoWo + pc, pfw + (b * 4 + v) * 64);
+                        } else {
                             nx[PFL ? 0 : b][v] = rowp[(4 * lk + v) * HoWo + pc];
+                        }
                     }
                 }
                 // register prefetch: keep the loads here, a full iteration ahead of their use
