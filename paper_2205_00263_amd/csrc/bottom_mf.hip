@@ -11,13 +11,16 @@
 //   transposed first convolution (Eq. 2): T[pos][tap] = sum_co ahat[co][pos] W[co][tap],
 //       with ahat as the MFMA A operand straight from registers    -> T in LDS
 //   barrier; col2im of T, concretisation over the box (Eq. 6), x*   -> x* in LDS
-//   block reduction of the bound (barrier)
+//   block reduction of the bound (barrier; the last wavefront finishes the sums and
+//       stores the bounds)
 //   adjoint: ghat^T[co][pos] = sum_tap W[co][tap] x*[pos][tap] + b, whose MFMA
 //       output lands in the lanes that hold a' for the same neurons, so the
 //       relaxation of ReLU layer 0, the alpha-gradient sums and the rows' g are
 //       computed in registers.
-// Two barriers per row.  The alpha sums run over the chunk's rows in order; the
-// ghat sums for beta come from per-element counts of x* = hi (k_bottom_reduce).
+// Rows are taken two at a time where registers allow (RP), with two barriers per
+// iteration; the next rows' coefficients are loaded an iteration ahead (into LDS with
+// one input element per thread).  The alpha sums run over the chunk's rows in order;
+// the ghat sums for beta come from per-element counts of x* = hi (k_bottom_reduce).
 #include "bottom.h"
 #include "../../include/mnbab.h"
 
