@@ -423,25 +423,29 @@ __global__ void k_adam(AdamArgs a) {
         // intersected), so its alpha no longer enters any bound; a beta with zero gradient and
         // zero moments does not move.  Only those entries are updated.
         const long so = (long)in.slot * a.ld_state + k;
+        // S, l and u in one round trip (no short-circuit), then gradient, moments and parameter
+        // in one, before any store
         const int sj = (int)a.S[so];
-        if (sj == 0) {
-            if (a.l[so] < 0.f && a.u[so] > 0.f) {
-                const float g = a.g_alpha[go];
-                const float m = a.b1 * a.m_alpha[mo] + (1.f - a.b1) * g;
-                const float v = a.b2 * a.v_alpha[mo] + (1.f - a.b2) * g * g;
+        const float lj = a.l[so], uj = a.u[so];
+        const bool upd_a = (sj == 0) & (lj < 0.f) & (uj > 0.f);
+        if (upd_a || sj != 0) {
+            const bool al = sj == 0;
+            const float g = al ? a.g_alpha[go] : a.g_beta[go];
+            const float m0 = al ? a.m_alpha[mo] : a.m_beta[mo];
+            const float v0 = al ? a.v_alpha[mo] : a.v_beta[mo];
+            const float p0 = al ? a.alpha[po] : a.beta[po];
+            const float m = a.b1 * m0 + (1.f - a.b1) * g;
+            const float v = a.b2 * v0 + (1.f - a.b2) * g * g;
+            const float p = p0 + a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+            if (al) {
                 a.m_alpha[mo] = m;
                 a.v_alpha[mo] = v;
-                const float p = a.alpha[po] + a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
                 a.alpha[po] = fminf(fmaxf(p, 0.f), 1.f);
+            } else {
+                a.m_beta[mo] = m;
+                a.v_beta[mo] = v;
+                a.beta[po] = fmaxf(p, 0.f);
             }
-        } else {
-            const float g = a.g_beta[go];
-            const float m = a.b1 * a.m_beta[mo] + (1.f - a.b1) * g;
-            const float v = a.b2 * a.v_beta[mo] + (1.f - a.b2) * g * g;
-            a.m_beta[mo] = m;
-            a.v_beta[mo] = v;
-            const float p = a.beta[po] + a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
-            a.beta[po] = fmaxf(p, 0.f);
         }
     }
     if (a.gamma && k < a.n_gamma) {
