@@ -362,8 +362,10 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         }
         if constexpr (TAB) s_tab[MBT + t] = make_int4(gidx[0], gidx[KSM > 1 ? 1 : 0], gidx[KSM > 2 ? 2 : 0], gidx[KSM > 3 ? 3 : 0]);
     }
+    // (read at an in-bounds index by every lane, then zero for lanes without a position)
     auto relax = [&](int v) -> float4 {
-        return pv ? s_rx[(4 * lk + v) * HoWo + pos] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r = s_rx[(4 * lk + v) * HoWo + pc];
+        return pv ? r : make_float4(0.f, 0.f, 0.f, 0.f);
     };
     float da[4] = {0.f, 0.f, 0.f, 0.f};
     const float* vrow = a.v ? a.v + (long)ib * d1 : nullptr;
@@ -376,13 +378,30 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
     for (int ri = 0; ri < nr; ri += RP) {
         const int nb = min(RP, nr - ri);   // rows this iteration (the second may be absent)
         // ---- row coefficients a on the owned neurons of ReLU layer 0
+        // the relaxation of the owned neurons, read together with the prefetched rows below
+        float4 rxq[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rxq[v] = relax(v);
         float ap[RP][4];
         if constexpr (!SRC1) {
+            if constexpr (PFL) {
+                if (pfw_on) {
 #pragma unroll
-            for (int b = 0; b < RP; ++b)
+                    for (int b = 0; b < RP; ++b)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    ap[b][v] = PFL ? (pfw_on ? pfw[(b * 4 + v) * 64 + lane] : 0.f) : nx[PFL ? 0 : b][v];
+                        for (int v = 0; v < 4; ++v) ap[b][v] = pfw[(b * 4 + v) * 64 + lane];
+                } else {
+#pragma unroll
+                    for (int b = 0; b < RP; ++b)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) ap[b][v] = 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < RP; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) ap[b][v] = nx[b][v];
+            }
             if (ri + RP < nr) {
                 // the slots are read before they are reloaded
                 if constexpr (PFL) __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
@@ -438,7 +457,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
             for (int b = 0; b < RP; ++b) cpt[b] = 0.f;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float4 rx = relax(v);
+                const float4 rx = rxq[v];
 #pragma unroll
                 for (int b = 0; b < RP; ++b) {
                     const float p = ap[b][v];
