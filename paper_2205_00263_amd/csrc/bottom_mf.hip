@@ -653,11 +653,16 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                 }
             }
             float gv[RP][4];
+            // the four relaxations and the bias in one LDS round trip
+            float4 rxa[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) rxa[v] = relax(v);
             const float4 b1q = s_b1[lk];
             const float b1g[4] = {b1q.x, b1q.y, b1q.z, b1q.w};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float4 rx = relax(v);
+                const float4 rx = rxa[v];
+                float sg = 0.f;
 #pragma unroll
                 for (int b = 0; b < RP; ++b) {
                     // lane holds ghat[co = 4 lk + v][pos] without the bias
@@ -667,10 +672,12 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     const float g = (neg ? rx.y : rx.x) * gh + (neg ? rx.z : 0.f);
                     if (b < nb) {
                         if (rx.z > 0.f && !neg) da[v] += p * gh;
-                        if (a.gsum_out && pv) s_sg[(4 * lk + v) * HoWo + pos] += g;
+                        sg += g;
                     }
                     gv[b][v] = g;
                 }
+                // the rows' g in row order, one LDS update per neuron
+                if (a.gsum_out && pv) s_sg[(4 * lk + v) * HoWo + pos] += sg;
             }
             if constexpr (PFL) mf_drain(); else vmem_drain();
             if (a.Gout && pv) {
