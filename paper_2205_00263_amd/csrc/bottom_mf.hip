@@ -498,6 +498,9 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
         if (t == 0)
 #pragma unroll
             for (int b = 0; b < RP; ++b) cpt[b] += b < nb ? s_crow[ri + b] - gpv : 0.f;
+        // the owned element's col2im taps (written once in the prologue), read before the barrier
+        int4 tv;
+        if constexpr (TAB) tv = s_tab[t];
         lds_sync();
         // ---- col2im onto the input and concretisation over the box (Eq. 6), x*
         float lbp[RP], mag[RP];
@@ -507,7 +510,6 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
             if (t < d0) {
                 int tq[NTO];
                 if constexpr (TAB) {
-                    const int4 tv = s_tab[t];
                     tq[0] = tv.x;
                     tq[NTO > 1 ? 1 : 0] = NTO > 1 ? tv.y : tq[0];
                     tq[NTO > 2 ? 2 : 0] = NTO > 2 ? tv.z : tq[0];
@@ -516,12 +518,17 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
 #pragma unroll
                     for (int q = 0; q < NTO; ++q) tq[q] = tix[q];
                 }
+                // every row's taps read first (one LDS round trip), then summed in tap order
+                float tvq[RP][NTO];
+#pragma unroll
+                for (int b = 0; b < RP; ++b)
+#pragma unroll
+                    for (int q = 0; q < NTO; ++q) tvq[b][q] = s_T[b * TSZ + tq[q]];
 #pragma unroll
                 for (int b = 0; b < RP; ++b) {
                     float acc = 0.f;
 #pragma unroll
-                    for (int q = 0; q < NTO; ++q)
-                        acc += s_T[b * TSZ + tq[q]];
+                    for (int q = 0; q < NTO; ++q) acc += tvq[b][q];
                     lbp[b] = fminf(acc * lo_o, acc * hi_o);
                     mag[b] = fabsf(acc) * fmaxf(fabsf(lo_o), fabsf(hi_o));
                     const bool neg = acc < 0.f;
@@ -574,6 +581,9 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                 }
             }
         }
+        // the owned tile's adjoint gathers (written once in the prologue), read before the barrier
+        int4 gv4;
+        if constexpr (TAB) gv4 = s_tab[MBT + t];
         // block sums of the RP rows' bound terms (one barrier, which also publishes s_x)
         {
             float vals[3 * RP];
@@ -632,7 +642,6 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
             if (mt < MT) {
                 int gq[KSM];
                 if constexpr (TAB) {
-                    const int4 gv4 = s_tab[MBT + t];
                     gq[0] = gv4.x;
                     gq[KSM > 1 ? 1 : 0] = KSM > 1 ? gv4.y : gq[0];
                     gq[KSM > 2 ? 2 : 0] = KSM > 2 ? gv4.z : gq[0];
@@ -652,16 +661,20 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     }
                 }
             }
-            float gv[RP][4];
-            // the four relaxations and the bias in one LDS round trip
-            float4 rxa[4];
+            // O1: the four relaxations and the bias in one LDS round trip (otherwise each where
+            // it is used: fewer live registers)
+            float4 rxa[4], b1q;
+            if constexpr (O1) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) rxa[v] = relax(v);
-            const float4 b1q = s_b1[lk];
+                for (int v = 0; v < 4; ++v) rxa[v] = relax(v);
+                b1q = s_b1[lk];
+            }
+            float gv[RP][4];
+            if constexpr (!O1) b1q = s_b1[lk];
             const float b1g[4] = {b1q.x, b1q.y, b1q.z, b1q.w};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float4 rx = rxa[v];
+                const float4 rx = O1 ? rxa[v] : relax(v);
                 float sg = 0.f;
 #pragma unroll
                 for (int b = 0; b < RP; ++b) {
@@ -672,12 +685,13 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                     const float g = (neg ? rx.y : rx.x) * gh + (neg ? rx.z : 0.f);
                     if (b < nb) {
                         if (rx.z > 0.f && !neg) da[v] += p * gh;
-                        sg += g;
+                        if constexpr (O1) sg += g;
+                        else if (a.gsum_out && pv) s_sg[(4 * lk + v) * HoWo + pos] += g;
                     }
                     gv[b][v] = g;
                 }
-                // the rows' g in row order, one LDS update per neuron
-                if (a.gsum_out && pv) s_sg[(4 * lk + v) * HoWo + pos] += sg;
+                // O1: the rows' g in row order, one LDS update per neuron
+                if (O1 && a.gsum_out && pv) s_sg[(4 * lk + v) * HoWo + pos] += sg;
             }
             if constexpr (PFL) mf_drain(); else vmem_drain();
             if (a.Gout && pv) {
