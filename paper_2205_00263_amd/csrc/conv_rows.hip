@@ -270,14 +270,17 @@ __global__ __launch_bounds__(RT) void k_conv_rows(ConvRowsArgs a) {
                 for (int ky = 0; ky < a.k; ++ky)
                     for (int kx = 0; kx < a.k; ++kx) {
                         const int kb = (ky * a.k + kx) * a.Ci;
-                        const float* rt = rl + ky * a.Wq + kx;
+                        // the tap's row offset opaque to the compiler (one register, not one
+                        // induction register per read)
+                        int tb = ky * a.Wq + kx;
+                        asm volatile("" : "+v"(tb));
                         float av[C4][MT], bv[C4][NT];
 #pragma unroll
                         for (int c = 0; c < C4; ++c) {
 #pragma unroll
                             for (int m = 0; m < MT; ++m) av[c][m] = wrow[m][kb + 4 * c];
 #pragma unroll
-                            for (int j = 0; j < NT; ++j) bv[c][j] = rt[4 * c * HpWq + pb[j]];
+                            for (int j = 0; j < NT; ++j) bv[c][j] = rl[tb + pb[j] + 4 * c * HpWq];
                         }
 #pragma unroll
                         for (int c = 0; c < C4; ++c)
@@ -518,13 +521,18 @@ __global__ __launch_bounds__(PT, 4) void k_conv_pair(ConvRowsArgs a) {
                 for (int ky = 0; ky < a.k; ++ky)
                     for (int kx = 0; kx < a.k; ++kx) {
                         const int kb = (ky * a.k + kx) * a.Ci;
-                        const float* rt = rl + ky * a.Wq + kx;
+                        // the tap's row offset, opaque to the compiler: every read address is
+                        // then this plus a uniform channel offset, instead of one induction
+                        // register per (channel group, tile), and the tap's reads all fit in
+                        // registers at once
+                        int tb = ky * a.Wq + kx;
+                        asm volatile("" : "+v"(tb));
                         float av[C4], bv[C4][NT];
 #pragma unroll
                         for (int c = 0; c < C4; ++c) {
                             av[c] = wrow[kb + 4 * c];
 #pragma unroll
-                            for (int j = 0; j < NT; ++j) bv[c][j] = rt[4 * c * HpWq + pb[j]];
+                            for (int j = 0; j < NT; ++j) bv[c][j] = rl[tb + pb[j] + 4 * c * HpWq];
                         }
 #pragma unroll
                         for (int c = 0; c < C4; ++c)
