@@ -178,6 +178,19 @@ int mnb_set_params(mnb_problem* pb, int64_t id, int set, const float* alpha, con
  * g_gamma [n_relu * max_mnc]; each nullable.  Returns the row count in *rows. */
 int mnb_bound_grad(mnb_problem* pb, int64_t id, int set, int* rows, float* lb_rows, float* g_alpha,
                    float* g_beta, float* g_gamma);
+/* Branching scores of Section 3.4 from the multi-neuron constraints' Lagrange
+ * parameters: the active constraint score of neuron j of ReLU layer i,
+ * s_ij = |(gamma^T P)_j| + |(gamma^T Phat)_j| with gamma of set 0 (the spec
+ * rows) as it stands, for every unstable (l < 0 < u), unsplit neuron; with
+ * layer_weight [n_relu] (nullable: all 1; each finite and > 0) multiplied by
+ * layer_weight[i], which with the inverse split costs of Appendix B is cost
+ * adjusted branching.  scores [n][sum of ReLU widths] (host, nullable; -inf
+ * for non-candidates); branch_layer/branch_neuron [n] (nullable): the highest
+ * score, ties to the lowest (layer, neuron), -1 if the subproblem has no
+ * candidate.  MNB_EINVAL if the problem has no multi-neuron constraints or
+ * n > 65535.  Parameters and bounds are not modified. */
+int mnb_branch_scores(mnb_problem* pb, const int64_t* ids, int n, const float* layer_weight, float* scores,
+                      int32_t* branch_layer, int32_t* branch_neuron);
 /* Free subproblem slots. */
 int mnb_release(mnb_problem* pb, const int64_t* ids, int n);
 /* Slots in use / capacity. */

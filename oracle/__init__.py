@@ -15,5 +15,6 @@ Modules
     enum     -- exact minimum by activation-pattern enumeration
     mnc      -- exact 3-neuron ReLU hull constraints (MNC input data)
     cost     -- the split-cost model of Appendix B
+    branching -- active constraint score and cost adjusted branching (Section 3.4)
 """
-from . import net, backsub, optimize, bab, lp, enum, mnc, cost  # noqa: F401
+from . import net, backsub, optimize, bab, lp, enum, mnc, cost, branching  # noqa: F401

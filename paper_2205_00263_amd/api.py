@@ -287,6 +287,23 @@ class Problem:
                                    _ptr(gg)))
         return lbr[: rows.value], ga, gb, gg[: self.net.n_relu * self.max_mnc]
 
+    def branch_scores(self, ids, layer_weight=None, want_scores=False):
+        """Active constraint scores (Section 3.4) of the subproblems `ids` from their spec-row
+        gamma: the chosen (layer, neuron) per subproblem (-1 without a candidate) and, with
+        want_scores, the scores [n, sum of ReLU widths] (-inf for non-candidates).  layer_weight
+        [n_relu] multiplies layer i's scores; 1 / split_costs(...) gives cost adjusted branching."""
+        ids = np.ascontiguousarray(ids, np.int64)
+        n = len(ids)
+        w = None if layer_weight is None else _f32(layer_weight)
+        if w is not None and w.shape != (self.net.n_relu,):
+            raise ValueError("layer_weight needs one entry per ReLU layer")
+        sc = np.zeros((n, self.total_d), np.float32) if want_scores else None
+        bl = np.zeros(n, np.int32)
+        bn = np.zeros(n, np.int32)
+        check(lib().mnb_branch_scores(self.h, _ptr(ids, C.c_int64), n, _ptr(w) if w is not None else None,
+                                      _ptr(sc) if want_scores else None, _ptr(bl, C.c_int32), _ptr(bn, C.c_int32)))
+        return (bl, bn, sc) if want_scores else (bl, bn)
+
     def release(self, ids):
         ids = np.ascontiguousarray(ids, np.int64)
         check(lib().mnb_release(self.h, _ptr(ids, C.c_int64), len(ids)))
@@ -295,6 +312,42 @@ class Problem:
         u, c = C.c_int64(), C.c_int64()
         check(lib().mnb_problem_usage(self.h, C.byref(u), C.byref(c)))
         return u.value, c.value
+
+
+# --------------------------------------------------------------------------- split costs
+def split_costs(nodes, mnc_counts=None):
+    """Direct cost of a split in each ReLU layer, after Appendix B: the layers are the nodes after
+    the input, in order; a split in layer k costs sum over the later layers i of 2 d_i C_i, where
+    d_i is layer i's output width and C_i the sum of the back-substitution costs c_j of the layers
+    before it: d_j + p_j for a ReLU layer with p_j multi-neuron constraints, the weight count for
+    a fully connected layer, d_j k_j^2 for a convolution, and d_j for a residual addition (the
+    appendix gives no cost for it).  mnc_counts [n_relu] defaults to zeros.  Returns one float
+    per ReLU layer, for layer_weight = 1 / cost in Problem.branch_scores."""
+    from workloads import node_shapes  # shapes only
+    shapes = node_shapes(nodes)
+    layers = list(range(1, len(nodes)))
+    relus = [i for i in layers if nodes[i]["kind"] == "relu"]
+    p = list(mnc_counts) if mnc_counts is not None else [0] * len(relus)
+    if len(p) != len(relus):
+        raise ValueError("mnc_counts needs one entry per ReLU layer")
+    d = {i: int(np.prod(shapes[i])) for i in layers}
+    c = []
+    for i in layers:
+        kind = nodes[i]["kind"]
+        if kind == "relu":
+            c.append(d[i] + p[relus.index(i)])
+        elif kind == "fc":
+            c.append(int(np.asarray(nodes[i]["W"]).size))
+        elif kind == "conv":
+            c.append(d[i] * int(np.asarray(nodes[i]["W"]).shape[2]) ** 2)
+        else:
+            c.append(d[i])
+    prefix = np.concatenate([[0], np.cumsum(np.asarray(c, np.float64))])   # prefix[t] = sum of c over t layers
+    out = []
+    for r in relus:
+        k = layers.index(r)
+        out.append(float(sum(2.0 * d[layers[t]] * prefix[t] for t in range(k + 1, len(layers)))))
+    return out
 
 
 # --------------------------------------------------------------------------- kernel timer

@@ -150,6 +150,9 @@ void launch_score(const InstDesc* inst, int n_inst, const float* Ap, int d, cons
                   const int8_t* S, long ld_state, int state_off, float* score, long ld_score, int score_off,
                   hipStream_t st);
 void launch_argmax(const float* score, long ld, int n, int nb, int32_t* out, hipStream_t st);
+void launch_acs_score(const InstDesc* inst, int n_inst, const float* v, const float* vh, int d, const float* l,
+                      const float* u, const int8_t* S, long ld_state, int state_off, float w, float* score,
+                      long ld_score, int score_off, hipStream_t st);
 
 void launch_bits_to_x(const uint8_t* bits, const int32_t* row_slot, const int32_t* qid, const float* lo,
                       const float* hi, int d0, int M, float* X, hipStream_t st);

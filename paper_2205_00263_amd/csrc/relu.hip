@@ -561,6 +561,32 @@ void launch_score(const InstDesc* inst, int n_inst, const float* Ap, int d, cons
                        state_off, score, ld_score, score_off);
     MNB_HIP(hipGetLastError());
 }
+// Active constraint score (Section 3.4, multi-neuron constraint guided branching): the
+// sensitivity of the bound to the constraints that involve neuron j, through its output and
+// its input, s_j = |(gamma^T P)_j| + |(gamma^T Phat)_j| for unstable, unsplit j (v = P^T gamma and
+// vhat = Phat^T gamma come from k_gamma_proj), times the layer's weight (the inverse split cost
+// of cost adjusted branching, else 1); -inf elsewhere.
+__global__ void k_acs_score(const InstDesc* inst, const float* v, const float* vh, int d, const float* l,
+                            const float* u, const int8_t* S, long ld_state, int state_off, float w, float* score,
+                            long ld_score, int score_off) {
+    const InstDesc in = inst[blockIdx.y];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= d) return;
+    const long so = (long)in.slot * ld_state + state_off + j;
+    const float lj = l[so], uj = u[so];
+    const long vo = (long)blockIdx.y * d + j;
+    float sc = -INFINITY;
+    if (S[so] == 0 && lj < 0.f && uj > 0.f) sc = (fabsf(v[vo]) + fabsf(vh[vo])) * w;
+    score[(long)in.b * ld_score + score_off + j] = sc;
+}
+void launch_acs_score(const InstDesc* inst, int n_inst, const float* v, const float* vh, int d, const float* l,
+                      const float* u, const int8_t* S, long ld_state, int state_off, float w, float* score,
+                      long ld_score, int score_off, hipStream_t st) {
+    if (n_inst <= 0 || d <= 0) return;
+    hipLaunchKernelGGL(k_acs_score, dim3(cdiv(d, 256), n_inst), dim3(256), 0, st, inst, v, vh, d, l, u, S, ld_state,
+                       state_off, w, score, ld_score, score_off);
+    MNB_HIP(hipGetLastError());
+}
 // argmax per subproblem, ties to the lowest index; -1 if nothing finite
 __global__ void k_argmax(const float* score, long ld, int n, int32_t* out) {
     const int b = blockIdx.x;

@@ -39,3 +39,31 @@ def test_binding_declares_only_exported_symbols():
     lib = ctypes.CDLL(LIB)
     assert [n for n in _lib.exported_symbols() if not hasattr(lib, n)] == []
     assert set(_lib.exported_symbols()) == set(declared_functions())
+
+
+def test_split_costs_follow_appendix_b():
+    """The binding's per-layer split costs (host logic) against the oracle's cost model."""
+    import numpy as np
+    import workloads as W
+    from oracle import cost as ocost
+    from paper_2205_00263_amd import split_costs
+    for cfg in (1, 2):
+        wl = W.make_workload(cfg, scale="small")
+        nodes = wl.nodes
+        shapes = W.node_shapes(nodes)
+        layers, relu_pos = [], []
+        rng = np.random.default_rng(cfg)
+        p = []
+        for i in range(1, len(nodes)):
+            n = nodes[i]
+            d = int(np.prod(shapes[i]))
+            if n["kind"] == "relu":
+                p.append(int(rng.integers(0, 20)))
+                layers.append({"kind": "relu", "d": d, "p": p[-1]})
+                relu_pos.append(len(layers) - 1)
+            elif n["kind"] == "fc":
+                layers.append({"kind": "fc", "d": d, "nW": int(np.asarray(n["W"]).size)})
+            else:
+                layers.append({"kind": "conv", "d": d, "k": int(np.asarray(n["W"]).shape[2])})
+        got = split_costs(nodes, p)
+        assert got == [float(ocost.split_cost(layers, k)) for k in relu_pos]

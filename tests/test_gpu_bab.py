@@ -79,6 +79,73 @@ def test_mnc_gamma_parity(cfg):
         assert np.all(lb[b] <= sampled_min_sub(net_o, wl, S) + 1e-6)
 
 
+# --------------------------------------------------------------------------- branching scores
+@pytest.mark.parametrize("cfg", [3, 1])
+def test_branch_scores_match_oracle(cfg):
+    """Active constraint scores (and their cost adjusted form) of a root and two children after
+    4 Adam steps and with random feasible gamma, against the oracle evaluated on the GPU's own
+    gamma and bounds: the candidate
+    sets bit for bit, the scores to 1e-5 of the subproblem's largest, and the chosen neuron a
+    candidate whose score is the maximum (to the same tolerance)."""
+    from types import SimpleNamespace as NS
+    from oracle import branching as obr
+    P = _P()
+    wl = W.make_workload(cfg, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    mncs = omnc.generate(net_o, root.states, q.lo, q.hi, cap=60, max_groups=4)
+    oo.attach_mncs(q, root, mncs)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=32, max_mnc=60)
+    rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0, mncs=mnc_layers(net_o, mncs))
+    unst = root_unstable(net_o, root)
+    m0 = 0 if len(unst[0]) else 1
+    kids = pb.branch_split([rid], [m0], [int(unst[m0][0])])
+    ids = [rid] + [int(k) for k in kids]
+    pb.bound_optimize(ids, steps=4)
+    n_mnc = [mncs[i].e if i in mncs else 0 for i in net_o.relus]
+    # random feasible gamma in the spec set (the optimiser may leave it at zero on small nets)
+    rng = np.random.default_rng(17 + cfg)
+    for sid in ids:
+        gam = np.zeros(net.n_relu * 60, np.float32)
+        for t in range(net.n_relu):
+            gam[t * 60:t * 60 + n_mnc[t]] = rng.uniform(0, 0.3, n_mnc[t]) * (rng.uniform(size=n_mnc[t]) < 0.7)
+        pb.set_params(sid, 0, gamma=gam)
+    costs = P.split_costs(wl.nodes, n_mnc)
+    bl, bn, sc = pb.branch_scores(ids, want_scores=True)
+    cbl, cbn, csc = pb.branch_scores(ids, layer_weight=[1.0 / c for c in costs], want_scores=True)
+    offs = np.cumsum([0] + [net_o.sizes[i] for i in net_o.relus])
+    positive = 0
+    for b, sid in enumerate(ids):
+        _, _, g = pb.get_params(sid, 0)
+        states, fin = {}, {}
+        for t, i in enumerate(net_o.relus):
+            l, u, S = pb.get_bounds(sid, t)
+            states[i] = ob.ReluState(l.astype(np.float64), u.astype(np.float64), S)
+            fin[i] = {"gamma": g[t * 60:t * 60 + n_mnc[t]].astype(np.float64)}
+        ref = obr.acs_scores(net_o, NS(states=states, sets={"final": fin}), mncs)
+        cref = obr.cab_scores(ref, {i: costs[t] for t, i in enumerate(net_o.relus)})
+        for name, got, rr, L, J in (("acs", sc[b], ref, bl[b], bn[b]), ("cab", csc[b], cref, cbl[b], cbn[b])):
+            r = np.concatenate([rr[i] for i in net_o.relus])
+            fin_r = np.isfinite(r)
+            assert np.array_equal(np.isfinite(got), fin_r), (name, b, "candidate sets differ")
+            if not fin_r.any():
+                assert (L, J) == (-1, -1)
+                continue
+            top = np.abs(r[fin_r]).max()
+            tol = 1e-5 * top + 1e-30
+            assert np.all(np.abs(got[fin_r] - r[fin_r]) <= tol), (name, b, np.abs(got[fin_r] - r[fin_r]).max(), top)
+            assert L >= 0 and fin_r[offs[L] + J], (name, b, L, J)
+            assert r[offs[L] + J] >= r[fin_r].max() - 2 * tol, (name, b, L, J)
+            positive += int(top > 0)
+    assert positive > 0, "gamma stayed zero: the scores were never exercised"
+    # the call needs multi-neuron constraints
+    pb2 = P.Problem(net, n_spec=wl.C.shape[0], capacity=4)
+    rid2, _, _ = pb2.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    with pytest.raises(P.MnbError):
+        pb2.branch_scores([rid2])
+
+
 # --------------------------------------------------------------------------- BaB soundness / completeness
 def _gpu_bab(P, wl, steps=10, max_sub=2000):
     net = P.Net(wl.nodes)

@@ -415,3 +415,51 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(ob, "relu_backsub", no_intercept)
     bad = ob.backsub(net, {top: q.C[:1]}, q.c0[:1], root.states, res["params"], None, q.lo, q.hi)
     assert abs(bad["lb"][0] - res["value"]) > 1e-6
+
+
+# --------------------------------------------------------------------------- branching scores (Section 3.4)
+def _acs_case(gamma, S=(0, 0, 0), l=(-1.0, -1.0, -1.0), u=(1.0, 1.0, 1.0)):
+    from types import SimpleNamespace as NS
+    net = NS(relus=[2], sizes={2: 3})
+    m = ob.Mnc(P=[[1.0, -2.0, 0.0], [0.0, 1.0, 0.0]], Phat=[[0.0, 3.0, 0.0], [0.5, 0.0, 0.0]], p=[0.0, 0.0])
+    sub = NS(states={2: ob.ReluState(l, u, S)}, sets={"final": {2: {"gamma": np.asarray(gamma, float)}}})
+    return net, sub, {2: m}
+
+
+def test_acs_worked_example():
+    from oracle import branching as obr
+    # gamma = (0.5, 2): gamma^T P = (0.5, -1 + 2, 0) = (0.5, 1, 0); gamma^T Phat = (1, 1.5, 0)
+    net, sub, mncs = _acs_case([0.5, 2.0])
+    s = obr.acs_scores(net, sub, mncs)[2]
+    assert np.allclose(s, [1.5, 2.5, 0.0], rtol=0, atol=1e-15)
+    assert obr.select(net, {2: s}) == (0, 1)
+    # a split neuron and a stable one are no candidates
+    net, sub, mncs = _acs_case([0.5, 2.0], S=(0, 1, 0), l=(-1.0, -1.0, 0.5))
+    s = obr.acs_scores(net, sub, mncs)[2]
+    assert s[0] == 1.5 and np.isneginf(s[1]) and np.isneginf(s[2])
+    assert obr.select(net, {2: s}) == (0, 0)
+
+
+def test_acs_invariants():
+    from oracle import branching as obr
+    # gamma = 0 scores every candidate 0 (the lowest index is chosen); positive scaling of gamma
+    # scales every score; the sign of gamma does not matter (absolute values)
+    net, sub, mncs = _acs_case([0.0, 0.0])
+    s0 = obr.acs_scores(net, sub, mncs)[2]
+    assert np.all(s0 == 0.0) and obr.select(net, {2: s0}) == (0, 0)
+    base = obr.acs_scores(*_acs_case([0.3, 0.7]))[2]
+    assert np.allclose(obr.acs_scores(*_acs_case([0.9, 2.1]))[2], 3.0 * base, rtol=1e-14, atol=0)
+    assert np.allclose(obr.acs_scores(*_acs_case([-0.3, -0.7]))[2], base, rtol=1e-14, atol=0)
+    # no candidate at all
+    net, sub, mncs = _acs_case([1.0, 1.0], l=(0.1, 0.2, 0.3))
+    assert obr.select(net, obr.acs_scores(net, sub, mncs)) == (-1, -1)
+
+
+def test_cab_changes_the_choice_with_cost():
+    from types import SimpleNamespace as NS
+    from oracle import branching as obr
+    net = NS(relus=[2, 4])
+    scores = {2: np.array([2.0, -np.inf]), 4: np.array([1.5, 0.5])}
+    assert obr.select(net, scores) == (0, 0)
+    # 2.0 / 100 = 0.02 < 1.5 / 10 = 0.15
+    assert obr.select(net, obr.cab_scores(scores, {2: 100.0, 4: 10.0})) == (1, 0)
