@@ -7,7 +7,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <cmath>
 #include <atomic>
 #include <numeric>
 #include <set>
