@@ -82,6 +82,13 @@ struct mnb_net {
     ~mnb_net();
 };
 
+namespace mnb {
+// Active constraint branching adjusted by the split costs of Appendix B (Section 3.4) for the
+// subproblems ids: chosen layer / neuron (-1 without a candidate) and its score per subproblem.
+// Returns an MNB status code (MNB_EINVAL without multi-neuron constraints).
+int branch_acs_cab(mnb_problem* pb, const int64_t* ids, int n, int32_t* layer, int32_t* neuron, float* best);
+}  // namespace mnb
+
 struct mnb_problem {
     mnb_net* net = nullptr;
     int S = 0, R = 0, n_sets = 0, e_cap = 0;

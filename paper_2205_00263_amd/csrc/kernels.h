@@ -150,6 +150,7 @@ void launch_score(const InstDesc* inst, int n_inst, const float* Ap, int d, cons
                   const int8_t* S, long ld_state, int state_off, float* score, long ld_score, int score_off,
                   hipStream_t st);
 void launch_argmax(const float* score, long ld, int n, int nb, int32_t* out, hipStream_t st);
+void launch_pick(const float* score, long ld, const int32_t* arg, int n, float* out, hipStream_t st);
 void launch_acs_score(const InstDesc* inst, int n_inst, const float* v, const float* vh, int d, const float* l,
                       const float* u, const int8_t* S, long ld_state, int state_off, float w, float* score,
                       long ld_score, int score_off, hipStream_t st);

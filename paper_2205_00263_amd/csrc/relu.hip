@@ -587,6 +587,16 @@ void launch_acs_score(const InstDesc* inst, int n_inst, const float* v, const fl
                        state_off, w, score, ld_score, score_off);
     MNB_HIP(hipGetLastError());
 }
+// the score at each subproblem's argmax (-inf where there is none)
+__global__ void k_pick(const float* score, long ld, const int32_t* arg, int n, float* out) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b < n) out[b] = arg[b] >= 0 ? score[(long)b * ld + arg[b]] : -INFINITY;
+}
+void launch_pick(const float* score, long ld, const int32_t* arg, int n, float* out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pick, dim3(cdiv(n, 256)), dim3(256), 0, st, score, ld, arg, n, out);
+    MNB_HIP(hipGetLastError());
+}
 // argmax per subproblem, ties to the lowest index; -1 if nothing finite
 __global__ void k_argmax(const float* score, long ld, int n, int32_t* out) {
     const int b = blockIdx.x;

@@ -256,6 +256,19 @@ void mnb_server::run() {
                 }
                 continue;
             }
+            if (pb->has_mnc) {
+                // with multi-neuron constraints: cost adjusted active constraint branching
+                // (Section 3.4); a subproblem whose constraints carry no weight (score 0, e.g. a
+                // query without constraints) keeps the alpha-contribution choice
+                std::vector<int32_t> al(n), an(n);
+                std::vector<float> as(n);
+                if (mnb::branch_acs_cab(pb, ids.data(), n, al.data(), an.data(), as.data()) == MNB_OK)
+                    for (int b = 0; b < n; ++b)
+                        if (al[b] >= 0 && as[b] > 0.f) {
+                            bl[b] = al[b];
+                            bn[b] = an[b];
+                        }
+            }
             std::vector<int64_t> par, rel;
             std::vector<int32_t> lay, neu;
             std::vector<Live*> par_owner;

@@ -257,3 +257,42 @@ def test_serving_alone_equals_mix():
         if a["verdict"] == "verified":
             assert a["subproblems"] == m["subproblems"]
     assert sum(a["subproblems"] > 2 for a in alone) >= 4   # branching happened
+
+
+def test_serving_with_mnc_is_sound_and_complete():
+    """Queries that carry multi-neuron constraints are branched in the server by cost adjusted
+    active constraint scores; their verdicts against the exact minimum (activation-pattern
+    enumeration) on the tiny nets: never verified below zero nor falsified above it, and most
+    positive ones verified (a leaf whose neurons are all split can still end UNKNOWN: its split
+    constraints are enforced through beta after a fixed number of Adam steps, not exactly)."""
+    P = _P()
+    nets, qs = [], []
+    for (sd, eps) in HARD[:6]:
+        nodes = W.tiny_fc(sd, (3, 6, 5, 2))
+        x0, lo, hi = W.make_input(nodes[0]["shape"], eps, 40 + sd)
+        Cm, c0, _ = W.make_spec(nodes, x0)
+        net_o = onet.Net(nodes)
+        q = oo.Query(net_o, lo, hi, Cm, c0)
+        root, _ = oo.root_pass(q)
+        mncs = omnc.generate(net_o, root.states, q.lo, q.hi, cap=60, max_groups=4)
+        top = len(nodes) - 1
+        exact = min(oen.exact_min(net_o, lo, hi, {top: Cm[r].astype(np.float64)}, float(c0[r]))[0]
+                    for r in range(Cm.shape[0]))
+        nets.append(nodes)
+        qs.append((len(nets) - 1, lo, hi, Cm, c0, mnc_layers(net_o, mncs), exact, sum(m.e for m in mncs.values())))
+    srv = P.Server([P.Net(n) for n in nets], max_batch=64, steps=10)
+    tickets = [srv.query_submit(ni, lo, hi, Cm, c0, mncs=mm, timeout_s=120) for (ni, lo, hi, Cm, c0, mm, _, _) in qs]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    with_mnc = positive = verified = 0
+    for r, (_, _, _, _, _, _, exact, ne) in zip(res, qs):
+        print(r["verdict"], r["subproblems"], exact, ne, flush=True)
+        if exact < -1e-6:
+            assert r["verdict"] != "verified"
+        elif exact > 1e-4:
+            assert r["verdict"] != "falsified"
+            positive += 1
+            verified += r["verdict"] == "verified"
+        with_mnc += ne > 0
+    assert with_mnc >= 3
+    assert verified * 2 >= positive, (verified, positive)
