@@ -463,3 +463,94 @@ def test_cab_changes_the_choice_with_cost():
     assert obr.select(net, scores) == (0, 0)
     # 2.0 / 100 = 0.02 < 1.5 / 10 = 0.15
     assert obr.select(net, obr.cab_scores(scores, {2: 100.0, 4: 10.0})) == (1, 0)
+
+
+# --------------------------------------------------------------------------- Adam (Section 3.1 optimiser)
+def test_adam_matches_torch_optim_adam():
+    """The oracle's Adam ascent equals torch.optim.Adam(maximize=True) (bias-corrected, eps outside
+    the square root) on a fixed gradient sequence, in float64, for several hyper-parameters."""
+    import torch
+    rng = np.random.default_rng(7)
+    for lr, b1, b2, eps in ((0.1, 0.9, 0.999, 1e-8), (0.03, 0.5, 0.9, 1e-3), (1.0, 0.0, 0.99, 1e-6)):
+        p0 = {"a": rng.normal(size=5), "b": rng.normal(size=(2, 3))}
+        grads = [{k: rng.normal(size=v.shape) * 10.0 ** rng.integers(-3, 3) for k, v in p0.items()}
+                 for _ in range(12)]
+        params = {k: v.copy() for k, v in p0.items()}
+        opt = oo.Adam(lr, b1, b2, eps)
+        tp = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p0.items()}
+        topt = torch.optim.Adam(list(tp.values()), lr=lr, betas=(b1, b2), eps=eps, maximize=True)
+        for g in grads:
+            opt.step(params, g)
+            topt.zero_grad()
+            for k, t in tp.items():
+                t.grad = torch.tensor(g[k], dtype=torch.float64)
+            topt.step()
+            for k in p0:
+                np.testing.assert_allclose(params[k], tp[k].detach().numpy(), rtol=0, atol=1e-12)
+
+
+def test_adam_first_step_hand_computed():
+    """After one step the bias-corrected moments are g and g^2, so the ascent is lr * g / (|g| + eps)."""
+    g = np.array([2.0, -0.5, 0.0])
+    p = {"x": np.array([1.0, 1.0, 1.0])}
+    oo.Adam(lr=0.1, beta1=0.9, beta2=0.999, eps=1e-8).step(p, {"x": g})
+    np.testing.assert_allclose(p["x"], [1.0 + 0.1 * 2.0 / (2.0 + 1e-8), 1.0 - 0.1 * 0.5 / (0.5 + 1e-8), 1.0],
+                               rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------- alpha-contribution branching score
+def _score_net():
+    """input 2 -> fc 3 -> relu -> fc 2 -> relu -> fc 1, weights chosen so every a' is hand-computable."""
+    W1 = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    W2 = np.array([[4.0, 1.0, 10.0], [0.0, 0.0, 0.0]])
+    W3 = np.array([[2.0, -4.0]])
+    nodes = [{"kind": "input", "shape": (2, 1, 1)},
+             {"kind": "fc", "src": 0, "W": W1, "b": np.zeros(3)}, {"kind": "relu", "src": 1},
+             {"kind": "fc", "src": 2, "W": W2, "b": np.zeros(2)}, {"kind": "relu", "src": 3},
+             {"kind": "fc", "src": 4, "W": W3, "b": np.zeros(1)}]
+    net = onet.Net(nodes)
+    # ReLU layer 0: all unstable, triangle heights -u l / (u - l) = 0.5, 0.5, 1; neuron 2 split positive
+    s0 = ob.ReluState([-1.0, -1.0, 0.0], [1.0, 1.0, 2.0], S=[0, 0, -1])
+    # ReLU layer 1: heights 3/4 and 1/2
+    s1 = ob.ReluState([-1.0, -1.0], [3.0, 1.0])
+    states = {2: s0, 4: s1}
+    params = {2: {"alpha": np.full(3, 0.5), "beta": np.zeros(3)}, 4: {"alpha": np.full(2, 0.5), "beta": np.zeros(2)}}
+    return net, states, params
+
+
+def test_branching_score_hand_worked():
+    """One spec row C = [1]: a' on ReLU layer 1 is W3 = [2, -4] (scores 2 * 3/4, 4 * 1/2); the row
+    crosses it with D = (alpha, chord) = (0.5, 0.5), so a' on ReLU layer 0 is [1, -2] W2 = [4, 1, 10]
+    (scores 4 * 0.5, 1 * 0.5, and none for the split neuron whose unsplit score would be 10).  The
+    two maxima 2.0 tie between (layer 0, neuron 0) and (layer 1, neuron 1): the lowest layer wins."""
+    net, states, params = _score_net()
+    sub = oo.Subproblem(states, {}, None, None, recompute_from=2)
+    out = ob.backsub(net, ob.spec_start(net, [[1.0]]), [0.0], states, params)
+    np.testing.assert_allclose(out["records"][4]["ap"], [[2.0, -4.0]], atol=0)
+    np.testing.assert_allclose(out["records"][2]["ap"], [[4.0, 1.0, 10.0]], atol=0)
+    sc = obab.branching_score(net, sub, out["records"])
+    np.testing.assert_allclose(sc[0], [2.0, 0.5, -np.inf], atol=0)
+    np.testing.assert_allclose(sc[1], [1.5, 2.0], atol=0)
+    assert obab.pick_branch(sc) == (0, 0)
+    # a stable neuron is not a candidate: with l_0 >= 0 in layer 0 the other maximum is chosen
+    states[2] = ob.ReluState([0.0, -1.0, 0.0], [1.0, 1.0, 2.0], S=[0, 0, -1])
+    out = ob.backsub(net, ob.spec_start(net, [[1.0]]), [0.0], states, params)
+    sc = obab.branching_score(net, oo.Subproblem(states, {}, None, None, 2), out["records"])
+    assert sc[0][0] == -np.inf and obab.pick_branch(sc) == (1, 1)
+
+
+def test_branching_score_sums_spec_rows():
+    """Two spec rows C = [1], [-1]: the second row has a' = [-2, 4] on ReLU layer 1, crosses it with
+    D = (chord 3/4, alpha 0.5), giving a' = [-1.5, 2] W2 = [-6, -1.5, -15] on layer 0.  Scores are
+    sums of |a'| over the rows times the height: layer 0 (4+6)/2, (1+1.5)/2; layer 1 (2+2)*3/4, (4+4)/2."""
+    net, states, params = _score_net()
+    out = ob.backsub(net, ob.spec_start(net, [[1.0], [-1.0]]), [0.0, 0.0], states, params)
+    np.testing.assert_allclose(out["records"][2]["ap"][1], [-6.0, -1.5, -15.0], atol=0)
+    sc = obab.branching_score(net, oo.Subproblem(states, {}, None, None, 2), out["records"])
+    np.testing.assert_allclose(sc[0], [5.0, 1.25, -np.inf], atol=0)
+    np.testing.assert_allclose(sc[1], [3.0, 4.0], atol=0)
+    assert obab.pick_branch(sc) == (0, 0)
+    # nothing eligible: every neuron stable or split
+    st = {2: ob.ReluState([0.0, 0.0, 0.0], [1.0, 1.0, 2.0]), 4: ob.ReluState([1.0, -2.0], [3.0, -1.0])}
+    out = ob.backsub(net, ob.spec_start(net, [[1.0]]), [0.0], st, params)
+    assert obab.pick_branch(obab.branching_score(net, oo.Subproblem(st, {}, None, None, 2), out["records"])) is None
