@@ -22,12 +22,12 @@ Readings where the paper is loose (each listed in the design notes):
 * on a residual join the coefficient is passed unchanged to both operands and
   the contributions meeting at a common producer are summed (linearity).
 
-Optional rounding margin (`margin`, default 0 = the exact bound of Eq. 6): a
-sound FP32 implementation lowers every concretised bound by
-margin * (sum_j |a_j| max(|lo_j|, |hi_j|) + |c|) to cover its own rounding; with
-the margin set, this oracle computes that bound in FP64, so that nets deep
-enough for the loosened intermediate bounds to compound can be compared with
-such an implementation element by element.
+Optional rounding margin (`margin`, default 0 = the exact bound of Eq. 6): an
+FP32 implementation may lower the bounds it reports by
+margin * (sum_j |a_j| max(|lo_j|, |hi_j|) + |c|) to cover its own rounding
+where the bound is exact; with the margin set, this oracle computes that
+bound in FP64.  The optimiser applies it to the spec rows only (the reported
+lower bounds); intermediate bounds are the exact values of Eq. 6.
 
 Parameter arrays may be shared by all rows of a set (shape [d]) or per row
 (shape [R, d]); numpy broadcasting covers both.

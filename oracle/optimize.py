@@ -112,7 +112,7 @@ class Query:
 
     def __init__(self, net, lo, hi, C, c0, mncs=None, margin=0.0):
         self.net = net
-        self.margin = float(margin)   # rounding margin of every concretisation (0: exact Eq. 6)
+        self.margin = float(margin)   # rounding margin of the reported spec-row bounds (0: exact Eq. 6)
         self.lo = np.asarray(lo, dtype=np.float64)
         self.hi = np.asarray(hi, dtype=np.float64)
         self.C = np.asarray(C, dtype=np.float64)
@@ -207,9 +207,9 @@ def root_pass(q: Query):
                 params = {k: {"alpha": heuristic_alpha(s), "beta": np.zeros(s.l.shape)}
                           for k, s in states.items()}
                 lo_out = backsub(net, neuron_start(net, i, js, +1), np.zeros(len(js)),
-                                 states, params, None, q.lo, q.hi, q.margin)
+                                 states, params, None, q.lo, q.hi)
                 up_out = backsub(net, neuron_start(net, i, js, -1), np.zeros(len(js)),
-                                 states, params, None, q.lo, q.hi, q.margin)
+                                 states, params, None, q.lo, q.hi)
                 l[js] = np.maximum(l[js], lo_out["lb"])
                 u[js] = np.minimum(u[js], -up_out["lb"])
         states[i] = ReluState(l, u)
@@ -269,7 +269,7 @@ def bound_optimize(q: Query, sub: Subproblem, steps=20, lr=0.1, beta1=0.9, beta2
                 continue
             for s in (1, -1):
                 outs[(m, s)] = backsub(net, neuron_start(net, i, js, s), np.zeros(len(js)),
-                                       sub.states, sub.sets[(m, s)], q.mncs, q.lo, q.hi, q.margin)
+                                       sub.states, sub.sets[(m, s)], q.mncs, q.lo, q.hi)
             st = sub.states[i]
             st.l[js] = np.maximum(st.l[js], outs[(m, 1)]["lb"])
             st.u[js] = np.minimum(st.u[js], -outs[(m, -1)]["lb"])

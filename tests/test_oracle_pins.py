@@ -116,20 +116,33 @@ def test_rounding_margin_closed_form():
 
 
 def test_rounding_margin_only_loosens():
-    """On a residual net the margin lowers every lower bound and raises every upper bound (the
-    intermediate bounds compound), and a zero margin is the exact pass bit for bit."""
+    """On a residual net the margin touches only the reported spec-row bounds: every intermediate
+    bound is the exact pass's bit for bit, and each reported lb is the exact one lowered by the
+    closed-form margin of its own final row (Eq. 6 with a^(0), c of the exact pass).  A zero margin
+    is the exact pass bit for bit, also through optimisation."""
     wl = W.make_workload(4, scale="small")
     net = onet.Net(wl.nodes)
-    ex, _ = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0))
+    ex, out = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0))
     z, _ = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, margin=0.0))
-    mg, _ = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, margin=2.0 ** -12))
+    m = 2.0 ** -12
+    mg, _ = oo.root_pass(oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, margin=m))
     assert np.array_equal(z.lb, ex.lb)
-    assert np.all(mg.lb < ex.lb)
     for i in net.relus:
-        assert np.all(mg.states[i].l <= ex.states[i].l) and np.all(mg.states[i].u >= ex.states[i].u)
-        assert np.array_equal(z.states[i].l, ex.states[i].l)
-    # past the first ReLU layer (an interval), some intermediate bound moves
-    assert any(np.any(mg.states[i].l < ex.states[i].l) for i in net.relus[1:])
+        assert np.array_equal(mg.states[i].l, ex.states[i].l) and np.array_equal(mg.states[i].u, ex.states[i].u)
+    lo, hi = np.asarray(wl.lo, np.float64), np.asarray(wl.hi, np.float64)
+    delta = m * (np.abs(out["a0"]) @ np.maximum(np.abs(lo), np.abs(hi)) + np.abs(out["c"]))
+    np.testing.assert_allclose(mg.lb, ex.lb - delta, rtol=0, atol=1e-12)
+    assert np.all(mg.lb < ex.lb)
+    # through optimisation with splits: intermediate bounds equal, reported bounds only lower
+    st0 = ex.states[net.relus[0]]
+    j = int(np.nonzero((st0.l < 0) & (st0.u > 0))[0][0])
+    qe = oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0)
+    qm = oo.Query(net, wl.lo, wl.hi, wl.C, wl.c0, margin=m)
+    ce = oo.bound_optimize(qe, obab.branch_split(net, ex.clone(), 0, j)[0], steps=2)
+    cm = oo.bound_optimize(qm, obab.branch_split(net, mg.clone(), 0, j)[0], steps=2)
+    for i in net.relus:
+        assert np.array_equal(ce.states[i].l, cm.states[i].l) and np.array_equal(ce.states[i].u, cm.states[i].u)
+    assert np.all(cm.lb <= ce.lb)
 
 
 @pytest.mark.parametrize("seed", range(4))
