@@ -88,6 +88,18 @@ int mnb_net_create(const mnb_layer* layers, int n_layers, mnb_net** out);
 void mnb_net_destroy(mnb_net* net);
 /* Number of ReLU layers and their widths (caller array of n_relu ints). */
 int mnb_net_info(const mnb_net* net, int* n_relu, int* relu_sizes, int* d_in, int* d_out);
+/* Direct cost of a split in each ReLU layer (Appendix B, the cost model of cost
+ * adjusted branching, Section 3.4): for a split in layer k, the sum over the
+ * later layers i (the nodes after the input, in order) of 2 d_i C_i, where d_i
+ * is layer i's output width and C_i the sum of the back-substitution costs c_j
+ * of the layers before i: d_j + p_j for a ReLU layer with p_j multi-neuron
+ * constraints, the weight count for a fully connected layer, d_j k_j^2 for a
+ * convolution, and d_j for a residual addition (the appendix lists no cost for
+ * it).  layers: the node list of mnb_net_create (only kinds, src and shapes
+ * are read; no device work, so the call also works without a GPU);
+ * mnc_counts [n_relu] (nullable: all 0, else each >= 0); costs [n_relu] out.
+ * 1 / cost per layer is the layer_weight of mnb_branch_scores. */
+int mnb_split_costs(const mnb_layer* layers, int n_layers, const int32_t* mnc_counts, double* costs);
 
 /* ------------------------------------------------------------------ multi-neuron constraints */
 /* Constraints  P z + Phat zhat <= p  over the output z and input zhat of ReLU
@@ -178,19 +190,45 @@ int mnb_set_params(mnb_problem* pb, int64_t id, int set, const float* alpha, con
  * g_gamma [n_relu * max_mnc]; each nullable.  Returns the row count in *rows. */
 int mnb_bound_grad(mnb_problem* pb, int64_t id, int set, int* rows, float* lb_rows, float* g_alpha,
                    float* g_beta, float* g_gamma);
+/* The same two calls on DEVICE pointers (for callers that keep the parameters
+ * in device memory, e.g. behind torch.autograd.Function): mnb_set_params_device
+ * copies alpha/beta/gamma device-to-device on the library stream;
+ * mnb_bound_grad_device writes lb_rows (capacity: n_spec for set 0, else the
+ * width of the set's ReLU layer), g_alpha, g_beta and g_gamma into device
+ * arrays on the library stream.  Both return once the copies are done; the
+ * caller orders its own stream's writes before the call (same stream via
+ * mnb_set_stream, or a synchronisation). */
+int mnb_set_params_device(mnb_problem* pb, int64_t id, int set, const float* alpha, const float* beta,
+                          const float* gamma);
+int mnb_bound_grad_device(mnb_problem* pb, int64_t id, int set, int* rows, float* lb_rows, float* g_alpha,
+                          float* g_beta, float* g_gamma);
 /* Branching scores of Section 3.4 from the multi-neuron constraints' Lagrange
  * parameters: the active constraint score of neuron j of ReLU layer i,
  * s_ij = |(gamma^T P)_j| + |(gamma^T Phat)_j| with gamma of set 0 (the spec
  * rows) as it stands, for every unstable (l < 0 < u), unsplit neuron; with
  * layer_weight [n_relu] (nullable: all 1; each finite and > 0) multiplied by
  * layer_weight[i], which with the inverse split costs of Appendix B is cost
- * adjusted branching.  scores [n][sum of ReLU widths] (host, nullable; -inf
+ * adjusted branching (mnb_split_costs).  scores [n][sum of ReLU widths] (host, nullable; -inf
  * for non-candidates); branch_layer/branch_neuron [n] (nullable): the highest
  * score, ties to the lowest (layer, neuron), -1 if the subproblem has no
  * candidate.  MNB_EINVAL if the problem has no multi-neuron constraints or
  * n > 65535.  Parameters and bounds are not modified. */
 int mnb_branch_scores(mnb_problem* pb, const int64_t* ids, int n, const float* layer_weight, float* scores,
                       int32_t* branch_layer, int32_t* branch_neuron);
+/* The alpha-contribution branching score that bound_optimize's branch_layer /
+ * branch_neuron choose by (Section 3.2 splits an unstable ReLU; the score reads
+ * the bound's sensitivity to each unstable, unsplit neuron times the height of
+ * its triangle relaxation, Eq. 5): s_ij = sum over spec rows of |a'_j| *
+ * (-u_j l_j / (u_j - l_j)), with a' the spec rows' coefficients on ReLU layer i
+ * evaluated at the subproblems' current parameters (set 0) and bounds (no
+ * recompute, nothing is written).  Right after bound_optimize these are the
+ * parameters and bounds of its last evaluation, so the choice is the one it
+ * returned.  scores [n][sum of ReLU widths] (host, nullable; -inf for
+ * non-candidates); branch_layer/branch_neuron [n] (nullable): the highest score,
+ * ties to the lowest (layer, neuron), -1 without a candidate.  MNB_EINVAL for
+ * duplicate or invalid ids or n > 65535. */
+int mnb_contribution_scores(mnb_problem* pb, const int64_t* ids, int n, float* scores,
+                            int32_t* branch_layer, int32_t* branch_neuron);
 /* Free subproblem slots. */
 int mnb_release(mnb_problem* pb, const int64_t* ids, int n);
 /* Slots in use / capacity. */

@@ -72,7 +72,12 @@ _SIGS = {
     "mnb_get_params": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, fp, fp, fp]),
     "mnb_set_params": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, fp, fp, fp]),
     "mnb_bound_grad": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_int), fp, fp, fp, fp]),
+    "mnb_set_params_device": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mnb_bound_grad_device": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_int), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]),
     "mnb_branch_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, fp, ip32, ip32]),
+    "mnb_contribution_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, ip32, ip32]),
+    "mnb_split_costs": (C.c_int, [C.POINTER(Layer), C.c_int, ip32, C.POINTER(C.c_double)]),
     "mnb_release": (C.c_int, [C.c_void_p, ip64, C.c_int]),
     "mnb_problem_usage": (C.c_int, [C.c_void_p, ip64, ip64]),
     "mnb_kernel_fc_backsub": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int]),

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import check, lib
 
 __all__ = ["Net", "Problem", "use_torch_plumbing", "mnc_to_csr", "set_index", "set_kernel_variants",
-           "get_kernel_variants", "VARIANTS"]
+           "get_kernel_variants", "VARIANTS", "split_costs"]
 
 
 def _f32(a):
@@ -66,32 +66,53 @@ def use_torch_plumbing(enable=True):
 
 
 # --------------------------------------------------------------------------- network
+def _layer_array(nodes):
+    """ctypes array of mnb_layer for a node list (workloads format) and the buffers it points into."""
+    from workloads import node_shapes  # shapes only
+    shapes = node_shapes(nodes)
+    arr = (_lib.Layer * len(nodes))()
+    keep = []
+    kinds = {"input": _lib.MNB_INPUT, "fc": _lib.MNB_FC, "conv": _lib.MNB_CONV,
+             "relu": _lib.MNB_RELU, "add": _lib.MNB_ADD}
+    for i, n in enumerate(nodes):
+        L = arr[i]
+        L.kind = kinds[n["kind"]]
+        L.src = n.get("src", -1)
+        L.src2 = n.get("src2", -1)
+        for t in range(3):
+            L.out_chw[t] = shapes[i][t]
+            if i > 0:
+                L.in_chw[t] = shapes[n["src"]][t]
+        if n["kind"] in ("fc", "conv"):
+            W, b = _f32(n["W"]), _f32(n["b"])
+            keep += [W, b]
+            L.W, L.b = _ptr(W), _ptr(b)
+        if n["kind"] == "conv":
+            L.k = n["W"].shape[2]
+            L.stride, L.pad = n["stride"], n["pad"]
+    return arr, keep
+
+
+def split_costs(nodes, mnc_counts=None):
+    """mnb_split_costs: direct split cost of each ReLU layer (Appendix B) of a node list, with
+    mnc_counts [n_relu] multi-neuron constraints per layer (None: none); 1 / cost is a layer weight
+    of Problem.branch_scores.  Host-only call of the library (no GPU needed)."""
+    arr, _keep = _layer_array(nodes)
+    n_relu = sum(1 for n in nodes if n["kind"] == "relu")
+    p = None if mnc_counts is None else np.ascontiguousarray(mnc_counts, np.int32)
+    if p is not None and p.shape != (n_relu,):
+        raise ValueError("mnc_counts needs one entry per ReLU layer")
+    out = np.zeros(n_relu, np.float64)
+    check(lib().mnb_split_costs(arr, len(nodes), _ptr(p, C.c_int32) if p is not None else None,
+                                out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
 class Net:
     """A network (node list in the workloads format) copied to the device."""
 
     def __init__(self, nodes):
-        from workloads import node_shapes  # shapes only
-        shapes = node_shapes(nodes)
-        arr = (_lib.Layer * len(nodes))()
-        keep = []
-        kinds = {"input": _lib.MNB_INPUT, "fc": _lib.MNB_FC, "conv": _lib.MNB_CONV,
-                 "relu": _lib.MNB_RELU, "add": _lib.MNB_ADD}
-        for i, n in enumerate(nodes):
-            L = arr[i]
-            L.kind = kinds[n["kind"]]
-            L.src = n.get("src", -1)
-            L.src2 = n.get("src2", -1)
-            for t in range(3):
-                L.out_chw[t] = shapes[i][t]
-                if i > 0:
-                    L.in_chw[t] = shapes[n["src"]][t]
-            if n["kind"] in ("fc", "conv"):
-                W, b = _f32(n["W"]), _f32(n["b"])
-                keep += [W, b]
-                L.W, L.b = _ptr(W), _ptr(b)
-            if n["kind"] == "conv":
-                L.k = n["W"].shape[2]
-                L.stride, L.pad = n["stride"], n["pad"]
+        arr, keep = _layer_array(nodes)
         h = C.c_void_p()
         check(lib().mnb_net_create(arr, len(nodes), C.byref(h)))
         self.h = h
@@ -107,6 +128,10 @@ class Net:
     @property
     def n_relu(self):
         return len(self.relu_sizes)
+
+    def split_costs(self, mnc_counts=None):
+        """split_costs of this net's node list."""
+        return split_costs(self.nodes, mnc_counts)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -277,6 +302,19 @@ class Problem:
         check(lib().mnb_set_params(self.h, int(sid), int(set_idx), _ptr(a) if a is not None else None,
                                    _ptr(b) if b is not None else None, _ptr(g) if g is not None else None))
 
+    def set_params_device(self, sid, set_idx, alpha_ptr=0, beta_ptr=0, gamma_ptr=0):
+        """mnb_set_params_device: parameters from device arrays (pointers, 0 = leave unchanged)."""
+        v = lambda p: C.c_void_p(p) if p else None
+        check(lib().mnb_set_params_device(self.h, int(sid), int(set_idx), v(alpha_ptr), v(beta_ptr), v(gamma_ptr)))
+
+    def bound_grad_device(self, sid, set_idx, lb_ptr=0, ga_ptr=0, gb_ptr=0, gg_ptr=0):
+        """mnb_bound_grad_device: row bounds and gradients into device arrays; returns the row count."""
+        v = lambda p: C.c_void_p(p) if p else None
+        rows = C.c_int()
+        check(lib().mnb_bound_grad_device(self.h, int(sid), int(set_idx), C.byref(rows), v(lb_ptr), v(ga_ptr),
+                                          v(gb_ptr), v(gg_ptr)))
+        return rows.value
+
     def bound_grad(self, sid, set_idx):
         rows = C.c_int()
         lbr = np.zeros(max(self.S, max(self.net.relu_sizes) * 1), np.float32)
@@ -304,6 +342,19 @@ class Problem:
                                       _ptr(sc) if want_scores else None, _ptr(bl, C.c_int32), _ptr(bn, C.c_int32)))
         return (bl, bn, sc) if want_scores else (bl, bn)
 
+    def contribution_scores(self, ids, want_scores=True):
+        """mnb_contribution_scores: the alpha-contribution branching scores of bound_optimize at the
+        subproblems' current parameters and bounds: (layer, neuron) per subproblem and, with
+        want_scores, the scores [n, sum of ReLU widths] (-inf for non-candidates)."""
+        ids = np.ascontiguousarray(ids, np.int64)
+        n = len(ids)
+        sc = np.zeros((n, self.total_d), np.float32) if want_scores else None
+        bl = np.zeros(n, np.int32)
+        bn = np.zeros(n, np.int32)
+        check(lib().mnb_contribution_scores(self.h, _ptr(ids, C.c_int64), n, _ptr(sc) if want_scores else None,
+                                            _ptr(bl, C.c_int32), _ptr(bn, C.c_int32)))
+        return (bl, bn, sc) if want_scores else (bl, bn)
+
     def release(self, ids):
         ids = np.ascontiguousarray(ids, np.int64)
         check(lib().mnb_release(self.h, _ptr(ids, C.c_int64), len(ids)))
@@ -312,42 +363,6 @@ class Problem:
         u, c = C.c_int64(), C.c_int64()
         check(lib().mnb_problem_usage(self.h, C.byref(u), C.byref(c)))
         return u.value, c.value
-
-
-# --------------------------------------------------------------------------- split costs
-def split_costs(nodes, mnc_counts=None):
-    """Direct cost of a split in each ReLU layer, after Appendix B: the layers are the nodes after
-    the input, in order; a split in layer k costs sum over the later layers i of 2 d_i C_i, where
-    d_i is layer i's output width and C_i the sum of the back-substitution costs c_j of the layers
-    before it: d_j + p_j for a ReLU layer with p_j multi-neuron constraints, the weight count for
-    a fully connected layer, d_j k_j^2 for a convolution, and d_j for a residual addition (the
-    appendix gives no cost for it).  mnc_counts [n_relu] defaults to zeros.  Returns one float
-    per ReLU layer, for layer_weight = 1 / cost in Problem.branch_scores."""
-    from workloads import node_shapes  # shapes only
-    shapes = node_shapes(nodes)
-    layers = list(range(1, len(nodes)))
-    relus = [i for i in layers if nodes[i]["kind"] == "relu"]
-    p = list(mnc_counts) if mnc_counts is not None else [0] * len(relus)
-    if len(p) != len(relus):
-        raise ValueError("mnc_counts needs one entry per ReLU layer")
-    d = {i: int(np.prod(shapes[i])) for i in layers}
-    c = []
-    for i in layers:
-        kind = nodes[i]["kind"]
-        if kind == "relu":
-            c.append(d[i] + p[relus.index(i)])
-        elif kind == "fc":
-            c.append(int(np.asarray(nodes[i]["W"]).size))
-        elif kind == "conv":
-            c.append(d[i] * int(np.asarray(nodes[i]["W"]).shape[2]) ** 2)
-        else:
-            c.append(d[i])
-    prefix = np.concatenate([[0], np.cumsum(np.asarray(c, np.float64))])   # prefix[t] = sum of c over t layers
-    out = []
-    for r in relus:
-        k = layers.index(r)
-        out.append(float(sum(2.0 * d[layers[t]] * prefix[t] for t in range(k + 1, len(layers)))))
-    return out
 
 
 # --------------------------------------------------------------------------- kernel timer

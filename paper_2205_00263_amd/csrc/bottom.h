@@ -7,6 +7,7 @@ namespace mnb {
 
 struct BottomArgs {
     int mode;        // 0: intermediate rows (update l/u), 1: spec rows (lb + best), 2: lb only
+    float margin;    // rounding margin factor: 2^-20 for spec rows, 0 for intermediate rows
     int src_mode;    // 0: rows read from A; 1: rows built from the objective convolution's filter
     const float* A;  // [M, d1] coefficients on the output of ReLU layer 0 (src_mode 0)
     const float* c;  // [M] (src_mode 0)

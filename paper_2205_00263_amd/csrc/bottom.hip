@@ -304,7 +304,7 @@ __global__ __launch_bounds__(BT, (NJ <= 6 ? 4 : 2)) void k_bottom(BottomArgs a) 
         }
         block_sum3(lbp, mag, cpt, red);   // also publishes s_x
         if (t == 0) {
-            float lb = (lbp + cpt) - (mag + fabsf(cpt)) * 9.5367431640625e-07f;   // 2^-20 rounding margin
+            float lb = (lbp + cpt) - (mag + fabsf(cpt)) * a.margin;   // rounding margin of spec rows
             if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
             const float old = s_old[ri];
             if (a.mode == 0) {

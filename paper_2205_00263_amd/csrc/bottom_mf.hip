@@ -613,7 +613,7 @@ __global__ __launch_bounds__(MBT) void k_bottom_mf(BottomArgs a) {
                 if (b < nb) {
                     const int r = cr0 + ri + b;
                     const RowDesc rd = s_rd[ri + b];
-                    float lb = (t0 + t2) - (t1 + fabsf(t2)) * 9.5367431640625e-07f;   // 2^-20 margin
+                    float lb = (t0 + t2) - (t1 + fabsf(t2)) * a.margin;   // rounding margin of spec rows
                     if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
                     const float old = s_old[ri + b];
                     if (a.mode == 0) {

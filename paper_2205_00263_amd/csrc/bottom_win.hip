@@ -71,7 +71,7 @@ __global__ __launch_bounds__(WT) void k_win_prep(WinArgs a) {
     const float* lo = a.lo + (long)qi * a.d0;
     const float* hi = a.hi + (long)qi * a.d0;
     float* As = a.asplit + (long)blockIdx.x * a.d0;
-    float L = 0.f, MG = 0.f;
+    float L = 0.f, unused = 0.f;
     for (int o = t; o < a.d0; o += WT) {
         float acc = 0.f;
         if (nz) {
@@ -91,13 +91,12 @@ __global__ __launch_bounds__(WT) void k_win_prep(WinArgs a) {
         As[o] = acc;
         const float l = lo[o], h = hi[o];
         L += fminf(acc * l, acc * h);
-        MG += fabsf(acc) * fmaxf(fabsf(l), fabsf(h));
     }
-    win_sum3(L, MG, cs, red);
+    win_sum3(L, unused, cs, red);
     if (t == 0) {
         float* sc = a.scal + (long)blockIdx.x * 4;
         sc[0] = L;
-        sc[1] = MG;
+        sc[1] = 0.f;
         sc[2] = cs;
         sc[3] = 0.f;
     }
@@ -310,19 +309,17 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
         rbn[v] = bn;
     }
     // split terms outside the window: the instance totals minus the window's share
-    float Lw = 0.f, Mw = 0.f;   // every wavefront owns the same pixels: each sums them itself
+    float Lw = 0.f;   // every wavefront owns the same pixels: each sums them itself
     {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (qv[i]) {
                 Lw += fminf(as_q[i] * lo_q[i], as_q[i] * hi_q[i]);
-                Mw += fabsf(as_q[i]) * fmaxf(fabsf(lo_q[i]), fabsf(hi_q[i]));
             }
     }
     Lw = wave_sum(Lw);
-    Mw = wave_sum(Mw);
     const float* sc = a.scal + (long)ib * 4;
-    const float L_out = sc[0] - Lw, M_out = sc[1] - Mw, c_split = sc[2];
+    const float L_out = sc[0] - Lw, c_split = sc[2];
     __syncthreads();   // s_tix and s_ent complete
 
     float da[4] = {0.f, 0.f, 0.f, 0.f}, xs[4] = {0.f, 0.f, 0.f, 0.f};
@@ -361,7 +358,7 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
         }
         wave_sync();
         // col2im onto the input window plus A_s, then concretisation over the box (Eq. 6)
-        float lbp = 0.f, mag = 0.f;
+        float lbp = 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int q = lane + 64 * i;
@@ -371,18 +368,16 @@ __global__ __launch_bounds__(WT) void k_bottom_win(WinArgs a) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) acc += sT[s_tix[q][u]];
                 lbp += fminf(acc * lo_q[i], acc * hi_q[i]);
-                mag += fabsf(acc) * fmaxf(fabsf(lo_q[i]), fabsf(hi_q[i]));
                 xq = acc < 0.f ? hi_q[i] : lo_q[i];
             }
             sx[q] = xq;
             xs[i] += xq;
         }
         lbp = wave_sum(lbp);
-        mag = wave_sum(mag);
         ce = wave_sum(ce);
         if (lane == 0) {
             const float cpt = (ce + c_split) + en.cb;
-            float lb = ((L_out + lbp) + cpt) - ((M_out + mag) + fabsf(cpt)) * 9.5367431640625e-07f;   // 2^-20 margin
+            float lb = (L_out + lbp) + cpt;   // intermediate rows: no rounding margin
             if (!(lb == lb) || isinf(lb)) lb = -INFINITY;
             if (a.mode == 0) {
                 const long e = (long)in.slot * a.ld_state + a.state_off_obj + en.j;

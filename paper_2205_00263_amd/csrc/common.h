@@ -29,6 +29,8 @@ void set_error(int code, const std::string& msg);
     } while (0)
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+// Largest grid.y (and grid.z) of one launch; kernels with rows on grid.y are launched in slices.
+constexpr int kMaxGridY = 65535;
 
 // ---------------------------------------------------------------- device helpers
 // v + the value of the lane `CTRL` selects (a DPP row shift or row broadcast), 0 where the

@@ -114,6 +114,7 @@ struct mnb_problem {
         float *col_P = nullptr, *col_Ph = nullptr, *row_P = nullptr, *row_Ph = nullptr, *p = nullptr;
     };
     std::vector<MncLayer> mnc;
+    std::vector<std::vector<int32_t>> q_mnc_e;   // host: constraints per ReLU layer of each query
     int nnz_cap = 0;
     bool has_mnc = false;
     std::vector<void*> owned;

@@ -635,6 +635,11 @@ struct PassCtx {
 
 static int fold_cols(int d) { return cdiv(d, 256) * 4; }
 
+// Rounding margin of a reported (spec-row) bound: lb is lowered by 2^-20 (sum_j |a_j| max(|lo_j|,
+// |hi_j|) + |c|), which covers the FP32 rounding of the concretisation where the bound is exact.
+// Intermediate bounds are concretised without it.
+constexpr float kSpecMargin = 9.5367431640625e-07f;
+
 // Total partial-constant columns of a pass whose rows start at node `top`.
 static int pass_cols(const mnb_net* net, int top) {
     int cols = 0;
@@ -1077,6 +1082,7 @@ struct Evaluator {
                 ba.mode = 0;
                 ba.lw = pb->l; ba.uw = pb->u; ba.state_off_obj = net->relu_off[ch.obj_layer];
             }
+            ba.margin = ch.obj_layer < 0 ? kSpecMargin : 0.f;
             ba.adjoint = adjoint;
             const int top = pass_top(net, ch.obj_layer);
             if (adjoint && top > r0n) g_bottom = pool.acquire();
@@ -1193,6 +1199,7 @@ struct Evaluator {
         ca.rows = ch.rows; ca.slots = slots_d; ca.qid = pb->qid; ca.lo = pb->lo; ca.hi = pb->hi;
         ca.M = M; ca.d0 = net->d0;
         ca.G0 = adjoint ? cx.G0 : nullptr;
+        ca.margin = ch.obj_layer < 0 ? kSpecMargin : 0.f;
         if (ch.obj_layer < 0) {
             ca.mode = 1;
             ca.xbits = cx.xbits;

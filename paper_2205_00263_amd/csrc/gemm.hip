@@ -421,19 +421,26 @@ static bool launch_convT_small(const ConvGeom& g, const float* A, float* C, int 
     // window rows: y from ceil((ty0 + p - (k-1)) / s) to (ty0 + TCT - 1 + p) / s
     const int WY = (TCT - 1 + g.k - 1) / g.s + 2, WX = WY;
     const size_t lds = ((size_t)g.Co * g.Ci * g.k * g.k + (size_t)TCO * WY * WX) * sizeof(float);
-    if (lds > 64 * 1024 || M > 65535) return false;
-    const dim3 grid(tiles_y * tiles_x, M);
-    switch (g.Ci) {
-        case 1: hipLaunchKernelGGL(k_convT_small<1>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
-                                   g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
-        case 2: hipLaunchKernelGGL(k_convT_small<2>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
-                                   g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
-        case 3: hipLaunchKernelGGL(k_convT_small<3>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
-                                   g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
-        default: hipLaunchKernelGGL(k_convT_small<4>, grid, dim3(256), lds, st, A, C, g.W, g.Hi, g.Wi, g.Co, g.Ho,
-                                    g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+    if (lds > 64 * 1024) return false;
+    // rows go on grid.y (at most 65535 per launch): larger batches are launched in row slices
+    const long ldA = (long)g.Co * g.Ho * g.Wo, ldC = (long)g.Ci * g.Hi * g.Wi;
+    for (int r0 = 0; r0 < M; r0 += kMaxGridY) {
+        const int nr = M - r0 < kMaxGridY ? M - r0 : kMaxGridY;
+        const dim3 grid(tiles_y * tiles_x, nr);
+        const float* Ar = A + r0 * ldA;
+        float* Cr = C + r0 * ldC;
+        switch (g.Ci) {
+            case 1: hipLaunchKernelGGL(k_convT_small<1>, grid, dim3(256), lds, st, Ar, Cr, g.W, g.Hi, g.Wi, g.Co,
+                                       g.Ho, g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+            case 2: hipLaunchKernelGGL(k_convT_small<2>, grid, dim3(256), lds, st, Ar, Cr, g.W, g.Hi, g.Wi, g.Co,
+                                       g.Ho, g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+            case 3: hipLaunchKernelGGL(k_convT_small<3>, grid, dim3(256), lds, st, Ar, Cr, g.W, g.Hi, g.Wi, g.Co,
+                                       g.Ho, g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+            default: hipLaunchKernelGGL(k_convT_small<4>, grid, dim3(256), lds, st, Ar, Cr, g.W, g.Hi, g.Wi, g.Co,
+                                        g.Ho, g.Wo, g.k, g.s, g.p, (int)accumulate, tiles_x, WY, WX); break;
+        }
+        MNB_HIP(hipGetLastError());
     }
-    MNB_HIP(hipGetLastError());
     return true;
 }
 

@@ -87,6 +87,7 @@ void launch_relu_fold(const FoldArgs& a, hipStream_t st, const float* gp);
 
 struct ConcArgs {
     int mode;              // 0: intermediate-bound rows (update l/u), 1: spec rows, 2: lb only
+    float margin;          // rounding margin factor: 2^-20 for spec rows, 0 for intermediate rows
     const float* A;        // [M, d0] coefficients on the input
     const float* c;        // [M]
     const float* cpart; int ldcp, ncp;  // partial constants of the folds
@@ -152,8 +153,8 @@ void launch_score(const InstDesc* inst, int n_inst, const float* Ap, int d, cons
 void launch_argmax(const float* score, long ld, int n, int nb, int32_t* out, hipStream_t st);
 void launch_pick(const float* score, long ld, const int32_t* arg, int n, float* out, hipStream_t st);
 void launch_acs_score(const InstDesc* inst, int n_inst, const float* v, const float* vh, int d, const float* l,
-                      const float* u, const int8_t* S, long ld_state, int state_off, float w, float* score,
-                      long ld_score, int score_off, hipStream_t st);
+                      const float* u, const int8_t* S, long ld_state, int state_off, const float* w, int ldw,
+                      float* score, long ld_score, int score_off, hipStream_t st);
 
 void launch_bits_to_x(const uint8_t* bits, const int32_t* row_slot, const int32_t* qid, const float* lo,
                       const float* hi, int d0, int M, float* X, hipStream_t st);

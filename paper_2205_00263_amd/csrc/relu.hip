@@ -178,7 +178,8 @@ void launch_relu_relax(const RelaxArgs& a, hipStream_t st) {
 
 // ------------------------------------------------------------------ concretisation (Eq. 6)
 // lb_r = sum_j min(a_j lo_j, a_j hi_j) + c_r (+ the partial constants of the
-// ReLU folds), minus a rounding margin 2^-20 (sum_j |a_j| max(|lo_j|,|hi_j|) + |c_r|).
+// ReLU folds); a spec row's bound is lowered by the rounding margin
+// 2^-20 (sum_j |a_j| max(|lo_j|,|hi_j|) + |c_r|), an intermediate row's is not.
 // x*_j = hi_j if a_j < 0 else lo_j.
 __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
     const int r = blockIdx.x;
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
     if (threadIdx.x != 0) return;
     const float tot = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) + c;
     const float m = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) + fabsf(c);
-    float lb = tot - m * 9.5367431640625e-07f;   // 2^-20
+    float lb = tot - m * a.margin;
     if (!(lb == lb) || isinf(lb)) lb = -INFINITY;   // NaN / Inf never gives a positive bound
     if (a.mode == 2) {
         a.lb_out[r] = lb;
@@ -263,8 +264,8 @@ void launch_keep_best_x(const uint8_t* xbits, uint8_t* best_bits, const uint8_t*
 // ------------------------------------------------------------------ row initialisation
 // Spec rows: coefficients Chat = C W^(L) (the property folded into the last affine layer).
 __global__ void k_init_spec(const RowDesc* rows, const int32_t* slots, const int32_t* qid, const float* Chat,
-                            const float* chat, int S, int d, float* A, float* c) {
-    const int r = blockIdx.y;
+                            const float* chat, int S, int d, float* A, float* c, int r0) {
+    const int r = r0 + blockIdx.y;
     const RowDesc rd = rows[r];
     const int q = qid[slots[rd.b]];
     const float* src = Chat + ((long)q * S + rd.j) * d;
@@ -275,15 +276,17 @@ void launch_init_spec(const RowDesc* rows, int M, const int32_t* slots, const in
                       const float* Chat, const float* chat, int S, int d, float* A, float* c,
                       hipStream_t st) {
     if (M <= 0) return;
-    hipLaunchKernelGGL(k_init_spec, dim3(cdiv(d, 256), M), dim3(256), 0, st, rows, slots, qid, Chat, chat,
-                       S, d, A, c);
-    MNB_HIP(hipGetLastError());
+    for (int r0 = 0; r0 < M; r0 += kMaxGridY) {
+        hipLaunchKernelGGL(k_init_spec, dim3(cdiv(d, 256), std::min(M - r0, kMaxGridY)), dim3(256), 0, st, rows,
+                           slots, qid, Chat, chat, S, d, A, c, r0);
+        MNB_HIP(hipGetLastError());
+    }
 }
 
 // Intermediate rows +-e_j on the output of an FC node: a = +-W[j, :], c = +-bias[j].
 __global__ void k_init_fc(const RowDesc* rows, const float* W, const float* bias_eff, int din, float* A,
-                          float* c, int write_c) {
-    const int r = blockIdx.y;
+                          float* c, int write_c, int r0) {
+    const int r = r0 + blockIdx.y;
     const RowDesc rd = rows[r];
     const float sg = (float)rd.sign;
     const float* w = W + (long)rd.j * din;
@@ -294,17 +297,19 @@ __global__ void k_init_fc(const RowDesc* rows, const float* W, const float* bias
 void launch_init_fc(const RowDesc* rows, int M, const float* W, const float* bias_eff, int din, float* A,
                     float* c, bool write_c, hipStream_t st) {
     if (M <= 0) return;
-    hipLaunchKernelGGL(k_init_fc, dim3(cdiv(din, 256), M), dim3(256), 0, st, rows, W, bias_eff, din, A, c,
-                       (int)write_c);
-    MNB_HIP(hipGetLastError());
+    for (int r0 = 0; r0 < M; r0 += kMaxGridY) {
+        hipLaunchKernelGGL(k_init_fc, dim3(cdiv(din, 256), std::min(M - r0, kMaxGridY)), dim3(256), 0, st, rows, W,
+                           bias_eff, din, A, c, (int)write_c, r0);
+        MNB_HIP(hipGetLastError());
+    }
 }
 
 // Intermediate rows +-e_j on the output of a conv node (j = (co, y, x)): the
 // filter of output channel co placed at its input window.
 __global__ void k_init_conv(const RowDesc* rows, const float* W, const float* bias_eff, int Ci, int Hi,
                             int Wi, int Co, int Ho, int Wo, int k, int s, int p, float* A, float* c,
-                            int write_c) {
-    const int r = blockIdx.y;
+                            int write_c, int r0) {
+    const int r = r0 + blockIdx.y;
     const RowDesc rd = rows[r];
     const float sg = (float)rd.sign;
     const int co = rd.j / (Ho * Wo);
@@ -326,9 +331,11 @@ void launch_init_conv(const RowDesc* rows, int M, const ConvGeom& g, const float
                       float* c, bool write_c, hipStream_t st) {
     if (M <= 0) return;
     const int din = g.Ci * g.Hi * g.Wi;
-    hipLaunchKernelGGL(k_init_conv, dim3(cdiv(din, 256), M), dim3(256), 0, st, rows, g.W, bias_eff, g.Ci,
-                       g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.k, g.s, g.p, A, c, (int)write_c);
-    MNB_HIP(hipGetLastError());
+    for (int r0 = 0; r0 < M; r0 += kMaxGridY) {
+        hipLaunchKernelGGL(k_init_conv, dim3(cdiv(din, 256), std::min(M - r0, kMaxGridY)), dim3(256), 0, st, rows,
+                           g.W, bias_eff, g.Ci, g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.k, g.s, g.p, A, c, (int)write_c, r0);
+        MNB_HIP(hipGetLastError());
+    }
 }
 
 // ------------------------------------------------------------------ interval propagation
@@ -566,9 +573,10 @@ void launch_score(const InstDesc* inst, int n_inst, const float* Ap, int d, cons
 // its input, s_j = |(gamma^T P)_j| + |(gamma^T Phat)_j| for unstable, unsplit j (v = P^T gamma and
 // vhat = Phat^T gamma come from k_gamma_proj), times the layer's weight (the inverse split cost
 // of cost adjusted branching, else 1); -inf elsewhere.
+// w: this layer's weight of instance 0, instance i's at w[i * ldw] (ldw 0: one weight for all; w null: 1)
 __global__ void k_acs_score(const InstDesc* inst, const float* v, const float* vh, int d, const float* l,
-                            const float* u, const int8_t* S, long ld_state, int state_off, float w, float* score,
-                            long ld_score, int score_off) {
+                            const float* u, const int8_t* S, long ld_state, int state_off, const float* w, int ldw,
+                            float* score, long ld_score, int score_off) {
     const InstDesc in = inst[blockIdx.y];
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= d) return;
@@ -576,15 +584,16 @@ __global__ void k_acs_score(const InstDesc* inst, const float* v, const float* v
     const float lj = l[so], uj = u[so];
     const long vo = (long)blockIdx.y * d + j;
     float sc = -INFINITY;
-    if (S[so] == 0 && lj < 0.f && uj > 0.f) sc = (fabsf(v[vo]) + fabsf(vh[vo])) * w;
+    const float wt = w ? w[(long)blockIdx.y * ldw] : 1.f;
+    if (S[so] == 0 && lj < 0.f && uj > 0.f) sc = (fabsf(v[vo]) + fabsf(vh[vo])) * wt;
     score[(long)in.b * ld_score + score_off + j] = sc;
 }
 void launch_acs_score(const InstDesc* inst, int n_inst, const float* v, const float* vh, int d, const float* l,
-                      const float* u, const int8_t* S, long ld_state, int state_off, float w, float* score,
-                      long ld_score, int score_off, hipStream_t st) {
+                      const float* u, const int8_t* S, long ld_state, int state_off, const float* w, int ldw,
+                      float* score, long ld_score, int score_off, hipStream_t st) {
     if (n_inst <= 0 || d <= 0) return;
     hipLaunchKernelGGL(k_acs_score, dim3(cdiv(d, 256), n_inst), dim3(256), 0, st, inst, v, vh, d, l, u, S, ld_state,
-                       state_off, w, score, ld_score, score_off);
+                       state_off, w, ldw, score, ld_score, score_off);
     MNB_HIP(hipGetLastError());
 }
 // the score at each subproblem's argmax (-inf where there is none)

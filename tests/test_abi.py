@@ -41,29 +41,36 @@ def test_binding_declares_only_exported_symbols():
     assert set(_lib.exported_symbols()) == set(declared_functions())
 
 
-def test_split_costs_follow_appendix_b():
-    """The binding's per-layer split costs (host logic) against the oracle's cost model."""
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_split_costs_follow_appendix_b(cfg):
+    """mnb_split_costs (host code of the library, no device work) against the oracle's cost model of
+    Appendix B on the four full-size network shapes (configuration 4 has residual additions), with
+    random multi-neuron constraint counts and without any."""
     import numpy as np
     import workloads as W
     from oracle import cost as ocost
     from paper_2205_00263_amd import split_costs
-    for cfg in (1, 2):
-        wl = W.make_workload(cfg, scale="small")
-        nodes = wl.nodes
-        shapes = W.node_shapes(nodes)
-        layers, relu_pos = [], []
-        rng = np.random.default_rng(cfg)
-        p = []
-        for i in range(1, len(nodes)):
-            n = nodes[i]
-            d = int(np.prod(shapes[i]))
-            if n["kind"] == "relu":
-                p.append(int(rng.integers(0, 20)))
-                layers.append({"kind": "relu", "d": d, "p": p[-1]})
-                relu_pos.append(len(layers) - 1)
-            elif n["kind"] == "fc":
-                layers.append({"kind": "fc", "d": d, "nW": int(np.asarray(n["W"]).size)})
-            else:
-                layers.append({"kind": "conv", "d": d, "k": int(np.asarray(n["W"]).shape[2])})
+    nodes = W.make_net(cfg)
+    shapes = W.node_shapes(nodes)
+    layers, relu_pos = [], []
+    for i in range(1, len(nodes)):
+        n = nodes[i]
+        d = int(np.prod(shapes[i]))
+        if n["kind"] == "relu":
+            layers.append({"kind": "relu", "d": d})
+            relu_pos.append(len(layers) - 1)
+        elif n["kind"] == "fc":
+            layers.append({"kind": "fc", "d": d, "nW": int(np.asarray(n["W"]).size)})
+        elif n["kind"] == "conv":
+            layers.append({"kind": "conv", "d": d, "k": int(np.asarray(n["W"]).shape[2])})
+        else:
+            layers.append({"kind": "add", "d": d})
+    rng = np.random.default_rng(cfg)
+    for p in (None, rng.integers(0, 500, len(relu_pos)).astype(np.int32)):
         got = split_costs(nodes, p)
-        assert got == [float(ocost.split_cost(layers, k)) for k in relu_pos]
+        for t, k in enumerate(relu_pos):
+            layers[k]["p"] = 0 if p is None else int(p[t])
+        assert got.tolist() == [float(ocost.split_cost(layers, k)) for k in relu_pos]
+    with pytest.raises(Exception):
+        split_costs(nodes, -np.ones(len(relu_pos), np.int32))

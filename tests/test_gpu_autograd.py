@@ -97,7 +97,7 @@ def test_autograd_adam_matches_fused_optimiser(cfg):
     a_id, b_id = int(kids[0]), int(kids[2])
     steps = 6
     lb_fused, _ = pb.bound_optimize([a_id], steps=steps, lr=0.1, recompute_intermediate=False)
-    best = optimize_set(pb, b_id, 0, steps=steps, lr=0.1)
+    best = optimize_set(pb, b_id, 0, steps=steps, lr=0.1).cpu().numpy()
     lb_auto = np.maximum(best, root_lb)
     print("fused", lb_fused[0][:3], "autograd", lb_auto[:3], flush=True)
     assert_parity(lb_auto, lb_fused[0].astype(np.float64), "autograd Adam vs fused Adam")

@@ -111,7 +111,7 @@ def test_branch_scores_match_oracle(cfg):
         for t in range(net.n_relu):
             gam[t * 60:t * 60 + n_mnc[t]] = rng.uniform(0, 0.3, n_mnc[t]) * (rng.uniform(size=n_mnc[t]) < 0.7)
         pb.set_params(sid, 0, gamma=gam)
-    costs = P.split_costs(wl.nodes, n_mnc)
+    costs = P.split_costs(wl.nodes, n_mnc).tolist()
     bl, bn, sc = pb.branch_scores(ids, want_scores=True)
     cbl, cbn, csc = pb.branch_scores(ids, layer_weight=[1.0 / c for c in costs], want_scores=True)
     offs = np.cumsum([0] + [net_o.sizes[i] for i in net_o.relus])
@@ -296,3 +296,55 @@ def test_serving_with_mnc_is_sound_and_complete():
         with_mnc += ne > 0
     assert with_mnc >= 3
     assert verified * 2 >= positive, (verified, positive)
+
+
+# --------------------------------------------------------------------------- alpha-contribution branching
+@pytest.mark.parametrize("cfg,scale", [(1, "small"), (2, "small"), (4, "small"), (2, "full")])
+def test_contribution_branching_matches_oracle(cfg, scale):
+    """bound_optimize's branching choice (want_branch) against the oracle's alpha-contribution score
+    (oracle.bab.branching_score) evaluated on the GPU's own last-evaluation state: the spec rows are
+    back-substituted by the oracle with the subproblem's parameters (set 0) and bounds as they stand
+    after the call.  The GPU's scores (mnb_contribution_scores, same state) must give the same choice
+    as bound_optimize bit for bit, the same candidate sets bit for bit, scores within 1e-5 of the
+    subproblem's largest, and the chosen neuron a maximum to that tolerance."""
+    from types import SimpleNamespace as NS
+    from _common import make_batch
+    P = _P()
+    wl = W.make_workload(cfg, scale=scale)
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    n_sub = 6 if scale == "small" else 3
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=8 * n_sub + 8)
+    rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    splits = W.make_split_sets(root_unstable(net_o, root), n_sub, 1, 3, seed=77 + cfg)
+    ids = make_batch(pb, rid, splits)
+    _, _, bl, bn = pb.bound_optimize(ids, steps=3, want_branch=True)
+    bl2, bn2, sc = pb.contribution_scores(ids)
+    assert np.array_equal(bl, bl2) and np.array_equal(bn, bn2), (bl, bl2, bn, bn2)
+    offs = np.cumsum([0] + [net_o.sizes[i] for i in net_o.relus])
+    for b, sid in enumerate(ids):
+        a_, b_, _ = pb.get_params(int(sid), 0)
+        states, params = {}, {}
+        for t, i in enumerate(net_o.relus):
+            l, u, S = pb.get_bounds(int(sid), t)
+            states[i] = ob.ReluState(l.astype(np.float64), u.astype(np.float64), S)
+            params[i] = {"alpha": a_[offs[t]:offs[t + 1]].astype(np.float64),
+                         "beta": b_[offs[t]:offs[t + 1]].astype(np.float64)}
+        out = ob.backsub(net_o, ob.spec_start(net_o, q.C), q.c0, states, params, None, q.lo, q.hi)
+        ref = obab.branching_score(net_o, NS(states=states), out["records"])
+        r = np.concatenate(ref)
+        fin = np.isfinite(r)
+        assert np.array_equal(np.isfinite(sc[b]), fin), (b, "candidate sets differ")
+        if not fin.any():
+            assert (bl[b], bn[b]) == (-1, -1)
+            continue
+        top = np.abs(r[fin]).max()
+        tol = 1e-5 * top + 1e-30
+        assert np.all(np.abs(sc[b][fin] - r[fin]) <= tol), (b, np.abs(sc[b][fin] - r[fin]).max(), top)
+        assert bl[b] >= 0 and fin[offs[bl[b]] + bn[b]], (b, bl[b], bn[b])
+        assert r[offs[bl[b]] + bn[b]] >= r[fin].max() - 2 * tol, (b, bl[b], bn[b])
+        om, oj = obab.pick_branch(ref)
+        srt = np.sort(r[fin])
+        if len(srt) == 1 or srt[-1] > srt[-2] + 2 * tol:   # a clear maximum: the same neuron
+            assert (bl[b], bn[b]) == (om, oj), (b, (bl[b], bn[b]), (om, oj))
