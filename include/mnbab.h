@@ -115,6 +115,22 @@ typedef struct {
     const float* p;
 } mnb_mnc;
 
+/* Constraint generator (host only, no device work).  The paper takes its
+ * multi-neuron constraints from PRIMA (Section 3.1); this library generates
+ * constraints of the same form from the exact convex hull of the graph of
+ * three ReLUs over an input polytope Q = {v : s . v >= lb_s} given by
+ * octahedral bounds on the 26 directions s in {-1,0,1}^3 \ {0}, listed in
+ * lexicographic order of (s0, s1, s2) with -1 < 0 < 1: relu is linear on each
+ * orthant, so the hull is that of the points (v, relu(v)) over the vertices v
+ * of Q intersected with each orthant; facets come from the double description
+ * method, each offset is reset to the maximum of its facet over those points
+ * (valid whatever the rounding), and facets that involve one neuron only are
+ * dropped.  lb [26]; out [max_out][7] = (Phat[3], P[3], p) per constraint
+ * Phat . zhat + P . z <= p, normals scaled to max |coefficient| = 1, in the
+ * lexicographic order of their normals; *n_out <= max_out written.  No
+ * constraints (n_out 0) when the points do not span 6 dimensions. */
+int mnb_relu_hull(const double* lb, int max_out, double* out, int* n_out);
+
 /* ------------------------------------------------------------------ problems */
 /* A problem is a device-resident pool of `capacity` subproblem slots on one
  * network; every query added to it has n_spec spec rows.  max_mnc bounds the
@@ -172,6 +188,30 @@ void mnb_opt_cfg_default(mnb_opt_cfg* cfg);
  * at the last evaluation (-1 if none). */
 int bound_optimize(mnb_problem* pb, const int64_t* ids, int n, const mnb_opt_cfg* cfg, float* lb,
                    float* ub, int32_t* branch_layer, int32_t* branch_neuron);
+
+/* bound_optimize in steps, for callers that interleave optimisation with other
+ * work (a scheduler advancing batches one Adam step at a time) or time single
+ * steps.  bound_optimize(cfg) is exactly begin(cfg), cfg->steps calls of step,
+ * then end.  begin validates the ids, counts the neurons each subproblem
+ * recomputes (unstable at this point), plans the passes and resets the Adam
+ * moments; cfg->steps = 0 plans an evaluation only (step then returns
+ * MNB_ESTATE).  step runs one evaluation (recomputed intermediate bounds, then
+ * the spec rows; best lb per row kept), its adjoint and one projected Adam
+ * update with bias correction for the session's own step count.  end runs the
+ * last evaluation, the upper bound and the outputs of bound_optimize, updates
+ * the subproblems' reported lb and frees the session; if end fails the session
+ * stays valid for mnb_opt_session_destroy.  A session owns its workspace, so
+ * other calls on the problem may run between steps, but the session's
+ * subproblems must not be released, split or optimised elsewhere until end.
+ * One session per thread at a time; sessions on one problem are serialised
+ * by the problem's lock. */
+typedef struct mnb_opt_session mnb_opt_session;
+int bound_optimize_begin(mnb_problem* pb, const int64_t* ids, int n, const mnb_opt_cfg* cfg,
+                         mnb_opt_session** out);
+int bound_optimize_step(mnb_opt_session* s);
+int bound_optimize_end(mnb_opt_session* s, float* lb, float* ub, int32_t* branch_layer,
+                       int32_t* branch_neuron);
+void mnb_opt_session_destroy(mnb_opt_session* s);
 
 /* Read back a subproblem's intermediate bounds of ReLU layer `layer`
  * (l, u [d_layer]) and split diagonal S (int8 [d_layer], may be NULL). */

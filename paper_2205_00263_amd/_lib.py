@@ -68,6 +68,10 @@ _SIGS = {
     "branch_split": (C.c_int, [C.c_void_p, ip64, ip32, ip32, C.c_int, ip64]),
     "mnb_opt_cfg_default": (None, [C.POINTER(OptCfg)]),
     "bound_optimize": (C.c_int, [C.c_void_p, ip64, C.c_int, C.POINTER(OptCfg), fp, fp, ip32, ip32]),
+    "bound_optimize_begin": (C.c_int, [C.c_void_p, ip64, C.c_int, C.POINTER(OptCfg), C.POINTER(C.c_void_p)]),
+    "bound_optimize_step": (C.c_int, [C.c_void_p]),
+    "bound_optimize_end": (C.c_int, [C.c_void_p, fp, fp, ip32, ip32]),
+    "mnb_opt_session_destroy": (None, [C.c_void_p]),
     "mnb_get_bounds": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, fp, fp, C.POINTER(C.c_int8)]),
     "mnb_get_params": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, fp, fp, fp]),
     "mnb_set_params": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, fp, fp, fp]),
@@ -78,6 +82,7 @@ _SIGS = {
     "mnb_branch_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, fp, ip32, ip32]),
     "mnb_contribution_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, ip32, ip32]),
     "mnb_split_costs": (C.c_int, [C.POINTER(Layer), C.c_int, ip32, C.POINTER(C.c_double)]),
+    "mnb_relu_hull": (C.c_int, [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "mnb_release": (C.c_int, [C.c_void_p, ip64, C.c_int]),
     "mnb_problem_usage": (C.c_int, [C.c_void_p, ip64, ip64]),
     "mnb_kernel_fc_backsub": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_int]),

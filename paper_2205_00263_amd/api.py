@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import check, lib
 
 __all__ = ["Net", "Problem", "use_torch_plumbing", "mnc_to_csr", "set_index", "set_kernel_variants",
-           "get_kernel_variants", "VARIANTS", "split_costs"]
+           "get_kernel_variants", "VARIANTS", "split_costs", "relu_hull"]
 
 
 def _f32(a):
@@ -280,6 +280,10 @@ class Problem:
             return lb, ub, bl, bn
         return lb, ub
 
+    def optimize_begin(self, ids, **kw):
+        """bound_optimize_begin: an OptSession over the subproblems `ids` (keywords as bound_optimize)."""
+        return OptSession(self, ids, self.opt_cfg(**kw))
+
     def get_bounds(self, sid, layer):
         d = self.net.relu_sizes[layer]
         l = np.zeros(d, np.float32)
@@ -363,6 +367,58 @@ class Problem:
         u, c = C.c_int64(), C.c_int64()
         check(lib().mnb_problem_usage(self.h, C.byref(u), C.byref(c)))
         return u.value, c.value
+
+
+class OptSession:
+    """bound_optimize in steps: step() is one Adam iteration (evaluation, adjoint, update) of every
+    subproblem of the session; end() runs the last evaluation and returns bound_optimize's outputs."""
+
+    def __init__(self, problem, ids, cfg):
+        self.problem = problem
+        self.ids = np.ascontiguousarray(ids, np.int64)
+        h = C.c_void_p()
+        check(lib().bound_optimize_begin(problem.h, _ptr(self.ids, C.c_int64), len(self.ids), C.byref(cfg),
+                                         C.byref(h)))
+        self.h = h
+
+    def step(self):
+        check(lib().bound_optimize_step(self.h))
+
+    def end(self, want_branch=False):
+        n, S = len(self.ids), self.problem.S
+        lb = np.zeros((n, S), np.float32)
+        ub = np.zeros((n, S), np.float32)
+        bl = np.zeros(n, np.int32) if want_branch else None
+        bn = np.zeros(n, np.int32) if want_branch else None
+        check(lib().bound_optimize_end(self.h, _ptr(lb), _ptr(ub), _ptr(bl, C.c_int32) if want_branch else None,
+                                       _ptr(bn, C.c_int32) if want_branch else None))
+        self.h = None
+        return (lb, ub, bl, bn) if want_branch else (lb, ub)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().mnb_opt_session_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def relu_hull(lb, max_out=4096):
+    """mnb_relu_hull: constraints (Phat [k,3], P [k,3], p [k]) of the 3-neuron ReLU hull over the
+    polytope of the 26 octahedral bounds lb (host-only call of the library)."""
+    lb = np.ascontiguousarray(lb, np.float64)
+    if lb.shape != (26,):
+        raise ValueError("lb needs the 26 octahedral bounds")
+    out = np.zeros((max(max_out, 1), 7), np.float64)
+    n = C.c_int()
+    check(lib().mnb_relu_hull(lb.ctypes.data_as(C.POINTER(C.c_double)), int(max_out),
+                              out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+    o = out[: n.value]
+    return o[:, :3].copy(), o[:, 3:6].copy(), o[:, 6].copy()
 
 
 # --------------------------------------------------------------------------- kernel timer

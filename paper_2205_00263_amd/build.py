@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmnbab.so")
-SOURCES = ["gemm.hip", "relu.hip", "bottom.hip", "bottom_mf.hip", "bottom_win.hip", "conv_rows.hip", "engine.hip", "serve.hip"]
+SOURCES = ["hull.cpp", "gemm.hip", "relu.hip", "bottom.hip", "bottom_mf.hip", "bottom_win.hip", "conv_rows.hip", "engine.hip", "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -22,7 +22,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
             continue
-        obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
+        obj = os.path.join(CSRC, "_build", os.path.splitext(src)[0] + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
         cmd = [HIPCC] + FLAGS + ["-c", path, "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

@@ -2,6 +2,7 @@
 // passes, their adjoint, and the C ABI of include/mnbab.h.
 #include "engine.h"
 #include "bottom.h"
+#include "hull.h"
 
 #include <math.h>
 #include <string.h>
@@ -999,6 +1000,7 @@ struct Evaluator {
     const int32_t* slots_d;
     Workspace& ws;
     Evaluator(mnb_problem* p, const int32_t* s) : pb(p), slots_d(s), ws(p->ws) {}
+    Evaluator(mnb_problem* p, const int32_t* s, Workspace& w) : pb(p), slots_d(s), ws(w) {}
 
     BufPool make_pool(int M, int nbuf) {
         BufPool pool;

@@ -355,3 +355,42 @@ def test_batch_composition_does_not_change_results():
             back[perm] = lb
             res[mode] = back
     np.testing.assert_array_equal(res["alone"], res["batch"])
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_optimize_session_equals_one_shot(cfg):
+    """bound_optimize_begin + T steps + end gives bound_optimize's results bit for bit, also with other
+    calls on the same problem between the steps (another query's bound_init, splits and a one-shot
+    optimisation of other subproblems)."""
+    import paper_2205_00263_amd as P
+    from _common import make_batch
+    wl = W.make_workload(cfg, scale="small")
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=128)
+    rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    splits = W.make_split_sets(root_unstable(net_o, root), 8, 1, 4, seed=91 + cfg)
+    a = make_batch(pb, rid, splits)
+    b = make_batch(pb, rid, splits)
+    c = make_batch(pb, rid, splits)
+    lb1, ub1, bl1, bn1 = pb.bound_optimize(a, steps=5, lr=0.1, want_branch=True)
+    s = pb.optimize_begin(b, steps=5, lr=0.1)
+    for t in range(5):
+        s.step()
+        if t == 2:   # unrelated work on the same problem between two steps
+            wl2 = W.make_workload(cfg, scale="small", seed_offset=1)
+            rid2, _, _ = pb.bound_init(wl2.lo, wl2.hi, wl2.C, wl2.c0)
+            pb.bound_optimize(c[:3], steps=2)
+            pb.release([rid2])
+    lb2, ub2, bl2, bn2 = s.end(want_branch=True)
+    assert np.array_equal(lb1, lb2) and np.array_equal(ub1, ub2)
+    assert np.array_equal(bl1, bl2) and np.array_equal(bn1, bn2)
+    for sid1, sid2 in zip(a, b):
+        for m in range(net.n_relu):
+            l1, u1, _ = pb.get_bounds(int(sid1), m)
+            l2, u2, _ = pb.get_bounds(int(sid2), m)
+            assert np.array_equal(l1, l2) and np.array_equal(u1, u2)
+        for si in range(2 * net.n_relu - 1):
+            p1, p2 = pb.get_params(int(sid1), si), pb.get_params(int(sid2), si)
+            assert all(np.array_equal(x, y) for x, y in zip(p1, p2))
