@@ -132,6 +132,8 @@ typedef struct {
 int mnb_relu_hull(const double* lb, int max_out, double* out, int* n_out);
 
 /* ------------------------------------------------------------------ problems */
+/* (mnb_octahedral_bounds / mnb_mnc_generate below generate constraints on the
+ * device for a query's root.) */
 /* A problem is a device-resident pool of `capacity` subproblem slots on one
  * network; every query added to it has n_spec spec rows.  max_mnc bounds the
  * number of MNC rows per ReLU layer of any query (0: no MNCs). */
@@ -269,6 +271,31 @@ int mnb_branch_scores(mnb_problem* pb, const int64_t* ids, int n, const float* l
  * duplicate or invalid ids or n > 65535. */
 int mnb_contribution_scores(mnb_problem* pb, const int64_t* ids, int n, float* scores,
                             int32_t* branch_layer, int32_t* branch_neuron);
+/* Multi-neuron constraint generation on the device (the input of Eq. 3 that
+ * the paper takes from PRIMA, Section 3.1).  mnb_octahedral_bounds: for the
+ * groups [n][3] of neurons of ReLU layer `layer`, the lower bounds lb [n][26]
+ * of s . zhat over the group for the 26 directions of mnb_relu_hull (same
+ * order), by back-substitution of the rows sum_t s_t e_{g_t} on the layer's
+ * input with the subproblem's parameters of the set bounding that layer from
+ * below (heuristic alpha and beta = gamma = 0 right after bound_init), without
+ * rounding margin.  mnb_mnc_generate: the constraints of every ReLU layer of
+ * the subproblem's query from its current bounds: unstable neurons ordered by
+ * the height -l u / (u - l) of their triangle (largest first, ties by index) in
+ * consecutive disjoint triples; per group its octahedral bounds, then the
+ * ReLU hull constraints of mnb_relu_hull on the host, group by group until cap
+ * constraints per layer; coefficients are stored in float32 with each offset
+ * recomputed for the rounded coefficients over the hull's vertices and
+ * rounded up (the stored constraint stays valid).  The query's constraint sets
+ * are replaced and gamma of the subproblem is reset to 0; e_out [n_relu]
+ * (nullable) receives the counts.  Call it on a query's root before branching:
+ * MNB_ESTATE if other subproblems of the query exist, MNB_EINVAL if the problem
+ * has max_mnc = 0 or cap > max_mnc.  mnb_get_mnc reads a query's constraints of
+ * one layer back (CSR as in mnb_mnc; arrays sized max_mnc + 1 / 4 max_mnc /
+ * max_mnc, each nullable). */
+int mnb_octahedral_bounds(mnb_problem* pb, int64_t id, int layer, const int32_t* groups, int n, float* lb);
+int mnb_mnc_generate(mnb_problem* pb, int64_t id, int cap, int32_t* e_out);
+int mnb_get_mnc(mnb_problem* pb, int64_t id, int layer, int* e, int32_t* row_ptr, int32_t* col, float* P,
+                float* Phat, float* p);
 /* Free subproblem slots. */
 int mnb_release(mnb_problem* pb, const int64_t* ids, int n);
 /* Slots in use / capacity. */

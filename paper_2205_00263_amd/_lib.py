@@ -82,6 +82,9 @@ _SIGS = {
     "mnb_branch_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, fp, ip32, ip32]),
     "mnb_contribution_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, ip32, ip32]),
     "mnb_split_costs": (C.c_int, [C.POINTER(Layer), C.c_int, ip32, C.POINTER(C.c_double)]),
+    "mnb_octahedral_bounds": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, ip32, C.c_int, fp]),
+    "mnb_mnc_generate": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, ip32]),
+    "mnb_get_mnc": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_int), ip32, ip32, fp, fp, fp]),
     "mnb_relu_hull": (C.c_int, [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "mnb_release": (C.c_int, [C.c_void_p, ip64, C.c_int]),
     "mnb_problem_usage": (C.c_int, [C.c_void_p, ip64, ip64]),

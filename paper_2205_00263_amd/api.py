@@ -359,6 +359,34 @@ class Problem:
                                             _ptr(bl, C.c_int32), _ptr(bn, C.c_int32)))
         return (bl, bn, sc) if want_scores else (bl, bn)
 
+    def octahedral_bounds(self, sid, layer, groups):
+        """mnb_octahedral_bounds: lb [n, 26] of the groups [n, 3] of ReLU layer `layer`."""
+        g = np.ascontiguousarray(groups, np.int32).reshape(-1, 3)
+        lb = np.zeros((len(g), 26), np.float32)
+        check(lib().mnb_octahedral_bounds(self.h, int(sid), int(layer), _ptr(g, C.c_int32), len(g), _ptr(lb)))
+        return lb
+
+    def mnc_generate(self, sid, cap=500):
+        """mnb_mnc_generate: constraints of every ReLU layer of the query of root `sid`; counts per layer."""
+        e = np.zeros(self.net.n_relu, np.int32)
+        check(lib().mnb_mnc_generate(self.h, int(sid), int(cap), _ptr(e, C.c_int32)))
+        return e
+
+    def get_mnc(self, sid, layer):
+        """mnb_get_mnc: (row_ptr, col, P, Phat, p) of the query's constraints of one ReLU layer."""
+        E = max(self.max_mnc, 1)
+        e = C.c_int()
+        rp = np.zeros(E + 1, np.int32)
+        col = np.zeros(4 * E, np.int32)
+        P_ = np.zeros(4 * E, np.float32)
+        H_ = np.zeros(4 * E, np.float32)
+        p = np.zeros(E, np.float32)
+        check(lib().mnb_get_mnc(self.h, int(sid), int(layer), C.byref(e), _ptr(rp, C.c_int32), _ptr(col, C.c_int32),
+                                _ptr(P_), _ptr(H_), _ptr(p)))
+        n = e.value
+        nnz = int(rp[n])
+        return rp[:n + 1].copy(), col[:nnz].copy(), P_[:nnz].copy(), H_[:nnz].copy(), p[:n].copy()
+
     def release(self, ids):
         ids = np.ascontiguousarray(ids, np.int64)
         check(lib().mnb_release(self.h, _ptr(ids, C.c_int64), len(ids)))

@@ -582,6 +582,9 @@ struct PassChunk {
     std::vector<InstDesc> inst;      // host, rows relative to the chunk
     InstDesc* inst_d = nullptr;
     int obj_layer = -1;         // ReLU layer of the objective, -1: spec rows
+    // octahedral rows (multi-neuron constraint generation): row 26 g + s is sum_t s_t e_{grp[g][t]}
+    // on the input of ReLU layer obj_layer, for the 26 directions s; groups [M / 26][3] on the device
+    const int32_t* oct_groups = nullptr;
 };
 
 // A pool of [M, max_width] coefficient buffers with reference counts.
@@ -654,6 +657,12 @@ static int pass_top(const mnb_net* net, int obj_layer) {
     const NetNode& o = net->nodes[net->nodes[net->relus[obj_layer]].src];
     if (o.kind == MNB_ADD) return std::max(net->nodes[o.src].src, net->nodes[o.src2].src);
     return o.src;
+}
+
+// Highest node a chunk's rows are on: octahedral rows start on the ReLU input node itself.
+static int chunk_top(const mnb_net* net, const PassChunk& ch) {
+    if (ch.oct_groups) return net->nodes[net->relus[ch.obj_layer]].src;
+    return pass_top(net, ch.obj_layer);
 }
 
 // Back-substitute a chunk of rows from its objective down to the input (Eq. 2 and
@@ -762,7 +771,12 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
     const int M = ch.M;
     std::map<int, float*> coef;
     int top;
-    if (ch.obj_layer < 0) {
+    if (ch.oct_groups) {
+        top = chunk_top(net, ch);
+        float* A = pool.acquire();
+        launch_init_oct(ch.oct_groups, M / 26, net->nodes[top].size, net->relu_bias[ch.obj_layer], A, cx.c, st);
+        coef[top] = A;
+    } else if (ch.obj_layer < 0) {
         top = net->nodes[net->last].src;
         float* A = pool.acquire();
         const int d = net->nodes[top].size;
@@ -813,7 +827,7 @@ static void run_adjoint(PassCtx& cx, const PassChunk& ch, BufPool& pool, float* 
     mnb_net* net = pb->net;
     hipStream_t st = stream();
     const int M = ch.M;
-    const int top = pass_top(net, ch.obj_layer);
+    const int top = chunk_top(net, ch);
     const int n_inst = (int)ch.inst.size();
     std::vector<float*> g(net->nodes.size(), nullptr);
     std::vector<int> uses(net->nodes.size(), 0);
@@ -941,7 +955,7 @@ static void gamma_projections(PassCtx& cx, const PassChunk& ch, Workspace& ws, c
     mnb_problem* pb = cx.pb;
     if (!pb->has_mnc) return;
     mnb_net* net = pb->net;
-    const int top = pass_top(net, ch.obj_layer);
+    const int top = chunk_top(net, ch);
     const int n_inst = (int)ch.inst.size();
     for (int m = 0; m < pb->R; ++m) {
         const int ri = net->relus[m];
@@ -1020,7 +1034,7 @@ struct Evaluator {
         hipStream_t st = stream();
         const int M = ch.M;
         if (M == 0) return;
-        const int top = pass_top(net, ch.obj_layer);
+        const int top = chunk_top(net, ch);
         PassCtx cx{};
         cx.pb = pb;
         cx.slots_d = slots_d;
@@ -1047,7 +1061,7 @@ struct Evaluator {
             BottomArgs ba{};
             float* A1 = nullptr;
             bool src1 = false;
-            if (ch.obj_layer == 1) {
+            if (ch.obj_layer == 1 && !ch.oct_groups) {
                 const NetNode& on = net->nodes[net->nodes[net->relus[1]].src];
                 src1 = on.kind == MNB_CONV && on.src == r0n;
                 if (src1) {
@@ -1086,7 +1100,7 @@ struct Evaluator {
             }
             ba.margin = ch.obj_layer < 0 ? kSpecMargin : 0.f;
             ba.adjoint = adjoint;
-            const int top = pass_top(net, ch.obj_layer);
+            const int top = chunk_top(net, ch);
             if (adjoint && top > r0n) g_bottom = pool.acquire();
             ba.Gout = g_bottom;
             ba.Ap_out = keep_ap ? cx.ap.at(r0n) : nullptr;

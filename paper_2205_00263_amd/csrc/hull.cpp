@@ -256,8 +256,8 @@ void polytope_vertices(const std::vector<std::array<double, 3>>& A, const std::v
 
 }  // namespace
 
-void relu_hull_constraints(const double lb[26], int max_out, std::vector<GroupConstraint>* out) {
-    if (max_out <= 0) return;
+void relu_hull_points(const double lb[26], std::vector<std::vector<double>>* out) {
+    out->clear();
     for (int s = 0; s < 26; ++s)
         if (!std::isfinite(lb[s])) return;
     // Q: s . v >= lb_s, i.e. -s . v <= -lb_s
@@ -267,7 +267,6 @@ void relu_hull_constraints(const double lb[26], int max_out, std::vector<GroupCo
         for (int t = 0; t < 3; ++t) A0[s][t] = -(double)kOctDirs[s][t];
         b0[s] = -lb[s];
     }
-    std::vector<std::vector<double>> pts;
     std::set<std::array<long long, 6>> seen;
     for (int o = 0; o < 8; ++o) {
         const double sg[3] = {(o & 4) ? 1.0 : -1.0, (o & 2) ? 1.0 : -1.0, (o & 1) ? 1.0 : -1.0};
@@ -285,9 +284,15 @@ void relu_hull_constraints(const double lb[26], int max_out, std::vector<GroupCo
             std::vector<double> p = {v[0], v[1], v[2], std::max(v[0], 0.0), std::max(v[1], 0.0), std::max(v[2], 0.0)};
             std::array<long long, 6> key;
             for (int t = 0; t < 6; ++t) key[t] = std::llround(p[t] * 1e12);
-            if (seen.insert(key).second) pts.push_back(p);
+            if (seen.insert(key).second) out->push_back(p);
         }
     }
+}
+
+void relu_hull_constraints(const double lb[26], int max_out, std::vector<GroupConstraint>* out) {
+    if (max_out <= 0) return;
+    std::vector<std::vector<double>> pts;
+    relu_hull_points(lb, &pts);
     if (pts.size() < 7) return;
     std::vector<std::vector<double>> nrm;
     std::vector<double> off;

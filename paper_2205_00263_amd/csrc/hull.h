@@ -22,6 +22,10 @@ struct GroupConstraint {
 bool hull_facets(const std::vector<std::vector<double>>& pts, int D, std::vector<std::vector<double>>* normals,
                  std::vector<double>* offsets);
 
+// The points (v, relu(v)) over the vertices v of Q intersected with each orthant (below),
+// deduplicated at 1e-12; empty if a bound is not finite.
+void relu_hull_points(const double lb[26], std::vector<std::vector<double>>* pts);
+
 // Constraints of the exact convex hull of {(v, relu(v)) : v in Q} for the polytope
 // Q = {v in R^3 : s . v >= lb_s for the 26 directions s}: relu is linear on each orthant, so the
 // hull is that of the points (v, relu(v)) over the vertices v of Q intersected with each orthant.

@@ -111,6 +111,8 @@ void launch_init_fc(const RowDesc* rows, int M, const float* W, const float* bia
                     float* c, bool write_c, hipStream_t st);
 void launch_init_conv(const RowDesc* rows, int M, const ConvGeom& g, const float* bias_eff, float* A, float* c,
                       bool write_c, hipStream_t st);
+void launch_init_oct(const int32_t* grp, int n_groups, int d, const float* bias, float* A, float* c,
+                     hipStream_t st);
 
 void launch_ibp_fc(const float* W, const float* b, const float* L, const float* U, float* Lo, float* Uo, int din,
                    int dout, hipStream_t st);

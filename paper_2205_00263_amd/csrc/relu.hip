@@ -338,6 +338,31 @@ void launch_init_conv(const RowDesc* rows, int M, const ConvGeom& g, const float
     }
 }
 
+// Octahedral rows of multi-neuron constraint generation: row r = 26 g + s carries direction s of
+// the 26 in {-1,0,1}^3 \ {0} (lexicographic in (s0, s1, s2), s2 fastest) on the three neurons of
+// group g, on the input of a ReLU layer; c_r = s . bias (the input node's bias).  A is zeroed first.
+__global__ void k_init_oct(const int32_t* grp, int n_groups, int d, const float* bias, float* A, float* c) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= 26 * n_groups) return;
+    const int g = r / 26, s = r - 26 * g;
+    const int code = s < 13 ? s : s + 1;   // skip the zero direction, code 13 of the 27
+    const int dir[3] = {code / 9 - 1, (code / 3) % 3 - 1, code % 3 - 1};
+    float cc = 0.f;
+    for (int t = 0; t < 3; ++t) {
+        const int j = grp[3 * g + t];
+        A[(long)r * d + j] = (float)dir[t];
+        cc += (float)dir[t] * bias[j];
+    }
+    c[r] = cc;
+}
+void launch_init_oct(const int32_t* grp, int n_groups, int d, const float* bias, float* A, float* c,
+                     hipStream_t st) {
+    if (n_groups <= 0) return;
+    launch_fill(A, (long)26 * n_groups * d, 0.f, st);
+    hipLaunchKernelGGL(k_init_oct, dim3(cdiv(26 * n_groups, 128)), dim3(128), 0, st, grp, n_groups, d, bias, A, c);
+    MNB_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ interval propagation
 // center/radius form of one affine node: c' = W c + b, r' = |W| r.
 __global__ void k_ibp_fc(const float* W, const float* b, const float* L, const float* U, float* Lo, float* Uo,

@@ -1,0 +1,159 @@
+"""On-device multi-neuron constraint generation (needs an MI355X): octahedral bounds through the
+back-substitution kernels, the ReLU hull on the host, against the oracle's generator (oracle/mnc.py)
+and against the network itself."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import backsub as ob
+from oracle import bab as obab
+from oracle import mnc as omnc
+from oracle import net as onet
+from oracle import optimize as oo
+
+from _common import assert_parity, oracle_query, root_unstable, sampled_min_sub
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CAP = 60
+# (configuration, radius): the small residual net needs a wider box to have unstable groups
+CASES = [(3, None), (2, None), (1, None), (4, 0.05)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_00263_amd as P
+    P.lib()
+    yield
+
+
+def _setup(cfg, eps):
+    import paper_2205_00263_amd as P
+    wl = W.make_workload(cfg, scale="small", eps=eps)
+    net_o, q = oracle_query(wl)
+    root, _ = oo.root_pass(q)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=64, max_mnc=CAP)
+    rid, _, _ = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    return wl, net_o, q, root, net, pb, rid
+
+
+def _dense(pb, rid, net_o, m):
+    rp, col, Pz, Ph, p = pb.get_mnc(rid, m)
+    d = net_o.sizes[net_o.relus[m]]
+    e = len(p)
+    Pm, Hm = np.zeros((e, d)), np.zeros((e, d))
+    for r in range(e):
+        for t in range(rp[r], rp[r + 1]):
+            Pm[r, col[t]] += Pz[t]
+            Hm[r, col[t]] += Ph[t]
+    return ob.Mnc(Pm, Hm, p.astype(np.float64)), col.reshape(-1, 3) if e else np.zeros((0, 3), int)
+
+
+@pytest.mark.parametrize("cfg,eps", CASES)
+def test_octahedral_bounds_match_oracle(cfg, eps):
+    """The 26 octahedral bounds of the oracle's groups, GPU against oracle.mnc.octahedral_bounds on the
+    oracle's own root bounds, within 1e-4."""
+    wl, net_o, q, root, net, pb, rid = _setup(cfg, eps)
+    n = 0
+    for m, i in enumerate(net_o.relus):
+        groups = omnc.make_groups(root.states[i])[:6]
+        if not groups:
+            continue
+        got = pb.octahedral_bounds(rid, m, np.array(groups))
+        for g, grp in enumerate(groups):
+            ref = omnc.octahedral_bounds(net_o, root.states, i, grp, q.lo, q.hi)
+            assert_parity(got[g], ref, f"layer {m} group {grp}")
+            n += 1
+    assert n > 0
+
+
+@pytest.mark.parametrize("cfg,eps", CASES)
+def test_generated_constraints_match_oracle_generator(cfg, eps):
+    """mnb_mnc_generate against oracle.mnc.generate with the same cap: the same groups in the same order
+    and, for every group both keep whole, the same constraints within 1e-4 (the library stores float32
+    coefficients).  The last group of a layer that reaches the cap is cut in different places (the hull
+    lists facets in different orders) and groups where the oracle's Qhull needed its joggled mode carry
+    extra near-facets there; both are left out of the set comparison."""
+    wl, net_o, q, root, net, pb, rid = _setup(cfg, eps)
+    e = pb.mnc_generate(rid, cap=CAP)
+    ref = omnc.generate(net_o, root.states, q.lo, q.hi, cap=CAP)
+    compared = 0
+    for m, i in enumerate(net_o.relus):
+        R = ref[i]
+        mnc, groups = _dense(pb, rid, net_o, m)
+        assert mnc.e == e[m] <= CAP
+        # group of each oracle constraint: the oracle's group that holds its nonzero columns
+        owner = {}
+        for grp in omnc.make_groups(root.states[i]):
+            for j in grp:
+                owner[j] = tuple(sorted(grp))
+        rg = [owner[int(np.nonzero((R.P[r] != 0) | (R.Phat[r] != 0))[0][0])] for r in range(R.e)]
+        gg = [tuple(sorted(g)) for g in groups]
+        order_o = list(dict.fromkeys(tuple(sorted(g)) for g in rg))
+        order_g = list(dict.fromkeys(gg))
+        k = min(len(order_o), len(order_g))
+        assert order_o[:k - 1] == order_g[:k - 1], (m, order_o[:k], order_g[:k])
+        for grp in order_g[:k - 1]:
+            A = np.array([np.concatenate([R.Phat[r][list(grp)], R.P[r][list(grp)], [R.p[r]]])
+                          for r in range(R.e) if tuple(sorted(rg[r])) == grp])
+            B = np.array([np.concatenate([mnc.Phat[r][list(grp)], mnc.P[r][list(grp)], [mnc.p[r]]])
+                          for r in range(mnc.e) if gg[r] == grp])
+            if len(A) != len(B):
+                continue   # the oracle's joggled hull
+            for x in B:
+                assert np.min(np.abs(A - x).max(1)) <= 1e-4 * (1 + np.abs(x).max()), (m, grp, x)
+            compared += 1
+    assert compared > 0
+
+
+@pytest.mark.parametrize("cfg,eps", CASES)
+def test_generated_constraints_hold_on_the_network(cfg, eps):
+    """Every generated constraint P z + Phat zhat <= p holds at dense samples of the input box (the
+    network's own values of the layer), and optimising with them never bounds above a sampled
+    minimum; the bounds match the oracle run on the library's own constraints."""
+    wl, net_o, q, root, net, pb, rid = _setup(cfg, eps)
+    e = pb.mnc_generate(rid, cap=CAP)
+    assert e.sum() > 0
+    rng = np.random.default_rng(cfg)
+    X = rng.uniform(wl.lo, wl.hi, size=(20000, len(wl.lo)))
+    X = np.vstack([X, np.where(rng.integers(0, 2, size=(512, len(wl.lo))) > 0, wl.hi, wl.lo)])
+    vals = onet.forward_all(net_o, X)
+    mncs = {}
+    for m, i in enumerate(net_o.relus):
+        mnc, _ = _dense(pb, rid, net_o, m)
+        mncs[i] = mnc
+        if mnc.e == 0:
+            continue
+        zh, z = vals[net_o.nodes[i]["src"]], vals[i]
+        lhs = z @ mnc.P.T + zh @ mnc.Phat.T
+        assert np.all(lhs <= mnc.p + 1e-5 * (1 + np.abs(mnc.p))), (m, (lhs - mnc.p).max())
+    oo.attach_mncs(q, root, mncs)
+    unst = root_unstable(net_o, root)
+    m0 = next(t for t in range(len(unst)) if len(unst[t]))
+    j0 = int(unst[m0][0])
+    kids = pb.branch_split([rid], [m0], [j0])
+    okids = obab.branch_split(net_o, root, m0, j0)
+    lb, _ = pb.bound_optimize(kids, steps=4)
+    for b in range(2):
+        ref = oo.bound_optimize(q, okids[b], steps=4).lb
+        assert_parity(lb[b], ref, f"child {b} with generated constraints")
+        S = {i: okids[b].states[i].S for i in net_o.relus}
+        assert np.all(lb[b] <= sampled_min_sub(net_o, wl, S) + 1e-6)
+
+
+def test_generate_needs_a_lone_root():
+    import paper_2205_00263_amd as P
+    wl, net_o, q, root, net, pb, rid = _setup(3, None)
+    l, u, _ = pb.get_bounds(rid, 1)
+    j = int(np.nonzero((l < 0) & (u > 0))[0][0])
+    kids = pb.branch_split([rid], [1], [j])
+    with pytest.raises(P.MnbError):
+        pb.mnc_generate(rid, cap=CAP)
+    pb.release(list(kids))
+    assert pb.mnc_generate(rid, cap=CAP).sum() > 0
+    with pytest.raises(P.MnbError):
+        pb.mnc_generate(rid, cap=CAP + 1)
