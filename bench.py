@@ -1,20 +1,29 @@
 """Benchmark: BaB subproblems bounded per second on one MI355X.
 
-Workload (default): ConvSmall-shaped network (1x28x28 -> conv 16 4x4/2 -> conv 32
-4x4/2 -> FC 100 -> FC 10, He-normal FP32, seeded), eps = 0.03, 9 spec rows,
-a batch of 512 subproblems with 1-8 random splits among the root-unstable
-neurons; one step = one bound_optimize of the batch: intermediate bounds of
-the layers after each subproblem's earliest split recomputed and alpha/beta
-optimised by 20 Adam steps (lr 0.1) through the hand-written adjoint.
-Inputs (network, boxes, subproblem state) are resident in HBM before timing.
-Beside the batch it times two per-subproblem loops on the same subproblems:
-the library called with one subproblem at a time, and a plain PyTorch loop
-(autograd + torch.optim.Adam), each with the bounds it reaches.
+Workload (default, --config 3): the ConvBig-shaped network (3x32x32 -> conv 32
+3x3/1/1 -> conv 32 4x4/2/1 -> conv 64 3x3/1/1 -> conv 64 4x4/2/1 -> FC 512 ->
+FC 512 -> FC 10, He-normal FP32, seeded), eps = 2/255, 9 spec rows, multi-neuron
+constraints generated on the device for the root (groups of three unstable
+neurons, <= 500 per ReLU layer), and a batch of 1024 subproblems with 1-8 random
+splits among the root-unstable neurons.  A subproblem is bounded by 20 Adam
+steps on (alpha, beta, gamma) through the hand-written adjoint, each step
+recomputing the intermediate bounds of the layers after its earliest split and
+then bounding the spec rows.  One timed step is one such Adam iteration over the
+whole batch (bound_optimize_step of a session); value = batch / (20 x step time
++ the final evaluation), with inputs and state resident in HBM.  A short Poisson
+stream of verification queries through the continuous-batching server gives the
+p50/p99 query latency in the same line.
 
---serving runs the query stream instead: Poisson arrivals of queries on the
-FC / ConvSmall / ConvBig nets (one spec row, eps ~ U[0.005, 0.03]) through the
-continuous-batching server, with p50/p99 query latency, subproblems/s and the
-verdict mix, and the same stream served one query at a time by a
+--config 2 measures the ConvSmall-shaped network instead (1x28x28 -> conv 16
+4x4/2 -> conv 32 4x4/2 -> FC 100 -> FC 10, eps = 0.03, 512 subproblems, alpha and
+beta), one step being one whole bound_optimize of the batch, beside two
+per-subproblem loops on the same subproblems (the library one subproblem at a
+time, and a plain PyTorch loop with autograd and torch.optim.Adam).
+
+--serving runs the full query stream instead: Poisson arrivals of queries on
+the FC / ConvSmall / ConvBig nets (one spec row, eps ~ U[0.005, 0.03]) through
+the continuous-batching server, with p50/p99 query latency, subproblems/s and
+the verdict mix, and the same stream served one query at a time by a
 per-subproblem loop for comparison.
 
 Prints one JSON line (see the repository's measurement notes).
@@ -32,8 +41,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BATCH = 512
-SPLIT_SEED = 3002
+SPLIT_SEED_CS = 3002   # ConvSmall split sets
+SPLIT_SEED_CB = 3003   # ConvBig split sets
+MNC_CAP = 500          # multi-neuron constraints per ReLU layer (ConvBig)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bottom_convsmall_traffic.json")
 # sources that fix the fused kernel and the rows each of its launches gets
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_00263_amd", "csrc", f)
@@ -482,48 +492,38 @@ def bab_run(args):
                       "queries": res}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=BATCH)
-    ap.add_argument("--adam-steps", type=int, default=20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--no-loop-baseline", action="store_true",
-                    help="skip the per-subproblem loops (library at batch 1, PyTorch autograd)")
-    ap.add_argument("--loop-budget", type=float, default=10.0, help="seconds per per-subproblem loop")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="run one 1 GiB device copy first (a kernel of known traffic for counter calibration)")
-    ap.add_argument("--roofline-kernel", default="bottom",
-                    help="kernel class timed for the roofline object (dominant one for this workload)")
-    ap.add_argument("--serving", action="store_true", help="serving stream instead of the batch benchmark")
-    ap.add_argument("--bab", action="store_true", help="complete BaB of ResNet6 queries instead of the batch benchmark")
-    ap.add_argument("--bab-eps", type=float, default=1 / 255)
-    ap.add_argument("--bab-queries", type=int, default=4)
-    ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--serve-rate", type=float, default=10.0, help="Poisson arrival rate (queries/s)")
-    ap.add_argument("--serve-timeout", type=float, default=60.0)
-    ap.add_argument("--serve-batch", type=int, default=1024)
-    ap.add_argument("--serve-nets", default="1,2,3", help="configurations whose nets the stream draws from")
-    ap.add_argument("--serve-loop-budget", type=float, default=60.0,
-                    help="seconds for the per-subproblem FIFO loop on the same stream (0: skip)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(subproblems shard across GPUs without collectives; see the design notes)", file=sys.stderr)
-        sys.exit(2)
+def roofline_of(kstats, traffic=None):
+    """Roofline object of one timed kernel class: its bound follows from its algorithmic intensity
+    against the MI355X ridge point (FP32 MFMA 157.3 TFLOP/s over HBM 8 TB/s = 19.7 flop/byte)."""
+    if not kstats or kstats["count"] == 0:
+        return None
+    avg_s = kstats["ms"] / kstats["count"] / 1e3
+    flops = kstats["flops"] / kstats["count"]
+    byts = kstats["bytes"] / kstats["count"]
+    ridge = 157.3e12 / 8.0e12
+    if byts > 0 and (flops == 0 or flops / byts < ridge):
+        achieved = byts / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4)}
+    else:
+        achieved = flops / avg_s / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": 157.3, "unit": "TFLOP/s",
+                "frac": round(achieved / 157.3, 4)}
+    roof.update({"traffic": traffic, "kernel": kstats["name"], "launches": kstats["count"],
+                 "avg_us": round(avg_s * 1e6, 2), "algorithmic_gflop_per_launch": round(flops / 1e9, 4),
+                 "algorithmic_mb_per_launch": round(byts / 1e6, 3),
+                 "flop_per_byte": round(flops / byts, 2) if byts > 0 else None})
+    return roof
 
-    if args.serving:
-        serving(args)
-        return
-    if args.bab:
-        bab_run(args)
-        return
+
+def convsmall_batch(args):
+    """The ConvSmall batch (--config 2): one step = one bound_optimize of 512 subproblems."""
     import torch
     import paper_2205_00263_amd as P
     import workloads as W
+
+    args.batch = args.batch or 512
+    args.roofline_kernel = args.roofline_kernel or "bottom"
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -542,7 +542,7 @@ def main():
     for m in range(net.n_relu):
         l, u, _ = pb.get_bounds(rid, m)
         unstable.append(np.nonzero((l < 0) & (u > 0))[0])
-    splits = W.make_split_sets(unstable, args.batch, 1, 8, seed=SPLIT_SEED)
+    splits = W.make_split_sets(unstable, args.batch, 1, 8, seed=SPLIT_SEED_CS)
     batches = [make_batch(P, pb, rid, splits) for _ in range(n_steps)]
     kw = dict(steps=args.adam_steps, lr=0.1)
 
@@ -564,27 +564,7 @@ def main():
     kstats = timer.stop()
     n_bounded = args.batch * args.steps
     value = n_bounded / el
-    roof = None
-    if kstats and kstats["count"] > 0:
-        avg_s = kstats["ms"] / kstats["count"] / 1e3
-        flops = kstats["flops"] / kstats["count"]
-        byts = kstats["bytes"] / kstats["count"]
-        # the kernel's bound follows from its algorithmic intensity against the MI355X ridge point
-        # (FP32 MFMA 157.3 TFLOP/s over HBM 8 TB/s = 19.7 flop/byte)
-        ridge = 157.3e12 / 8.0e12
-        if byts > 0 and (flops == 0 or flops / byts < ridge):
-            achieved = byts / avg_s / 1e9
-            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                    "frac": round(achieved / 8000.0, 4)}
-        else:
-            achieved = flops / avg_s / 1e12
-            roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": 157.3, "unit": "TFLOP/s",
-                    "frac": round(achieved / 157.3, 4)}
-        roof.update({"traffic": measured_traffic(args.roofline_kernel), "kernel": kstats["name"],
-                     "launches": kstats["count"], "avg_us": round(avg_s * 1e6, 2),
-                     "algorithmic_gflop_per_launch": round(flops / 1e9, 4),
-                     "algorithmic_mb_per_launch": round(byts / 1e6, 3),
-                     "flop_per_byte": round(flops / byts, 2) if byts > 0 else None})
+    roof = roofline_of(kstats, measured_traffic(args.roofline_kernel))
     out = {
         "metric": "BaB subproblems bounded/sec (alpha,beta-optimised, 20 Adam steps) + p50/p99 batch latency",
         "value": round(value, 2), "unit": "subproblems/s", "n_gpus": 1, "steps": args.steps,
@@ -614,6 +594,260 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, splits, args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+
+def host_cores():
+    """(cores this process may run on, CPU model) of the host."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return int(n), model
+
+
+def cpu_baseline_convbig(wl, mean_rows, threads, rows_per_layer=16):
+    """The FP64 oracle on a bounded sample of the ConvBig workload: one Adam iteration's work (the
+    back-substitution of Eq. 2 / Eq. 5 / Eq. 6 and the analytic gradient) of a few rows of every
+    recomputed layer and of the spec rows, timed per row and scaled by the batch's mean rows per
+    subproblem and layer, with BLAS limited to `threads` threads.  The oracle's own bounds come from an
+    interval pass of the same net and box (the work per row does not depend on the bound values)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import backsub as ob
+    from oracle import net as onet
+    from oracle import optimize as oo
+    net = onet.Net(wl.nodes)
+    lo, hi = np.asarray(wl.lo, np.float64), np.asarray(wl.hi, np.float64)
+    states = {}
+    for i in net.relus:
+        src = net.nodes[i]["src"]
+        L, U = onet.interval_forward(net, lo, hi, {k: (st.l, st.u) for k, st in states.items()}, src)
+        states[i] = ob.ReluState(L[src], U[src])
+    params = {i: {"alpha": ob.heuristic_alpha(st), "beta": np.zeros(st.l.shape)} for i, st in states.items()}
+    t_row, t_total = {}, 0.0
+    with threadpool_limits(limits=threads):
+        for m, i in enumerate(net.relus):
+            if m == 0 or mean_rows.get(m, 0.0) == 0.0:
+                continue
+            js = np.nonzero((states[i].l < 0) & (states[i].u > 0))[0][:rows_per_layer]
+            t0 = time.perf_counter()
+            out = ob.backsub(net, ob.neuron_start(net, i, js, 1), np.zeros(len(js)), states, params, None, lo, hi)
+            oo.bound_grads(net, out)
+            dt = time.perf_counter() - t0
+            t_row[m] = dt / len(js)
+            t_total += dt
+        t0 = time.perf_counter()
+        out = ob.backsub(net, ob.spec_start(net, wl.C), wl.c0, states, params, None, lo, hi)
+        oo.bound_grads(net, out)
+        t_spec = time.perf_counter() - t0
+        t_total += t_spec
+    per_iter = sum(mean_rows[m] * t for m, t in t_row.items()) + t_spec
+    return {"value": 1.0 / (20.0 * per_iter), "unit": "subproblems/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 numpy back-substitution + analytic gradient of {rows_per_layer} rows of each recomputed "
+                      f"layer and the {len(wl.C)} spec rows ({t_total:.1f} s), scaled by the batch's mean rows per "
+                      f"subproblem and layer {dict((m, round(v, 1)) for m, v in mean_rows.items())} and 20 Adam "
+                      f"steps: {per_iter:.1f} s of CPU per subproblem step",
+            "seconds_per_row": {str(m): round(t, 4) for m, t in t_row.items()}}
+
+
+def query_stream(args, n_queries):
+    """A short Poisson stream of queries on the FC / ConvSmall / ConvBig nets through the server: p50/p99
+    query latency, subproblems/s and the verdict mix."""
+    import collections
+    import paper_2205_00263_amd as P
+    import workloads as W
+    cfgs = [int(c) for c in args.serve_nets.split(",")]
+    nodes = [W.make_net(c) for c in cfgs]
+    nets = [P.Net(n) for n in nodes]
+    stream = make_stream(W, nodes, n_queries, args.serve_rate)
+    srv = P.Server(nets, max_batch=args.serve_batch, steps=args.adam_steps, lr=0.1)
+    for ni in range(len(nets)):   # untimed warm-up: problem pools are created on first use
+        q = next(x for x in stream if x[1] == ni)
+        srv.wait(srv.query_submit(ni, *q[2:], timeout_s=5.0), timeout=600)
+    t0 = time.perf_counter()
+    tickets = []
+    for (ta, ni, lo, hi, Cm, c0) in stream:
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.query_submit(ni, lo, hi, Cm, c0, timeout_s=args.serve_timeout))
+    res = [srv.wait(tk, timeout=args.serve_timeout + 600) for tk in tickets]
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r["latency"] for r in res])
+    n_sub = int(sum(r["subproblems"] for r in res))
+    return {"queries": len(res), "p50_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_s": round(float(np.percentile(lat, 99)), 4), "subproblems_per_s": round(n_sub / wall, 1),
+            "wall_s": round(wall, 2), "verdicts": dict(collections.Counter(r["verdict"] for r in res)),
+            "nets": [f"cfg{c}" for c in cfgs], "arrivals": f"Poisson {args.serve_rate}/s", "n_spec": 1,
+            "eps": "U[0.005,0.03]", "timeout_s": args.serve_timeout}
+
+
+def convbig_batch(args):
+    """The headline: ConvBig with generated multi-neuron constraints, 1024 subproblems, alpha, beta and
+    gamma; one timed step = one Adam iteration of the whole batch."""
+    import torch
+    import paper_2205_00263_amd as P
+    import workloads as W
+
+    B = args.batch or 1024
+    kind = args.roofline_kernel or "conv_backsub"
+    node = args.roofline_node
+    T = args.adam_steps
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    P.use_torch_plumbing(True)
+    wl = W.make_workload(3)
+    net = P.Net(wl.nodes)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=2 * B + 64, max_mnc=MNC_CAP)
+    t = time.perf_counter()
+    rid, root_lb, root_ub = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
+    t_init = time.perf_counter() - t
+    t = time.perf_counter()
+    n_mnc = pb.mnc_generate(rid, cap=MNC_CAP)
+    t_mnc = time.perf_counter() - t
+    unstable = []
+    for m in range(net.n_relu):
+        l, u, _ = pb.get_bounds(rid, m)
+        unstable.append(np.nonzero((l < 0) & (u > 0))[0])
+    splits = W.make_split_sets(unstable, B, 1, 8, seed=SPLIT_SEED_CB)
+    ids = make_batch(P, pb, rid, splits)
+    # rows each subproblem recomputes per layer (2 per unstable neuron of the layers after its
+    # earliest split), on a sample of the batch: the CPU baseline's scale
+    mean_rows = {}
+    sample = list(range(0, B, max(1, B // 64)))
+    for m in range(1, net.n_relu):
+        tot = 0
+        for b in sample:
+            if min(sp[0] for sp in splits[b]) + 1 <= m:
+                l, u, _ = pb.get_bounds(int(ids[b]), m)
+                tot += 2 * int(np.sum((l < 0) & (u > 0)))
+        mean_rows[m] = tot / len(sample)
+    log(f"root lb {root_lb.min():.3f}, constraints per layer {n_mnc.tolist()} ({t_mnc:.2f} s), batch of {B} ready")
+    sess = pb.optimize_begin(ids, steps=T, lr=0.1)
+    for w in range(args.warmup):
+        sess.step()
+        torch.cuda.synchronize()
+        log(f"warm-up step {w + 1}/{args.warmup}")
+    timer = P.KernelTimer(net, kind=kind, node=node)
+    timer.start()
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        sess.step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        log(f"step {k + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
+    el = time.perf_counter() - t0
+    kstats = timer.stop()
+    t = time.perf_counter()
+    lb, ub = sess.end()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter() - t
+    step_s = el / args.steps
+    value = B / (T * step_s + t_end)
+    out = {
+        "metric": "BaB subproblems bounded/sec (alpha,beta,gamma-optimised) + p50/p99 query latency",
+        "value": round(value, 3), "unit": "subproblems/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "convbig_mnc_batch",
+                   "net": "ConvBig 3x32x32 c32k3s1p1 c32k4s2p1 c64k3s1p1 c64k4s2p1 fc512 fc512 fc10",
+                   "eps": round(2 / 255, 6), "n_spec": int(wl.C.shape[0]), "batch": B, "split_depth": "1-8",
+                   "adam_steps": T, "lr": 0.1, "mnc_cap": MNC_CAP, "mnc_per_layer": n_mnc.tolist(),
+                   "step": "one Adam iteration (evaluation with intermediate recompute, adjoint, update) of the "
+                           "whole batch",
+                   "value": "batch / (adam_steps x step time + final evaluation)"},
+        "timing": {"final_evaluation_ms": round(t_end * 1e3, 2), "bound_init_ms": round(t_init * 1e3, 2),
+                   "mnc_generate_ms": round(t_mnc * 1e3, 2),
+                   "step_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                   "step_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+        "bound_summary": {"root_lb_min": float(root_lb.min()), "root_ub_min": float(root_ub.min()),
+                          "batch_lb_mean": float(lb.min(1).mean())},
+        "roofline": roofline_of(kstats),
+    }
+    if args.stream_queries > 0:
+        log(f"query stream: {args.stream_queries} queries")
+        qs = query_stream(args, args.stream_queries)
+        out["p50_s"], out["p99_s"] = qs["p50_s"], qs["p99_s"]
+        out["query_stream"] = qs
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        n, model = host_cores()
+        cb = cpu_baseline_convbig(wl, mean_rows, n)
+        cb1 = cpu_baseline_convbig(wl, mean_rows, 1)
+        cb["cpu_model"] = model
+        cb["single_thread"] = {"value": cb1["value"], "cores": 1}
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3, choices=[2, 3],
+                    help="3: ConvBig with multi-neuron constraints (default); 2: ConvSmall")
+    ap.add_argument("--batch", type=int, default=None, help="subproblems per batch (default 1024 / 512)")
+    ap.add_argument("--adam-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-loop-baseline", action="store_true",
+                    help="skip the per-subproblem loops (library at batch 1, PyTorch autograd)")
+    ap.add_argument("--loop-budget", type=float, default=10.0, help="seconds per per-subproblem loop")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first (a kernel of known traffic for counter calibration)")
+    ap.add_argument("--roofline-node", type=int, default=None,
+                    help="network node whose launches the roofline times (default: ConvBig's second convolution)")
+    ap.add_argument("--roofline-kernel", default=None,
+                    help="kernel class timed for the roofline object (dominant one for this workload)")
+    ap.add_argument("--serving", action="store_true", help="serving stream instead of the batch benchmark")
+    ap.add_argument("--bab", action="store_true", help="complete BaB of ResNet6 queries instead of the batch benchmark")
+    ap.add_argument("--bab-eps", type=float, default=1 / 255)
+    ap.add_argument("--bab-queries", type=int, default=4)
+    ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=10.0, help="Poisson arrival rate (queries/s)")
+    ap.add_argument("--serve-timeout", type=float, default=60.0)
+    ap.add_argument("--serve-batch", type=int, default=1024)
+    ap.add_argument("--serve-nets", default="1,2,3", help="configurations whose nets the stream draws from")
+    ap.add_argument("--serve-loop-budget", type=float, default=60.0,
+                    help="seconds for the per-subproblem FIFO loop on the same stream (0: skip)")
+    ap.add_argument("--stream-queries", type=int, default=200,
+                    help="Poisson queries served after the ConvBig batch for the latency keys (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(subproblems shard across GPUs without collectives; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    if args.serving:
+        serving(args)
+        return
+    if args.bab:
+        bab_run(args)
+        return
+    if args.config == 2:
+        args.roofline_node = -1 if args.roofline_node is None else args.roofline_node
+        convsmall_batch(args)
+    else:
+        args.roofline_node = 3 if args.roofline_node is None else args.roofline_node
+        convbig_batch(args)
 
 
 if __name__ == "__main__":
