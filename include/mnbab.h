@@ -59,7 +59,7 @@ int mnb_set_allocator(mnb_alloc_fn alloc, mnb_free_fn free_fn, void* ctx);
 int mnb_set_stream(void* hip_stream);
 
 /* ------------------------------------------------------------------ network */
-enum { MNB_INPUT = 0, MNB_FC = 1, MNB_CONV = 2, MNB_RELU = 3, MNB_ADD = 4 };
+enum { MNB_INPUT = 0, MNB_FC = 1, MNB_CONV = 2, MNB_RELU = 3, MNB_ADD = 4, MNB_BN = 5, MNB_AVGPOOL = 6 };
 
 /* One node of the network DAG (Section 2.1: affine layers zhat = W z + b,
  * ReLUs z = max(0, zhat); convolutional and residual layers as the paper's
@@ -69,7 +69,16 @@ enum { MNB_INPUT = 0, MNB_FC = 1, MNB_CONV = 2, MNB_RELU = 3, MNB_ADD = 4 };
  * MNB_CONV: W [Co][Ci][k][k], b [Co], stride, pad (zero padding), output
  * shape derived from the input shape.  MNB_RELU follows an MNB_FC, MNB_CONV
  * or MNB_ADD node; MNB_ADD joins two affine nodes of equal shape.  The last
- * node must be MNB_FC (the logits). in_chw/out_chw are checked when nonzero. */
+ * node must be MNB_FC (the logits). in_chw/out_chw are checked when nonzero.
+ * Batch normalisation and average pooling (Section 2.1 lists both among the
+ * layers the method covers; both are affine): MNB_BN, y = gamma (x - mean) /
+ * sqrt(var + eps) + beta per channel with W = [gamma | beta | mean | var]
+ * (4 x C floats) and eps, must directly follow an MNB_FC or MNB_CONV node that
+ * has no other consumer and is folded into that node's weights and bias;
+ * MNB_AVGPOOL (k, stride, pad; the mean over each k x k window with the zero
+ * padding counted, divisor k^2) becomes a convolution with 1/k^2 between equal
+ * channels.  Node indices of the other entry points (kernel-level calls,
+ * timer) count the nodes after this translation: MNB_BN nodes removed. */
 typedef struct {
     int kind;
     int src;
@@ -79,6 +88,7 @@ typedef struct {
     int k, stride, pad;
     const float* W;
     const float* b;
+    float eps;
 } mnb_layer;
 
 typedef struct mnb_net mnb_net;
@@ -358,7 +368,9 @@ int mnb_get_kernel_variants(void);
 
 /* ------------------------------------------------------------------ serving */
 /* A verification query for the server: box, spec and MNC sets as in
- * bound_init, plus a per-query wall-clock budget. */
+ * bound_init, plus a per-query wall-clock budget.  With mnc_cap > 0 and no
+ * MNC sets given, the server generates them for the query's root on the device
+ * (mnb_mnc_generate, at most mnc_cap <= 500 per ReLU layer). */
 typedef struct {
     int net_index;         /* index into the nets the server was created with */
     const float* x_lo;
@@ -369,22 +381,32 @@ typedef struct {
     const mnb_mnc* mnc;
     int n_mnc;
     double timeout_s;
+    int mnc_cap;
 } mnb_query;
 
 enum { MNB_VERIFIED = 1, MNB_FALSIFIED = 2, MNB_UNKNOWN = 3, MNB_TIMEOUT = 4 };
+/* Why a query ended UNKNOWN (or TIMEOUT). */
+enum { MNB_R_NONE = 0, MNB_R_NO_SPLIT = 1 /* a leaf with no unstable, unsplit neuron left */,
+       MNB_R_QUEUE_CAP = 2 /* its own queue_cap of live subproblems */,
+       MNB_R_MEMORY = 3 /* alone on the server, its tree outgrew the memory budget */,
+       MNB_R_ERROR = 4 /* a library error (see the server's error text) */, MNB_R_TIME = 5 };
 
 typedef struct {
     int verdict;           /* MNB_VERIFIED / MNB_FALSIFIED / MNB_UNKNOWN / MNB_TIMEOUT */
     float lb;              /* min over spec rows of the root's optimised lb        */
     int64_t subproblems;   /* subproblems bounded for this query                   */
     double t_submit, t_admit, t_done;  /* seconds on the server's clock            */
+    int reason;            /* MNB_R_*                                              */
+    int restarts;          /* times the query was preempted and started again      */
 } mnb_result;
 
 typedef struct {
-    mnb_opt_cfg opt;       /* per-batch optimisation settings                      */
+    mnb_opt_cfg opt;       /* per-batch optimisation settings (opt.mem_budget 0:   */
+                           /* a quarter of mem_budget per call)                    */
     int max_batch;         /* subproblems per engine step                          */
     int64_t queue_cap;     /* live subproblems per query before UNKNOWN            */
-    size_t mem_budget;     /* device bytes the admitted queries may hold           */
+    size_t mem_budget;     /* device bytes of all slot pools and workspaces        */
+    int64_t max_slots;     /* slots per pool at most (0: as many as mem_budget allows) */
 } mnb_server_cfg;
 void mnb_server_cfg_default(mnb_server_cfg* cfg);
 
@@ -392,11 +414,24 @@ typedef struct mnb_server mnb_server;
 /* Continuous-batching server: a host thread admits queries as slots and the
  * memory budget allow, advances every live subproblem batch by one
  * bound_optimize call per iteration, and branches or retires subproblems
- * (lb > 0 on every spec row: verified; ub < 0: counterexample). */
+ * (lb > 0 on every spec row: verified; ub < 0: counterexample).
+ * Memory: each (net, spec count, constraint use) has a slot pool that starts
+ * small and doubles while the pools and the problems' workspaces stay within
+ * mem_budget.  When a split finds no room its parent waits (parked, not
+ * bounded again) and is split as soon as slots free up; parked splits take
+ * precedence over admitting new queries.  If an iteration can neither bound
+ * nor split anything, the most recently admitted query holding slots is
+ * preempted (its subproblems released, the query queued again at the front
+ * to start over, result.restarts counted); a query alone on the server whose
+ * tree no longer fits ends UNKNOWN with reason MNB_R_MEMORY.  A query's own
+ * queue_cap still ends it UNKNOWN (MNB_R_QUEUE_CAP).  Waiting queries time
+ * out like live ones. */
 int mnb_server_create(mnb_net* const* nets, int n_nets, const mnb_server_cfg* cfg,
                       mnb_server** out);
 void mnb_server_destroy(mnb_server* srv);
-/* Non-blocking, thread-safe. */
+/* Non-blocking, thread-safe.  MNB_EINVAL (nothing queued) for bad arrays, a bad
+ * net index, more than 500 constraints per layer, or a query whose root and
+ * first two children alone exceed mem_budget. */
 int query_submit(mnb_server* srv, const mnb_query* q, uint64_t* ticket);
 /* MNB_PENDING until the query is done; then MNB_OK and *out filled. */
 int query_poll(mnb_server* srv, uint64_t ticket, mnb_result* out);

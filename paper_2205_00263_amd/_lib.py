@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libmnbab.so")
 
 MNB_OK, MNB_PENDING = 0, 1
 MNB_EINVAL, MNB_ENOMEM, MNB_EDEVICE, MNB_ETIMEOUT, MNB_ESTATE = -1, -2, -3, -4, -5
-MNB_INPUT, MNB_FC, MNB_CONV, MNB_RELU, MNB_ADD = 0, 1, 2, 3, 4
+MNB_INPUT, MNB_FC, MNB_CONV, MNB_RELU, MNB_ADD, MNB_BN, MNB_AVGPOOL = 0, 1, 2, 3, 4, 5, 6
 MNB_VERIFIED, MNB_FALSIFIED, MNB_UNKNOWN, MNB_TIMEOUT = 1, 2, 3, 4
 
 fp = C.POINTER(C.c_float)
@@ -21,7 +21,7 @@ class Layer(C.Structure):
     _fields_ = [("kind", C.c_int), ("src", C.c_int), ("src2", C.c_int),
                 ("in_chw", C.c_int * 3), ("out_chw", C.c_int * 3),
                 ("k", C.c_int), ("stride", C.c_int), ("pad", C.c_int),
-                ("W", fp), ("b", fp)]
+                ("W", fp), ("b", fp), ("eps", C.c_float)]
 
 
 class Mnc(C.Structure):
@@ -38,17 +38,18 @@ class OptCfg(C.Structure):
 class Query(C.Structure):
     _fields_ = [("net_index", C.c_int), ("x_lo", fp), ("x_hi", fp), ("C", fp), ("c0", fp),
                 ("n_spec", C.c_int), ("mnc", C.POINTER(Mnc)), ("n_mnc", C.c_int),
-                ("timeout_s", C.c_double)]
+                ("timeout_s", C.c_double), ("mnc_cap", C.c_int)]
 
 
 class Result(C.Structure):
     _fields_ = [("verdict", C.c_int), ("lb", C.c_float), ("subproblems", C.c_int64),
-                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("reason", C.c_int), ("restarts", C.c_int)]
 
 
 class ServerCfg(C.Structure):
     _fields_ = [("opt", OptCfg), ("max_batch", C.c_int), ("queue_cap", C.c_int64),
-                ("mem_budget", C.c_size_t)]
+                ("mem_budget", C.c_size_t), ("max_slots", C.c_int64)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

@@ -73,7 +73,7 @@ def _layer_array(nodes):
     arr = (_lib.Layer * len(nodes))()
     keep = []
     kinds = {"input": _lib.MNB_INPUT, "fc": _lib.MNB_FC, "conv": _lib.MNB_CONV,
-             "relu": _lib.MNB_RELU, "add": _lib.MNB_ADD}
+             "relu": _lib.MNB_RELU, "add": _lib.MNB_ADD, "bn": _lib.MNB_BN, "avgpool": _lib.MNB_AVGPOOL}
     for i, n in enumerate(nodes):
         L = arr[i]
         L.kind = kinds[n["kind"]]
@@ -90,6 +90,13 @@ def _layer_array(nodes):
         if n["kind"] == "conv":
             L.k = n["W"].shape[2]
             L.stride, L.pad = n["stride"], n["pad"]
+        if n["kind"] == "bn":
+            stats = np.ascontiguousarray(np.concatenate([np.asarray(n[k], np.float32).ravel()
+                                                         for k in ("gamma", "beta", "mean", "var")]))
+            keep.append(stats)
+            L.W, L.eps = _ptr(stats), float(n["eps"])
+        if n["kind"] == "avgpool":
+            L.k, L.stride, L.pad = n["k"], n["stride"], n["pad"]
     return arr, keep
 
 
@@ -471,16 +478,18 @@ class KernelTimer:
 
 # --------------------------------------------------------------------------- serving
 VERDICTS = {1: "verified", 2: "falsified", 3: "unknown", 4: "timeout"}
+REASONS = {0: "none", 1: "no_split", 2: "queue_cap", 3: "memory", 4: "error", 5: "time"}
 
 
 class Server:
     """Continuous-batching verification server (query_submit / query_poll)."""
 
-    def __init__(self, nets, max_batch=256, queue_cap=4096, mem_budget=64 << 30, steps=20, lr=0.1):
+    def __init__(self, nets, max_batch=256, queue_cap=4096, mem_budget=64 << 30, steps=20, lr=0.1, max_slots=0):
         self.nets = list(nets)
         cfg = _lib.ServerCfg()
         lib().mnb_server_cfg_default(C.byref(cfg))
         cfg.max_batch, cfg.queue_cap, cfg.mem_budget = int(max_batch), int(queue_cap), int(mem_budget)
+        cfg.max_slots = int(max_slots)
         cfg.opt.steps, cfg.opt.lr = int(steps), float(lr)
         arr = (C.c_void_p * len(self.nets))(*[n.h.value for n in self.nets])
         h = C.c_void_p()
@@ -498,7 +507,7 @@ class Server:
         except Exception:
             pass
 
-    def query_submit(self, net_index, lo, hi, Cm, c0, mncs=None, timeout_s=60.0):
+    def query_submit(self, net_index, lo, hi, Cm, c0, mncs=None, timeout_s=60.0, mnc_cap=0):
         lo, hi, Cm, c0 = _f32(lo), _f32(hi), _f32(Cm), _f32(c0)
         pack = _MncPack(mncs or {})
         q = _lib.Query()
@@ -508,6 +517,7 @@ class Server:
         q.mnc = pack.arr if pack.n else None
         q.n_mnc = pack.n
         q.timeout_s = float(timeout_s)
+        q.mnc_cap = int(mnc_cap)
         t = C.c_uint64()
         check(lib().query_submit(self.h, C.byref(q), C.byref(t)))
         return t.value
@@ -519,7 +529,8 @@ class Server:
             return None
         return {"verdict": VERDICTS.get(r.verdict, str(r.verdict)), "lb": r.lb, "subproblems": r.subproblems,
                 "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
-                "latency": r.t_done - r.t_submit}
+                "latency": r.t_done - r.t_submit, "reason": REASONS.get(r.reason, str(r.reason)),
+                "restarts": r.restarts}
 
     def wait(self, ticket, timeout=600.0, poll_s=0.002):
         import time

@@ -83,6 +83,8 @@ struct mnb_net {
 };
 
 namespace mnb {
+size_t problem_slot_bytes(const mnb_problem* pb);
+void problem_grow(mnb_problem* pb, int64_t capacity);
 // Active constraint branching adjusted by the split costs of Appendix B (Section 3.4) for the
 // subproblems ids: chosen layer / neuron (-1 without a candidate) and its score per subproblem.
 // Returns an MNB status code (MNB_EINVAL without multi-neuron constraints).

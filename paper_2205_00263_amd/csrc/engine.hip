@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <numeric>
 #include <set>
@@ -252,10 +253,110 @@ static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>&
         }
 }
 
-extern "C" int mnb_net_create(const mnb_layer* L, int n, mnb_net** out) {
+// Batch normalisation and average pooling are affine (Section 2.1 lists them among the layers the
+// method covers): a batch normalisation y = gamma (x - mean) / sqrt(var + eps) + beta that follows a
+// fully connected or convolutional node (its only consumer) is folded into that node's weights and
+// bias, per output channel; an average pooling k x k / s / p becomes a convolution whose filter is
+// 1/k^2 between equal channels and 0 elsewhere.  Later nodes are renumbered accordingly.
+struct TranslatedNet {
+    std::vector<mnb_layer> layers;
+    std::vector<std::vector<float>> buffers;   // folded or generated weights and biases
+};
+
+static TranslatedNet translate_layers(const mnb_layer* L, int n) {
+    TranslatedNet t;
+    std::vector<int> map(n, -1), consumers(n, 0);
+    std::vector<std::array<int, 3>> shp(n, std::array<int, 3>{0, 0, 0});   // output (C, H, W) of each node
+    for (int i = 1; i < n; ++i) {
+        MNB_CHECK(L[i].src >= 0 && L[i].src < i, MNB_EINVAL, "node " + std::to_string(i) + ": bad src");
+        consumers[L[i].src]++;
+        if (L[i].kind == MNB_ADD && L[i].src2 >= 0 && L[i].src2 < i) consumers[L[i].src2]++;
+    }
+    t.buffers.reserve(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        mnb_layer l = L[i];
+        if (i == 0) {
+            shp[0] = {l.out_chw[0], l.out_chw[1], l.out_chw[2]};
+            map[0] = 0;
+            t.layers.push_back(l);
+            continue;
+        }
+        const auto& in = shp[l.src];
+        switch (l.kind) {
+            case MNB_BN: {
+                mnb_layer& a = t.layers[map[l.src]];
+                MNB_CHECK((a.kind == MNB_FC || a.kind == MNB_CONV) && consumers[l.src] == 1, MNB_EINVAL,
+                          "batch normalisation must follow a fully connected or convolutional node, its only consumer");
+                MNB_CHECK(l.W && l.eps >= 0.f && a.W && a.b, MNB_EINVAL,
+                          "batch normalisation: need W = [gamma, beta, mean, var] per channel");
+                const int C = in[0];
+                const auto& ain = shp[L[l.src].src];
+                const long per_c = a.kind == MNB_FC ? (long)ain[0] * ain[1] * ain[2] : (long)ain[0] * a.k * a.k;
+                MNB_CHECK(C > 0 && per_c > 0, MNB_EINVAL, "batch normalisation: bad shape");
+                // the folded node's weights and bias (copies: the caller's arrays are only read)
+                std::vector<float> Wf(a.W, a.W + (size_t)C * per_c), bf(C);
+                for (int c = 0; c < C; ++c) {
+                    const double g = l.W[c], be = l.W[C + c], mu = l.W[2 * C + c], var = l.W[3 * C + c];
+                    MNB_CHECK(var + (double)l.eps > 0.0, MNB_EINVAL, "batch normalisation: var + eps must be positive");
+                    const double scale = g / std::sqrt(var + (double)l.eps);
+                    for (long q = 0; q < per_c; ++q) Wf[c * per_c + q] = (float)((double)Wf[c * per_c + q] * scale);
+                    bf[c] = (float)((double)a.b[c] * scale + (be - mu * scale));
+                }
+                t.buffers.push_back(std::move(Wf));
+                a.W = t.buffers.back().data();
+                t.buffers.push_back(std::move(bf));
+                a.b = t.buffers.back().data();
+                map[i] = map[l.src];
+                shp[i] = in;
+                continue;
+            }
+            case MNB_AVGPOOL: {
+                const int C = in[0];
+                MNB_CHECK(l.k > 0 && l.stride > 0 && l.pad >= 0 && C > 0, MNB_EINVAL, "average pooling: bad shape");
+                std::vector<float> Wp((size_t)C * C * l.k * l.k, 0.f), bp(C, 0.f);
+                const float v = 1.f / (float)(l.k * l.k);
+                for (int c = 0; c < C; ++c)
+                    for (int q = 0; q < l.k * l.k; ++q) Wp[((size_t)c * C + c) * l.k * l.k + q] = v;
+                t.buffers.push_back(std::move(Wp));
+                l.W = t.buffers.back().data();
+                t.buffers.push_back(std::move(bp));
+                l.b = t.buffers.back().data();
+                l.kind = MNB_CONV;
+                l.in_chw[0] = C;
+                l.out_chw[0] = C;
+                l.out_chw[1] = l.out_chw[2] = 0;   // derived from the input shape
+                shp[i] = {C, (in[1] + 2 * l.pad - l.k) / l.stride + 1, (in[2] + 2 * l.pad - l.k) / l.stride + 1};
+                break;
+            }
+            case MNB_FC:
+                shp[i] = {l.out_chw[0], 1, 1};
+                break;
+            case MNB_CONV:
+                shp[i] = {l.out_chw[0], l.k > 0 && l.stride > 0 ? (in[1] + 2 * l.pad - l.k) / l.stride + 1 : 0,
+                          l.k > 0 && l.stride > 0 ? (in[2] + 2 * l.pad - l.k) / l.stride + 1 : 0};
+                break;
+            default:
+                shp[i] = in;
+                break;
+        }
+        l.src = map[l.src];
+        if (l.kind == MNB_ADD) {
+            MNB_CHECK(l.src2 >= 0 && l.src2 < i, MNB_EINVAL, "add: bad src2");
+            l.src2 = map[l.src2];
+        }
+        map[i] = (int)t.layers.size();
+        t.layers.push_back(l);
+    }
+    return t;
+}
+
+extern "C" int mnb_net_create(const mnb_layer* L_in, int n_in, mnb_net** out) {
     API_BEGIN
-    MNB_CHECK(L && out && n >= 2, MNB_EINVAL, "need at least an input and one layer");
-    MNB_CHECK(L[0].kind == MNB_INPUT, MNB_EINVAL, "node 0 must be MNB_INPUT");
+    MNB_CHECK(L_in && out && n_in >= 2, MNB_EINVAL, "need at least an input and one layer");
+    MNB_CHECK(L_in[0].kind == MNB_INPUT, MNB_EINVAL, "node 0 must be MNB_INPUT");
+    const TranslatedNet tn = translate_layers(L_in, n_in);
+    const mnb_layer* L = tn.layers.data();
+    const int n = (int)tn.layers.size();
     auto net = new mnb_net();
     try {
         net->nodes.resize(n);
@@ -529,6 +630,57 @@ extern "C" void mnb_problem_destroy(mnb_problem* pb) {
     } catch (...) {
     }
     delete pb;
+}
+
+// Per-slot device bytes of a problem (bounds, split signs, parameter sets, query index, reported lb).
+size_t mnb::problem_slot_bytes(const mnb_problem* pb) {
+    return (size_t)pb->ld_state * 9 + (size_t)pb->n_sets * (pb->ld_param * 8 + pb->ld_gamma * 4) + 4 + (size_t)pb->S * 4;
+}
+
+// Grow the slot pool to `capacity` slots: every per-slot array is reallocated and copied (on the
+// stream, then synchronised); ids stay valid.  Callers hold the problem's lock or own it alone.
+void mnb::problem_grow(mnb_problem* pb, int64_t capacity) {
+    if (capacity <= pb->cap) return;
+    const long oc = pb->cap, nc = capacity;
+    hipStream_t st = stream();
+    auto regrow = [&](void*& p, size_t per_slot) {
+        void* np_ = dalloc(std::max<size_t>(nc * per_slot, 16));
+        MNB_HIP(hipMemcpyAsync(np_, p, oc * per_slot, hipMemcpyDeviceToDevice, st));
+        sync();
+        auto it = std::find(pb->owned.begin(), pb->owned.end(), p);
+        if (it != pb->owned.end()) *it = np_;
+        dfree(p);
+        p = np_;
+    };
+    auto grow_f = [&](float*& p, size_t per) {
+        void* v = p;
+        regrow(v, per * 4);
+        p = (float*)v;
+    };
+    grow_f(pb->l, pb->ld_state);
+    grow_f(pb->u, pb->ld_state);
+    {
+        void* v = pb->S_;
+        regrow(v, pb->ld_state);
+        pb->S_ = (int8_t*)v;
+    }
+    grow_f(pb->alpha, (size_t)pb->n_sets * pb->ld_param);
+    grow_f(pb->beta, (size_t)pb->n_sets * pb->ld_param);
+    grow_f(pb->gamma, (size_t)pb->n_sets * pb->ld_gamma);
+    {
+        void* v = pb->qid;
+        regrow(v, 4);
+        pb->qid = (int32_t*)v;
+    }
+    grow_f(pb->lb, pb->S);
+    pb->recompute_from.resize(nc, pb->R);
+    pb->slot_query.resize(nc, -1);
+    pb->used.resize(nc, 0);
+    // new slots handed out after the existing free ones, lowest index first
+    std::vector<int64_t> fresh;
+    for (int64_t s = nc - 1; s >= oc; --s) fresh.push_back(s);
+    pb->free_list.insert(pb->free_list.begin(), fresh.begin(), fresh.end());
+    pb->cap = nc;
 }
 
 static int64_t alloc_slot(mnb_problem* pb) {
