@@ -36,7 +36,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .net import affine_adjoint, bias_vector
+from .net import AFFINE_KINDS, affine_adjoint, bias_vector
 
 
 class ReluState:
@@ -144,7 +144,7 @@ def backsub(net, start, c0, states, params, mncs=None, lo=None, hi=None, margin=
         a = coef.pop(i)
         n = net.nodes[i]
         kind = n["kind"]
-        if kind in ("fc", "conv"):
+        if kind in AFFINE_KINDS:
             c = c + a @ bias_vector(net, i)            # Eq. 2 constant
             _accumulate(coef, n["src"], affine_adjoint(net, i, a))
         elif kind == "relu":

@@ -13,7 +13,7 @@ import itertools
 import numpy as np
 import scipy.optimize
 
-from .net import affine_apply, bias_vector
+from .net import AFFINE_KINDS, affine_apply, bias_vector
 
 
 def _affine_of_pattern(net, pattern):
@@ -23,7 +23,7 @@ def _affine_of_pattern(net, pattern):
     for i in range(1, len(net.nodes)):
         n = net.nodes[i]
         k = n["kind"]
-        if k in ("fc", "conv"):
+        if k in AFFINE_KINDS:
             A, c = maps[n["src"]]
             maps.append((affine_apply(net, i, A.T).T, affine_apply(net, i, c[None, :])[0] + bias_vector(net, i)))
         elif k == "relu":

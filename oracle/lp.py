@@ -23,7 +23,7 @@ import scipy.optimize
 import scipy.sparse as sp
 
 from .backsub import relu_cases
-from .net import affine_apply, bias_vector
+from .net import AFFINE_KINDS, affine_apply, bias_vector
 
 
 def _affine_matrix(net, i):
@@ -59,7 +59,7 @@ def lp_bound(net, states, mncs, lo, hi, start, c0=0.0, upto=None):
         n = net.nodes[i]
         k = n["kind"]
         o, d = int(offs[i]), net.sizes[i]
-        if k in ("fc", "conv"):
+        if k in AFFINE_KINDS:
             A = _affine_matrix(net, i)
             os_ = int(offs[n["src"]])
             blk = sp.lil_matrix((d, nvar))

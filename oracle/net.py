@@ -1,8 +1,14 @@
 """Network arithmetic in float64 (oracle; test infrastructure only).
 
 The network of Section 2.1: affine layers zhat = W z + b and ReLUs
-z = max(0, zhat), generalised to a DAG of fc / conv / relu / add nodes
-(Section 2.1 notes the method covers convolutional and residual layers).
+z = max(0, zhat), generalised to a DAG of fc / conv / bn / avgpool / relu /
+add nodes (Section 2.1 notes the method covers convolutional, residual,
+batch-normalisation and average-pooling layers; the latter two are affine).
+
+* bn: batch normalisation with fixed statistics, per channel c
+  y = gamma_c (x - mean_c) / sqrt(var_c + eps) + beta_c;
+* avgpool: the mean of each k x k window (stride s, zero padding p counted
+  in the window, so the divisor is always k^2).
 
 Everything here works on batches of row vectors [R, size]; conv tensors are
 flattened in (C, H, W) order.
@@ -10,6 +16,9 @@ flattened in (C, H, W) order.
 from __future__ import annotations
 
 import numpy as np
+
+
+AFFINE_KINDS = ("fc", "conv", "bn", "avgpool")
 
 
 class Net:
@@ -22,6 +31,9 @@ class Net:
             if "W" in m:
                 m["W"] = np.asarray(m["W"], dtype=np.float64)
                 m["b"] = np.asarray(m["b"], dtype=np.float64)
+            for key in ("gamma", "beta", "mean", "var"):
+                if key in m:
+                    m[key] = np.asarray(m[key], dtype=np.float64)
             self.nodes.append(m)
         self.shapes = _shapes(self.nodes)
         self.sizes = [int(np.prod(s)) for s in self.shapes]
@@ -48,7 +60,11 @@ def _shapes(nodes):
             co, _, kk, _ = n["W"].shape
             s, p = n["stride"], n["pad"]
             shapes.append((co, (hi + 2 * p - kk) // s + 1, (wi + 2 * p - kk) // s + 1))
-        elif k in ("relu",):
+        elif k == "avgpool":
+            c, hi, wi = shapes[n["src"]]
+            kk, s, p = n["k"], n["stride"], n["pad"]
+            shapes.append((c, (hi + 2 * p - kk) // s + 1, (wi + 2 * p - kk) // s + 1))
+        elif k in ("relu", "bn"):
             shapes.append(shapes[n["src"]])
         elif k == "add":
             shapes.append(shapes[n["src"]])
@@ -89,6 +105,41 @@ def conv_adjoint(W, a, in_shape, out_shape, stride, pad):
     return gp[:, :, p:p + hi, p:p + wi].reshape(R, -1)
 
 
+# --------------------------------------------------------------------------- batch norm / pooling
+def bn_scale(n):
+    """Per-channel slope gamma / sqrt(var + eps) of a batch-normalisation node."""
+    return n["gamma"] / np.sqrt(n["var"] + n["eps"])
+
+
+def avgpool_apply(z, in_shape, out_shape, k, stride, pad):
+    """out[c,y,x] = (1/k^2) sum_{ky,kx} z[c, s*y+ky-p, s*x+kx-p] (zero padding counted)."""
+    R = z.shape[0]
+    c, hi, wi = in_shape
+    _, ho, wo = out_shape
+    s, p = stride, pad
+    zp = np.zeros((R, c, hi + 2 * p, wi + 2 * p))
+    zp[:, :, p:p + hi, p:p + wi] = z.reshape(R, c, hi, wi)
+    out = np.zeros((R, c, ho, wo))
+    for ky in range(k):
+        for kx in range(k):
+            out += zp[:, :, ky:ky + s * (ho - 1) + 1:s, kx:kx + s * (wo - 1) + 1:s]
+    return (out / (k * k)).reshape(R, -1)
+
+
+def avgpool_adjoint(a, in_shape, out_shape, k, stride, pad):
+    """Adjoint of avgpool_apply: each output coefficient spread evenly over its window."""
+    R = a.shape[0]
+    c, hi, wi = in_shape
+    _, ho, wo = out_shape
+    s, p = stride, pad
+    a4 = a.reshape(R, c, ho, wo) / (k * k)
+    gp = np.zeros((R, c, hi + 2 * p, wi + 2 * p))
+    for ky in range(k):
+        for kx in range(k):
+            gp[:, :, ky:ky + s * (ho - 1) + 1:s, kx:kx + s * (wo - 1) + 1:s] += a4
+    return gp[:, :, p:p + hi, p:p + wi].reshape(R, -1)
+
+
 # --------------------------------------------------------------------------- affine nodes
 def affine_apply(net, i, z):
     """W z (no bias) for affine node i on a batch z [R, d_in]."""
@@ -97,6 +148,11 @@ def affine_apply(net, i, z):
         return z @ n["W"].T
     if n["kind"] == "conv":
         return conv_apply(n["W"], z, net.shapes[n["src"]], net.shapes[i], n["stride"], n["pad"])
+    if n["kind"] == "bn":
+        c, h, w = net.shapes[i]
+        return z * np.repeat(bn_scale(n), h * w)[None, :]
+    if n["kind"] == "avgpool":
+        return avgpool_apply(z, net.shapes[n["src"]], net.shapes[i], n["k"], n["stride"], n["pad"])
     raise ValueError(n["kind"])
 
 
@@ -107,6 +163,11 @@ def affine_adjoint(net, i, a):
         return a @ n["W"]
     if n["kind"] == "conv":
         return conv_adjoint(n["W"], a, net.shapes[n["src"]], net.shapes[i], n["stride"], n["pad"])
+    if n["kind"] == "bn":
+        c, h, w = net.shapes[i]
+        return a * np.repeat(bn_scale(n), h * w)[None, :]
+    if n["kind"] == "avgpool":
+        return avgpool_adjoint(a, net.shapes[n["src"]], net.shapes[i], n["k"], n["stride"], n["pad"])
     raise ValueError(n["kind"])
 
 
@@ -116,6 +177,10 @@ def bias_vector(net, i):
     if n["kind"] == "fc":
         return n["b"]
     c, h, w = net.shapes[i]
+    if n["kind"] == "bn":
+        return np.repeat(n["beta"] - n["mean"] * bn_scale(n), h * w)
+    if n["kind"] == "avgpool":
+        return np.zeros(c * h * w)
     return np.repeat(n["b"], h * w)
 
 
@@ -125,7 +190,7 @@ def forward_all(net, x):
     vals = [np.asarray(x, dtype=np.float64).reshape(len(x), -1)]
     for i, n in enumerate(net.nodes[1:], start=1):
         k = n["kind"]
-        if k in ("fc", "conv"):
+        if k in AFFINE_KINDS:
             vals.append(affine_apply(net, i, vals[n["src"]]) + bias_vector(net, i))
         elif k == "relu":
             vals.append(np.maximum(vals[n["src"]], 0.0))
@@ -150,7 +215,7 @@ def interval_forward(net, lo, hi, relu_bounds, upto):
     for i in range(1, upto + 1):
         n = net.nodes[i]
         k = n["kind"]
-        if k in ("fc", "conv"):
+        if k in AFFINE_KINDS:
             lo_s, hi_s = L[n["src"]][None, :], U[n["src"]][None, :]
             mid = (lo_s + hi_s) / 2.0
             rad = (hi_s - lo_s) / 2.0
@@ -173,7 +238,13 @@ def interval_forward(net, lo, hi, relu_bounds, upto):
 
 
 def _abs_affine(net, i, z):
+    """|W| z for affine node i (the radius of the interval image)."""
     n = net.nodes[i]
     if n["kind"] == "fc":
         return z @ np.abs(n["W"]).T
+    if n["kind"] == "bn":
+        c, h, w = net.shapes[i]
+        return z * np.repeat(np.abs(bn_scale(n)), h * w)[None, :]
+    if n["kind"] == "avgpool":
+        return affine_apply(net, i, z)      # nonnegative weights
     return conv_apply(np.abs(n["W"]), z, net.shapes[n["src"]], net.shapes[i], n["stride"], n["pad"])

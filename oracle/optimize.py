@@ -25,7 +25,7 @@ import copy
 
 import numpy as np
 
-from .net import affine_apply, bias_vector, forward, interval_forward
+from .net import AFFINE_KINDS, affine_apply, bias_vector, forward, interval_forward
 from .backsub import (ReluState, backsub, heuristic_alpha, neuron_start,
                       spec_start)
 
@@ -49,7 +49,7 @@ def bound_grads(net, out, mncs=None, per_row=False):
     for i in range(1, top + 1):
         n = net.nodes[i]
         k = n["kind"]
-        if k in ("fc", "conv"):
+        if k in AFFINE_KINDS:
             if n["src"] in g:
                 g[i] = affine_apply(net, i, g[n["src"]]) + bias_vector(net, i)
         elif k == "add":

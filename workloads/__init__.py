@@ -21,6 +21,8 @@ node 0 is the input):
     {"kind": "input", "shape": (C, H, W)}
     {"kind": "fc",   "src": i, "W": [dout, din], "b": [dout]}
     {"kind": "conv", "src": i, "W": [Co, Ci, k, k], "b": [Co], "stride": s, "pad": p}
+    {"kind": "bn",   "src": i, "gamma": [C], "beta": [C], "mean": [C], "var": [C], "eps": e}
+    {"kind": "avgpool", "src": i, "k": k, "stride": s, "pad": p}
     {"kind": "relu", "src": i}
     {"kind": "add",  "src": i, "src2": j}
 
@@ -60,7 +62,11 @@ def node_shapes(nodes):
             ho = (hi + 2 * p - kh) // s + 1
             wo = (wi + 2 * p - kw) // s + 1
             shapes.append((int(co), int(ho), int(wo)))
-        elif k == "relu":
+        elif k == "avgpool":
+            c, hi, wi = shapes[n["src"]]
+            kk, s, p = n["k"], n["stride"], n["pad"]
+            shapes.append((int(c), (hi + 2 * p - kk) // s + 1, (wi + 2 * p - kk) // s + 1))
+        elif k in ("relu", "bn"):
             shapes.append(shapes[n["src"]])
         elif k == "add":
             assert shapes[n["src"]] == shapes[n["src2"]], (i, shapes[n["src"]], shapes[n["src2"]])
@@ -102,6 +108,23 @@ class _Builder:
         b = self.rng.uniform(-bnd, bnd, size=cout).astype(np.float32)
         self.nodes.append({"kind": "conv", "src": src, "W": W, "b": b,
                            "stride": int(stride), "pad": int(pad)})
+        return self.last
+
+    def bn(self, src=None):
+        """Batch normalisation with fixed, seeded statistics (the evaluation-mode layer)."""
+        src = self.last if src is None else src
+        c = self.shape(src)[0]
+        r = self.rng
+        self.nodes.append({"kind": "bn", "src": src,
+                           "gamma": r.uniform(0.5, 1.5, c).astype(np.float32),
+                           "beta": r.uniform(-0.1, 0.1, c).astype(np.float32),
+                           "mean": r.normal(0.0, 0.1, c).astype(np.float32),
+                           "var": r.uniform(0.5, 1.5, c).astype(np.float32), "eps": 1e-5})
+        return self.last
+
+    def avgpool(self, k, stride, pad=0, src=None):
+        src = self.last if src is None else src
+        self.nodes.append({"kind": "avgpool", "src": src, "k": int(k), "stride": int(stride), "pad": int(pad)})
         return self.last
 
     def relu(self, src=None):
@@ -149,12 +172,18 @@ def convbig(seed, in_shape=(3, 32, 32), ch=(32, 32, 64, 64), hidden=(512, 512), 
     return B.nodes
 
 
-def _res_block(B, cout):
+def _res_block(B, cout, bn=False):
     x = B.last
-    a = B.conv(cout, 3, 2, 1, src=x)
+    B.conv(cout, 3, 2, 1, src=x)
+    if bn:
+        B.bn()
     B.relu()
     b = B.conv(cout, 3, 1, 1)
+    if bn:
+        b = B.bn()
     s = B.conv(cout, 1, 2, 0, src=x)
+    if bn:
+        s = B.bn()
     B.add(b, s)
     return B.relu()
 
@@ -174,9 +203,23 @@ def resnet6(seed, in_shape=(3, 32, 32), ch=(16, 32, 64), hidden=100, n_out=10, s
     return B.nodes
 
 
-def resnet8(seed, in_shape=(3, 32, 32)):
-    """ResNet8 shape (Table 5): stem conv 16 3x3/2/1 and three residual blocks."""
-    return resnet6(seed, in_shape=in_shape, ch=(16, 32, 64, 128))
+def resnet8(seed, in_shape=(3, 32, 32), ch=(16, 32, 64, 128), hidden=100, n_out=10, bn=False, pool=None):
+    """ResNet8 shape (Table 5): stem conv 16 3x3/2/1, three residual blocks, FC hidden, FC n_out.
+
+    bn=True puts a batch-normalisation layer after every convolution (before its ReLU or residual
+    addition); pool=(k, s) an average pooling k x k / s after the last block."""
+    B = _Builder(in_shape, np.random.default_rng(seed))
+    B.conv(ch[0], 3, 2, 1)
+    if bn:
+        B.bn()
+    B.relu()
+    for c in ch[1:]:
+        _res_block(B, c, bn=bn)
+    if pool:
+        B.avgpool(pool[0], pool[1])
+    B.fc(hidden); B.relu()
+    B.fc(n_out)
+    return B.nodes
 
 
 def tiny_fc(seed, widths=(3, 4, 4, 2)):
