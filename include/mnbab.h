@@ -267,6 +267,23 @@ int mnb_bound_grad_device(mnb_problem* pb, int64_t id, int set, int* rows, float
  * n > 65535.  Parameters and bounds are not modified. */
 int mnb_branch_scores(mnb_problem* pb, const int64_t* ids, int n, const float* layer_weight, float* scores,
                       int32_t* branch_layer, int32_t* branch_neuron);
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): mnb_branch_scores
+ * with every device buffer (ids, instance descriptors, layer weights, the
+ * projections gamma^T P and gamma^T Phat, the scores and the argmax) carved
+ * from a fixed device array of MNB_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends; no hipMalloc, hipFree
+ * or allocating library routine is called.  Same arguments, results and
+ * errors as mnb_branch_scores, bit for bit (the same kernels), except that
+ * layer_weight is [n_relu] only, and MNB_EINVAL when the call needs more than
+ * the array: 3 n (sum of ReLU widths) floats plus a few bytes per subproblem
+ * (e.g. n <= 89 for the ConvBig shape).  Every scratch byte a call reads it
+ * first writes.  Calls of one process are serialised on a host mutex and are
+ * complete when they return; calls that overlapped on one GPU would race on
+ * its array. */
+#define MNB_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mnb_branch_scores_noalloc(mnb_problem* pb, const int64_t* ids, int n, const float* layer_weight,
+                              float* scores, int32_t* branch_layer, int32_t* branch_neuron);
 /* The alpha-contribution branching score that bound_optimize's branch_layer /
  * branch_neuron choose by (Section 3.2 splits an unstable ReLU; the score reads
  * the bound's sensitivity to each unstable, unsplit neuron times the height of

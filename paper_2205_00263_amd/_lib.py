@@ -81,6 +81,7 @@ _SIGS = {
     "mnb_bound_grad_device": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_int), C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p]),
     "mnb_branch_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, fp, ip32, ip32]),
+    "mnb_branch_scores_noalloc": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, fp, ip32, ip32]),
     "mnb_contribution_scores": (C.c_int, [C.c_void_p, ip64, C.c_int, fp, ip32, ip32]),
     "mnb_split_costs": (C.c_int, [C.POINTER(Layer), C.c_int, ip32, C.POINTER(C.c_double)]),
     "mnb_octahedral_bounds": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, ip32, C.c_int, fp]),
