@@ -368,7 +368,35 @@ def test_conv_matches_library_and_adjoint_identity():
         np.testing.assert_allclose(lhs, rhs, atol=1e-10)
 
 
-@pytest.mark.parametrize("maker", ["tiny_conv", "tiny_resnet"])
+def test_bn_and_avgpool_match_library_and_adjoint_identity():
+    """Batch normalisation with fixed statistics against torch's batch_norm in evaluation mode, average
+    pooling against avg_pool2d (zero padding counted), each with <a, A z> = <A^T a, z>."""
+    torch = pytest.importorskip("torch")
+    F = torch.nn.functional
+    rng = np.random.default_rng(4)
+    c, h = 3, 6
+    bn = {"kind": "bn", "src": 0, "gamma": rng.uniform(0.5, 1.5, c), "beta": rng.normal(size=c),
+          "mean": rng.normal(size=c), "var": rng.uniform(0.5, 2.0, c), "eps": 1e-5}
+    for node in (bn, {"kind": "avgpool", "src": 0, "k": 2, "stride": 2, "pad": 0},
+                 {"kind": "avgpool", "src": 0, "k": 3, "stride": 2, "pad": 1}):
+        net = onet.Net([{"kind": "input", "shape": (c, h, h)}, node])
+        z = rng.normal(size=(4, c * h * h))
+        mine = onet.affine_apply(net, 1, z) + onet.bias_vector(net, 1)
+        zt = torch.from_numpy(z.reshape(4, c, h, h))
+        if node["kind"] == "bn":
+            ref = F.batch_norm(zt, torch.from_numpy(bn["mean"]), torch.from_numpy(bn["var"]),
+                               torch.from_numpy(bn["gamma"]), torch.from_numpy(bn["beta"]), training=False,
+                               eps=bn["eps"])
+        else:
+            ref = F.avg_pool2d(zt, node["k"], node["stride"], node["pad"], count_include_pad=True)
+        np.testing.assert_allclose(mine, ref.reshape(4, -1).numpy(), atol=1e-12)
+        a = rng.normal(size=(4, net.sizes[1]))
+        lhs = np.einsum("rj,rj->r", a, onet.affine_apply(net, 1, z))
+        rhs = np.einsum("rj,rj->r", onet.affine_adjoint(net, 1, a), z)
+        np.testing.assert_allclose(lhs, rhs, atol=1e-10)
+
+
+@pytest.mark.parametrize("maker", ["tiny_conv", "tiny_resnet", "tiny_resnet_bn"])
 def test_conv_and_residual_nets_lp_duality(maker):
     nodes = getattr(W, maker)(3)
     x0, lo, hi = W.make_input(nodes[0]["shape"], 0.15, 9)

@@ -35,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "node_shapes", "fc_net", "convsmall", "convbig", "resnet6", "resnet8",
-    "tiny_fc", "tiny_conv", "tiny_resnet", "make_net", "make_input",
+    "tiny_fc", "tiny_conv", "tiny_resnet", "tiny_resnet_bn", "make_net", "make_input",
     "make_spec", "forward_logits", "make_split_sets", "Workload",
     "make_workload", "CONFIG_SEEDS",
 ]
@@ -236,12 +236,23 @@ def tiny_conv(seed, in_shape=(1, 6, 6), c1=2, c2=3, hidden=4, n_out=3):
     return B.nodes
 
 
-def tiny_resnet(seed, in_shape=(1, 4, 4), ch=(2, 2), n_out=2):
+def tiny_resnet(seed, in_shape=(1, 4, 4), ch=(2, 2), n_out=2, bn=False, pool=None):
+    """Stem conv 3x3/1/1, one residual block, FC; bn=True adds batch normalisation after every
+    convolution, pool=(k, s) an average pooling after the block."""
     B = _Builder(in_shape, np.random.default_rng(seed))
-    B.conv(ch[0], 3, 1, 1); B.relu()
-    _res_block(B, ch[1])
+    B.conv(ch[0], 3, 1, 1)
+    if bn:
+        B.bn()
+    B.relu()
+    _res_block(B, ch[1], bn=bn)
+    if pool:
+        B.avgpool(pool[0], pool[1])
     B.fc(n_out)
     return B.nodes
+
+
+def tiny_resnet_bn(seed):
+    return tiny_resnet(seed, in_shape=(1, 4, 4), ch=(2, 3), bn=True, pool=(2, 2))
 
 
 def make_net(cfg, seed=None, scale="full"):
@@ -298,6 +309,17 @@ def forward_logits(nodes, x):
             W = torch.from_numpy(n["W"].astype(np.float64))
             b = torch.from_numpy(n["b"].astype(np.float64))
             out = torch.nn.functional.conv2d(z, W, b, stride=n["stride"], padding=n["pad"])
+            vals.append(out.reshape(out.shape[0], -1).numpy())
+        elif k in ("bn", "avgpool"):
+            import torch  # library layers, float64 on the CPU
+            ci, hi, wi = shapes[n["src"]]
+            z = torch.from_numpy(vals[n["src"]].reshape(-1, ci, hi, wi))
+            if k == "bn":
+                t = lambda key: torch.from_numpy(np.asarray(n[key], np.float64))
+                out = torch.nn.functional.batch_norm(z, t("mean"), t("var"), t("gamma"), t("beta"), training=False,
+                                                     eps=float(n["eps"]))
+            else:
+                out = torch.nn.functional.avg_pool2d(z, n["k"], n["stride"], n["pad"], count_include_pad=True)
             vals.append(out.reshape(out.shape[0], -1).numpy())
         elif k == "relu":
             vals.append(np.maximum(vals[n["src"]], 0.0))
