@@ -611,7 +611,7 @@ def host_cores():
     return int(n), model
 
 
-def cpu_baseline_convbig(wl, mean_rows, threads, rows_per_layer=16):
+def cpu_baseline_convbig(wl, mean_rows, threads, rows_per_layer=128):
     """The FP64 oracle on a bounded sample of the ConvBig workload: one Adam iteration's work (the
     back-substitution of Eq. 2 / Eq. 5 / Eq. 6 and the analytic gradient) of a few rows of every
     recomputed layer and of the spec rows, timed per row and scaled by the batch's mean rows per
@@ -713,7 +713,7 @@ def convbig_batch(args):
     P.use_torch_plumbing(True)
     wl = W.make_workload(3)
     net = P.Net(wl.nodes)
-    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=2 * B + 64, max_mnc=MNC_CAP)
+    pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=3 * B + 64, max_mnc=MNC_CAP)
     t = time.perf_counter()
     rid, root_lb, root_ub = pb.bound_init(wl.lo, wl.hi, wl.C, wl.c0)
     t_init = time.perf_counter() - t

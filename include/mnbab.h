@@ -374,12 +374,15 @@ int mnb_timer_end(int64_t* launches, double* ms, double* flops, double* bytes);
  *   MNB_VAR_NO_ROW_CONV      convolutions through the LDS-staged gather GEMMs
  *   MNB_VAR_NO_WINDOW        window rows of ReLU layer 1 through the fused kernel
  *   MNB_VAR_NO_FUSED_BOTTOM  first layer by the generic back-substitution and concretisation
+ *   MNB_VAR_NO_PATCH         intermediate-bound rows of convolution outputs as whole
+ *                            layers instead of receptive-field windows
  * The initial mask comes from the environment variables MNB_BOTTOM_VALU,
- * MNB_NO_TAP_CONVT, MNB_NO_PAIR_CONV, MNB_NO_ROW_CONV, MNB_NO_WIN_BOTTOM and
- * MNB_NO_FUSED_BOTTOM (set: bit on).  mnb_set_kernel_variants returns the
- * previous mask; neither call fails. */
+ * MNB_NO_TAP_CONVT, MNB_NO_PAIR_CONV, MNB_NO_ROW_CONV, MNB_NO_WIN_BOTTOM,
+ * MNB_NO_FUSED_BOTTOM and MNB_NO_PATCH (set: bit on).  The mask is read when a
+ * pass is planned (bound_init, bound_optimize, bound_optimize_begin).
+ * mnb_set_kernel_variants returns the previous mask; neither call fails. */
 enum { MNB_VAR_VALU_BOTTOM = 1, MNB_VAR_NO_TAP_CONVT = 2, MNB_VAR_NO_PAIR_CONV = 4, MNB_VAR_NO_ROW_CONV = 8,
-       MNB_VAR_NO_WINDOW = 16, MNB_VAR_NO_FUSED_BOTTOM = 32 };
+       MNB_VAR_NO_WINDOW = 16, MNB_VAR_NO_FUSED_BOTTOM = 32, MNB_VAR_NO_PATCH = 64 };
 int mnb_set_kernel_variants(int mask);
 int mnb_get_kernel_variants(void);
 

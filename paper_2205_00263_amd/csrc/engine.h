@@ -69,6 +69,20 @@ struct NetNode {
     double macs_per_row = 0;   // nonzero multiply-adds of the layer for one row
 };
 
+// Receptive-field rows of the intermediate bounds of one ReLU layer that a convolution feeds,
+// when every node below that convolution is a convolution or a ReLU: for each node of the pass
+// the window geometry of its rows, for each convolution the convolution between windows
+// (padding 0: a window holds every tap its outputs read) and its multiply-adds per row.
+struct PatchPlan {
+    bool ok = false;
+    int top = -1;                  // the objective convolution's input node
+    std::vector<PatchGeom> g;      // per node index
+    std::vector<ConvGeom> conv;    // per node index (convolution nodes of the pass)
+    std::vector<double> macs;      // per node index
+    int max_width = 0;
+    int width(int n) const { return g[n].C * g[n].P * g[n].P; }
+};
+
 }  // namespace mnb
 
 struct mnb_net {
@@ -79,6 +93,7 @@ struct mnb_net {
     int total_d = 0, d0 = 0, n_out = 0, last = 0, max_width = 0;
     bool bottom_ok = false;   // first layer is a small conv of the input feeding ReLU layer 0
     bool win_ok = false;      // ReLU layer 1 is fed by a conv of ReLU layer 0 the window kernel takes
+    std::vector<mnb::PatchPlan> patch;   // per ReLU layer
     ~mnb_net();
 };
 

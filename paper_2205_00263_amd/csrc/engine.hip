@@ -160,6 +160,7 @@ int initial_variants() {
     if (getenv("MNB_NO_ROW_CONV")) m |= MNB_VAR_NO_ROW_CONV;
     if (getenv("MNB_NO_WIN_BOTTOM")) m |= MNB_VAR_NO_WINDOW;
     if (getenv("MNB_NO_FUSED_BOTTOM")) m |= MNB_VAR_NO_FUSED_BOTTOM;
+    if (getenv("MNB_NO_PATCH")) m |= MNB_VAR_NO_PATCH;
     return m;
 }
 std::atomic<int> g_variants{initial_variants()};
@@ -196,14 +197,14 @@ mnb_net::~mnb_net() {
     for (void* p : owned) dfree(p);
 }
 
-static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>& Wh) {
-    const NetNode& in = net->nodes[nd.src];
-    ConvGeom& g = nd.geom;
-    g.Ci = in.C; g.Hi = in.H; g.Wi = in.W;
-    g.Co = nd.C; g.Ho = nd.H; g.Wo = nd.W;
-    g.k = nd.k; g.s = nd.stride; g.p = nd.pad;
-    g.W = nd.Wd; g.b = nd.bd;
-    const int k = g.k, s = g.s;
+// Device tables of a convolution Ci x Hi x Wi -> Co x Ho x Wo (k, s, p) with weights Wd / bd
+// (host copy Wh): the forward gather table and the stride phases of the transposed one.
+static void fill_conv_geom(mnb_net* net, ConvGeom& g, int Ci, int Hi, int Wi, int Co, int Ho, int Wo, int k, int s,
+                           int p, const float* Wd, const float* bd, const std::vector<float>& Wh) {
+    g.Ci = Ci; g.Hi = Hi; g.Wi = Wi;
+    g.Co = Co; g.Ho = Ho; g.Wo = Wo;
+    g.k = k; g.s = s; g.p = p;
+    g.W = Wd; g.b = bd;
     // forward gather table and weights with K ordered (ky, kx, ci), input channel innermost
     std::vector<int2> ft((size_t)g.Ci * k * k);
     std::vector<float> wf((size_t)g.Co * g.Ci * k * k);
@@ -251,6 +252,55 @@ static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>&
             }
             g.ph[g.n_phase++] = ph;
         }
+}
+
+static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>& Wh) {
+    const NetNode& in = net->nodes[nd.src];
+    fill_conv_geom(net, nd.geom, in.C, in.H, in.W, nd.C, nd.H, nd.W, nd.k, nd.stride, nd.pad, nd.Wd, nd.bd, Wh);
+}
+
+// Receptive-field plan of ReLU layer m (see PatchPlan): windows grow downwards, side
+// P_in = (P_out - 1) s + k through a convolution k / s / p, origin stride S_in = S_out s and
+// offset Q_in = Q_out s + p.  Used where the windows hold clearly fewer entries than the layers.
+static PatchPlan make_patch_plan(mnb_net* net, int m, const std::map<int, std::vector<float>>& wh) {
+    PatchPlan pp;
+    if (m < 1) return pp;
+    const int on = net->nodes[net->relus[m]].src;
+    const NetNode& o = net->nodes[on];
+    if (o.kind != MNB_CONV) return pp;
+    const size_t nn = net->nodes.size();
+    pp.g.assign(nn, PatchGeom{});
+    pp.conv.assign(nn, ConvGeom{});
+    pp.macs.assign(nn, 0.0);
+    pp.top = o.src;
+    int P = o.k, S = o.stride, Q = o.pad;
+    long win = 0, dense = 0;
+    int n = pp.top;
+    while (true) {
+        const NetNode& nd = net->nodes[n];
+        pp.g[n] = PatchGeom{nd.C, nd.H, nd.W, P, S, Q, o.H * o.W, o.W};
+        win += (long)nd.C * P * P;
+        dense += nd.size;
+        pp.max_width = std::max(pp.max_width, nd.C * P * P);
+        if (n == 0) break;
+        if (nd.kind == MNB_RELU) {
+            n = nd.src;
+        } else if (nd.kind == MNB_CONV) {
+            const NetNode& in = net->nodes[nd.src];
+            const int Pin = (P - 1) * nd.stride + nd.k;
+            fill_conv_geom(net, pp.conv[n], in.C, Pin, Pin, nd.C, P, P, nd.k, nd.stride, 0, nd.Wd, nd.bd, wh.at(n));
+            pp.macs[n] = (double)nd.C * in.C * nd.k * nd.k * P * P;
+            P = Pin;
+            S *= nd.stride;
+            Q = Q * nd.stride + nd.pad;
+            n = nd.src;
+        } else {
+            return PatchPlan{};
+        }
+    }
+    pp.ok = 2 * win <= dense;
+    if (!pp.ok) return PatchPlan{};
+    return pp;
 }
 
 // Batch normalisation and average pooling are affine (Section 2.1 lists them among the layers the
@@ -359,6 +409,7 @@ extern "C" int mnb_net_create(const mnb_layer* L_in, int n_in, mnb_net** out) {
     const int n = (int)tn.layers.size();
     auto net = new mnb_net();
     try {
+        std::map<int, std::vector<float>> conv_wh;   // host weights of the convolutions
         net->nodes.resize(n);
         for (int i = 0; i < n; ++i) {
             NetNode& nd = net->nodes[i];
@@ -398,6 +449,7 @@ extern "C" int mnb_net_create(const mnb_layer* L_in, int n_in, mnb_net** out) {
                         nd.Wd = upload(l.W, nw, &net->owned);
                         nd.bd = upload(l.b, (size_t)nd.C, &net->owned);
                         build_conv_geom(net, nd, Wh);
+                        conv_wh[i] = std::move(Wh);
                         {
                             // nonzero multiply-adds per row: taps that do not fall on padding
                             double taps = 0;
@@ -492,6 +544,7 @@ extern "C" int mnb_net_create(const mnb_layer* L_in, int n_in, mnb_net** out) {
                               win_supported(a1.C, net->nodes[0].C, a1.k, a1.stride, on.k, on.C, r0.size, net->d0);
             }
         }
+        for (int m = 0; m < (int)net->relus.size(); ++m) net->patch.push_back(make_patch_plan(net, m, conv_wh));
         sync();
     } catch (...) {
         delete net;
@@ -737,7 +790,20 @@ struct PassChunk {
     // octahedral rows (multi-neuron constraint generation): row 26 g + s is sum_t s_t e_{grp[g][t]}
     // on the input of ReLU layer obj_layer, for the 26 directions s; groups [M / 26][3] on the device
     const int32_t* oct_groups = nullptr;
+    // receptive-field rows (nullable): windows of each row's deviation from its instance's
+    // shared row
+    const PatchPlan* pp = nullptr;
+    int inst_base = 0;                // pass-wide index of the chunk's first instance
+    // the shared rows, one per instance (descriptors built on first use)
+    RowDesc* sh_rows_d = nullptr;
+    InstDesc* sh_inst_d = nullptr;
+    bool zero_rows = false;           // rows are the zero objective (a chunk of shared rows)
 };
+
+// Row width of a chunk's coefficients on node n.
+static int node_width(const mnb_net* net, const PassChunk& ch, int n) {
+    return ch.pp ? ch.pp->width(n) : net->nodes[n].size;
+}
 
 // A pool of [M, max_width] coefficient buffers with reference counts.
 struct BufPool {
@@ -787,6 +853,9 @@ struct PassCtx {
     const float* fold_W = nullptr;
     const float* fold_b = nullptr;
     const RowDesc* fold_rows = nullptr;
+    // receptive-field rows: a' deviation windows per relu node [M, window] and the shared rows'
+    // a' per relu node [n_inst, d]
+    std::map<int, float*> apw, ush;
 };
 
 static int fold_cols(int d) { return cdiv(d, 256) * 4; }
@@ -797,10 +866,10 @@ static int fold_cols(int d) { return cdiv(d, 256) * 4; }
 constexpr float kSpecMargin = 9.5367431640625e-07f;
 
 // Total partial-constant columns of a pass whose rows start at node `top`.
-static int pass_cols(const mnb_net* net, int top) {
+static int pass_cols(const mnb_net* net, int top, const PatchPlan* pp = nullptr) {
     int cols = 0;
     for (int i : net->relus)
-        if (i <= top) cols += fold_cols(net->nodes[i].size);
+        if (i <= top) cols += fold_cols(pp ? pp->width(i) : net->nodes[i].size);
     return std::max(cols, 1);
 }
 
@@ -860,12 +929,12 @@ static void walk_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, std::m
                 float* out = acc ? coef[dst] : pool.acquire();
                 {
                     TimerScope ts(nd.kind == MNB_FC ? MNB_T_FC_BACKSUB : MNB_T_CONV_BACKSUB, n,
-                                  2.0 * M * nd.macs_per_row,
-                                  4.0 * M * (nd.size + net->nodes[dst].size * (acc ? 2 : 1)));
+                                  2.0 * M * (ch.pp ? ch.pp->macs[n] : nd.macs_per_row),
+                                  4.0 * M * (node_width(net, ch, n) + node_width(net, ch, dst) * (acc ? 2 : 1)));
                     if (nd.kind == MNB_FC)
                         launch_fc_backsub(a, nd.Wd, out, M, nd.size, net->nodes[dst].size, acc, st);
                     else
-                        launch_conv_backsub(nd.geom, a, out, M, acc, st);
+                        launch_conv_backsub(ch.pp ? ch.pp->conv[n] : nd.geom, a, out, M, acc, st);
                 }
                 coef[dst] = out;
                 pool.release(a);
@@ -875,7 +944,7 @@ static void walk_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, std::m
                 const int m = nd.relu_m;
                 FoldArgs fa{};
                 fa.A = a;
-                fa.Ap = store_ap ? cx.ap.at(n) : nullptr;
+                fa.Ap = store_ap ? (ch.pp ? cx.apw.at(n) : cx.ap.at(n)) : nullptr;
                 fa.cpart = cx.cpart; fa.ldcp = cx.ldcp; fa.col_off = col;
                 fa.inst = ch.inst_d; fa.n_inst = (int)ch.inst.size();
                 fa.slots = cx.slots_d;
@@ -895,10 +964,14 @@ static void walk_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, std::m
                     cx.fold_W = nullptr;
                 }
                 {
-                    TimerScope ts(MNB_T_FOLD, n, 0.0, (double)M * nd.size * (store_ap ? 12 : 8));
-                    launch_relu_fold(fa, st, cx.gp.count(m) ? cx.gp[m] : nullptr);
+                    TimerScope ts(MNB_T_FOLD, n, 0.0, (double)M * node_width(net, ch, n) * (store_ap ? 12 : 8));
+                    if (ch.pp) {
+                        fa.ush = cx.ush.at(n);
+                        launch_relu_fold_patch(fa, ch.pp->g[n], ch.rows, ch.inst_base, st);
+                    } else
+                        launch_relu_fold(fa, st, cx.gp.count(m) ? cx.gp[m] : nullptr);
                 }
-                col += fold_cols(nd.size);
+                col += fold_cols(node_width(net, ch, n));
                 MNB_CHECK(!coef.count(nd.src), MNB_EDEVICE, "relu input reached twice");
                 coef[nd.src] = a;
                 break;
@@ -927,6 +1000,21 @@ static float* run_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, bool 
         top = chunk_top(net, ch);
         float* A = pool.acquire();
         launch_init_oct(ch.oct_groups, M / 26, net->nodes[top].size, net->relu_bias[ch.obj_layer], A, cx.c, st);
+        coef[top] = A;
+    } else if (ch.zero_rows) {
+        // the zero objective (shared rows of receptive-field passes): coefficient and constant 0
+        top = pass_top(net, ch.obj_layer);
+        float* A = pool.acquire();
+        launch_fill(A, (long)M * net->nodes[top].size, 0.f, st);
+        launch_fill(cx.c, M, 0.f, st);
+        coef[top] = A;
+    } else if (ch.pp) {
+        // receptive-field rows: sign W[co] on the objective convolution's input window
+        const NetNode& o = net->nodes[net->nodes[net->relus[ch.obj_layer]].src];
+        top = ch.pp->top;
+        float* A = pool.acquire();
+        launch_init_conv_patch(ch.rows, M, o.Wd, net->relu_bias[ch.obj_layer], net->nodes[top].C * o.k * o.k,
+                               o.H * o.W, A, cx.c, st);
         coef[top] = A;
     } else if (ch.obj_layer < 0) {
         top = net->nodes[net->last].src;
@@ -1132,15 +1220,23 @@ static void gamma_projections(PassCtx& cx, const PassChunk& ch, Workspace& ws, c
 }
 
 // Device workspace needed by a chunk of M rows of a pass with the given top node.
-static size_t chunk_bytes(const mnb_net* net, int top, long M, int n_inst, bool adjoint) {
+static size_t chunk_bytes(const mnb_net* net, int top, long M, int n_inst, bool adjoint,
+                          const PatchPlan* pp = nullptr) {
     size_t b = 0;
-    b += 3 * (size_t)M * net->max_width * 4;           // coefficient / forward buffers
+    b += 3 * (size_t)M * net->max_width * 4;            // coefficient / forward buffers
     b += (size_t)M * (pass_cols(net, top) + 1) * 4;     // c + partials
     b += (size_t)M * net->d0 * 5;                       // x* floats + bits
     if (adjoint)
         for (int i : net->relus)
             if (i <= top) b += (size_t)M * net->nodes[i].size * 4;   // a'
     b += (size_t)n_inst * net->total_d * 4 * 4;         // gradients / sums
+    if (pp) {
+        // shared rows (one per instance, whole layers) and the deviation windows of a'
+        b += (size_t)n_inst * (3 * (size_t)net->max_width + net->total_d + net->d0 + pass_cols(net, top) + 2) * 4;
+        if (adjoint)
+            for (int i : net->relus)
+                if (i <= top) b += (size_t)M * pp->width(i) * 4;
+    }
     return b;
 }
 
@@ -1168,13 +1264,85 @@ struct Evaluator {
     Evaluator(mnb_problem* p, const int32_t* s) : pb(p), slots_d(s), ws(p->ws) {}
     Evaluator(mnb_problem* p, const int32_t* s, Workspace& w) : pb(p), slots_d(s), ws(w) {}
 
-    BufPool make_pool(int M, int nbuf) {
+    BufPool make_pool(int M, int nbuf, int width) {
         BufPool pool;
         for (int i = 0; i < nbuf; ++i) {
-            pool.bufs.push_back(ws.get<float>("pool" + std::to_string(i), (size_t)M * pb->net->max_width));
+            pool.bufs.push_back(ws.get<float>("pool" + std::to_string(i), (size_t)M * width));
             pool.ref.push_back(0);
         }
         return pool;
+    }
+
+    // The shared rows of a receptive-field chunk: for every instance the back-substitution of the
+    // zero objective with the instance's parameters (whole layers): a' per ReLU node, the input
+    // coefficients U0, their x* and bound.
+    struct SharedRows {
+        std::map<int, float*> ap;
+        float* U0 = nullptr;
+        float* x0 = nullptr;
+        float* lb = nullptr;
+        BufPool pool;
+    };
+    void shared_rows(const PassChunk& ch, const PassCtx& rcx, SharedRows& sh) {
+        mnb_net* net = pb->net;
+        hipStream_t st = stream();
+        const int n = (int)ch.inst.size();
+        auto& c = const_cast<PassChunk&>(ch);
+        if (!ch.sh_rows_d) {
+            std::vector<RowDesc> rd(n);
+            std::vector<InstDesc> id(n);
+            for (int i = 0; i < n; ++i) {
+                rd[i] = RowDesc{ch.inst[i].b, ch.inst_base + i, 0, 0};
+                id[i] = ch.inst[i];
+                id[i].r0 = i;
+                id[i].r1 = i + 1;
+            }
+            const std::string tg = std::to_string((long)ch.inst_d);
+            c.sh_rows_d = ws.get<RowDesc>("shr" + tg, n);
+            c.sh_inst_d = ws.get<InstDesc>("shi" + tg, n);
+            h2d(c.sh_rows_d, rd.data(), n * sizeof(RowDesc));
+            h2d(c.sh_inst_d, id.data(), n * sizeof(InstDesc));
+        }
+        PassChunk sc;
+        sc.M = n;
+        sc.rows = ch.sh_rows_d;
+        sc.inst = ch.inst;
+        for (int i = 0; i < n; ++i) {
+            sc.inst[i].r0 = i;
+            sc.inst[i].r1 = i + 1;
+        }
+        sc.inst_d = ch.sh_inst_d;
+        sc.obj_layer = ch.obj_layer;
+        sc.zero_rows = true;
+        const int top = chunk_top(net, sc);
+        PassCtx cs{};
+        cs.pb = pb;
+        cs.slots_d = slots_d;
+        cs.c = ws.get<float>("sh_c", n);
+        cs.ldcp = pass_cols(net, top);
+        cs.cpart = ws.get<float>("sh_cpart", (size_t)n * cs.ldcp);
+        cs.ws = &ws;
+        cs.v = rcx.v;
+        cs.vh = rcx.vh;
+        cs.gp = rcx.gp;
+        for (int i : net->relus)
+            if (i <= top) cs.ap[i] = ws.get<float>("sh_ap" + std::to_string(i), (size_t)n * net->nodes[i].size);
+        for (int i = 0; i < 3; ++i) {
+            sh.pool.bufs.push_back(ws.get<float>("sh_pool" + std::to_string(i), (size_t)n * net->max_width));
+            sh.pool.ref.push_back(0);
+        }
+        sh.U0 = run_backsub(cs, sc, sh.pool, true);
+        sh.ap = cs.ap;
+        sh.x0 = ws.get<float>("sh_x0", (size_t)n * net->d0);
+        sh.lb = ws.get<float>("sh_lb", n);
+        ConcArgs ca{};
+        ca.mode = 2;
+        ca.A = sh.U0; ca.c = cs.c; ca.cpart = cs.cpart; ca.ldcp = cs.ldcp; ca.ncp = cs.ncp;
+        ca.rows = sc.rows; ca.slots = slots_d; ca.qid = pb->qid; ca.lo = pb->lo; ca.hi = pb->hi;
+        ca.M = n; ca.d0 = net->d0;
+        ca.G0 = sh.x0;
+        ca.lb_out = sh.lb;
+        launch_concretize(ca, st);
     }
 
     bool no_write = false;   // concretise intermediate rows without touching l/u, skip Adam
@@ -1191,20 +1359,31 @@ struct Evaluator {
         cx.pb = pb;
         cx.slots_d = slots_d;
         cx.c = ws.get<float>("c", M);
-        cx.ldcp = pass_cols(net, top);
+        cx.ldcp = pass_cols(net, top, ch.pp);
         cx.cpart = ws.get<float>("cpart", (size_t)M * cx.ldcp);
         cx.G0 = ws.get<float>("G0", (size_t)M * net->d0);
         cx.ws = &ws;
-        cx.ckpt_stride = (adjoint && !keep_ap && ckpt_stride > 1) ? ckpt_stride : 1;
+        // receptive-field rows keep the deviation windows of a' (no checkpoints)
+        cx.ckpt_stride = (adjoint && !keep_ap && ckpt_stride > 1 && !ch.pp) ? ckpt_stride : 1;
         const bool want_ap = (adjoint || keep_ap) && cx.ckpt_stride == 1;
         if (want_ap)
             for (int i : net->relus)
-                if (i <= top) cx.ap[i] = ws.get<float>("ap" + std::to_string(i), (size_t)M * net->nodes[i].size);
+                if (i <= top) {
+                    cx.ap[i] = ws.get<float>("ap" + std::to_string(i), (size_t)M * net->nodes[i].size);
+                    if (ch.pp) cx.apw[i] = ws.get<float>("apw" + std::to_string(i), (size_t)M * ch.pp->width(i));
+                }
         if (ch.obj_layer < 0) cx.xbits = ws.get<uint8_t>("xbits", (size_t)M * net->d0);
         gamma_projections(cx, ch, ws, "gproj");
-        BufPool pool = make_pool(M, cx.ckpt_stride > 1 ? 6 : 3);
+        BufPool pool = make_pool(M, cx.ckpt_stride > 1 ? 6 : 3, net->max_width);
+        // receptive-field rows: first the shared row of every instance (whole layers)
+        SharedRows sh;
+        if (ch.pp) {
+            shared_rows(ch, cx, sh);
+            cx.ush = sh.ap;
+        }
         const int r0n = net->relus[0];
-        const bool fused = net->bottom_ok && ch.obj_layer != 0 && !(kernel_variants() & MNB_VAR_NO_FUSED_BOTTOM);
+        const bool fused = net->bottom_ok && ch.obj_layer != 0 && !ch.pp &&
+                           !(kernel_variants() & MNB_VAR_NO_FUSED_BOTTOM);
         float* g_bottom = nullptr;
         if (fused) {
             // back-substitute down to the output of ReLU layer 0 (or build the rows there) and
@@ -1367,6 +1546,18 @@ struct Evaluator {
         ca.rows = ch.rows; ca.slots = slots_d; ca.qid = pb->qid; ca.lo = pb->lo; ca.hi = pb->hi;
         ca.M = M; ca.d0 = net->d0;
         ca.G0 = adjoint ? cx.G0 : nullptr;
+        if (ch.pp) {
+            // whole rows for the adjoint: x* and a' of the shared row plus each row's window
+            ca.pg = ch.pp->g[0];
+            ca.ush0 = sh.U0; ca.lbs = sh.lb; ca.inst_base = ch.inst_base;
+            if (adjoint) {
+                launch_patch_expand(sh.x0, nullptr, ch.rows, M, ch.inst_base, ch.pp->g[0], cx.G0, st);
+                for (int i : net->relus)
+                    if (i <= top)
+                        launch_patch_expand(sh.ap.at(i), cx.apw.at(i), ch.rows, M, ch.inst_base, ch.pp->g[i],
+                                            cx.ap.at(i), st);
+            }
+        }
         ca.margin = ch.obj_layer < 0 ? kSpecMargin : 0.f;
         if (ch.obj_layer < 0) {
             ca.mode = 1;
@@ -1381,10 +1572,12 @@ struct Evaluator {
             ca.state_off = net->relu_off[ch.obj_layer];
         }
         {
-            TimerScope ts(MNB_T_CONCRETIZE, 0, 0.0, (double)M * net->d0 * (4 + (ca.G0 ? 4 : 0) + (ca.xbits ? 1 : 0)));
+            TimerScope ts(MNB_T_CONCRETIZE, 0, 0.0,
+                          (double)M * node_width(net, ch, 0) * (4 + (ca.G0 ? 4 : 0) + (ca.xbits ? 1 : 0)));
             launch_concretize(ca, st);
         }
         pool.release(A0);
+        if (sh.pool.bufs.size() && sh.U0) sh.pool.release(sh.U0);
         if (ch.obj_layer < 0 && io.best_bits)
             launch_keep_best_x(cx.xbits, io.best_bits, io.improved, M, net->d0, st);
         }

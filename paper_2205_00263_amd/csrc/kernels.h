@@ -47,7 +47,45 @@ void launch_fc_forward(const float* G, const float* W, const float* b, float* C,
 void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
                          hipStream_t st);
 
+// Relaxation of one neuron (the D / b-underline case table of Section 3.1 with
+// the split matrix of Eq. 4): split first, then stable, then unstable.
+struct NeuronRelax {
+    float dpos, dneg, bneg;
+    bool unstable;
+};
+
+__device__ __forceinline__ NeuronRelax neuron_relax(float l, float u, int s, float alpha) {
+    NeuronRelax r;
+    r.unstable = false;
+    r.bneg = 0.f;
+    if (s == -1) {
+        r.dpos = r.dneg = 1.f;
+    } else if (s == 1) {
+        r.dpos = r.dneg = 0.f;
+    } else if (l >= 0.f) {
+        r.dpos = r.dneg = 1.f;
+    } else if (u <= 0.f) {
+        r.dpos = r.dneg = 0.f;
+    } else {
+        r.unstable = true;
+        r.dpos = alpha;
+        float w = u - l;
+        r.dneg = u / w;
+        r.bneg = -(u * l) / w;
+    }
+    return r;
+}
+
 // ---- elementwise / reduction kernels (relu.hip) ----
+// Receptive-field ("patch") rows: on one node of a pass, every row is the window [C][P][P] of
+// the node that its objective neuron j sees, with origin (y_j S - Q, x_j S - Q), where (y_j, x_j)
+// is j's position (j mod HWobj) on the objective layer.  Entries outside the node are padding.
+struct PatchGeom {
+    int C, H, W;          // node shape
+    int P, S, Q;          // window side, origin stride and offset
+    int HWobj, Wobj;      // positions of the objective layer and its width
+};
+
 struct FoldArgs {
     float* A;             // [M, d] in: a (coef on z), out: ahat (coef on zhat)
     float* Ap;            // [M, d] out: a' (nullable)
@@ -67,6 +105,9 @@ struct FoldArgs {
     // a = sign W[j] is read from Wsrc instead of A, and c[r] = sign bias_obj[j] is written
     // (nullable: a is read from A)
     const float* Wsrc; const RowDesc* rows; float* c; const float* bias_obj;
+    // receptive-field rows: a' of each instance's shared row [n_inst, d] (A holds windows of the
+    // deviation from it)
+    const float* ush;
 };
 void launch_relu_fold(const FoldArgs& a, hipStream_t st);
 
@@ -100,6 +141,11 @@ struct ConcArgs {
     float* l; float* u; long ld_state; int state_off;
     // mode 1
     float* lb_out; float* best; uint8_t* improved;
+    // receptive-field rows (pg.P > 0): A holds windows [M, C0 P P] of each row's deviation from its
+    // instance's shared row, whose input coefficients ush0 [n_inst, d0] and bound lbs [n_inst] are
+    // added; G0 (dense [M, d0], already holding the shared row's x*) gets the window entries
+    PatchGeom pg;
+    const float* ush0; const float* lbs; int inst_base;
 };
 void launch_concretize(const ConcArgs& a, hipStream_t st);
 void launch_keep_best_x(const uint8_t* xbits, uint8_t* best_bits, const uint8_t* improved, int M, int d0,
@@ -173,6 +219,15 @@ void launch_count_unstable(const int32_t* slots, int nb, const float* l, const f
 void launch_build_rows(const int32_t* bs, int nk, const int32_t* slots, const int32_t* row0, const int32_t* inst0,
                        const float* l, const float* u, long ld_state, int off, int d, RowDesc* rows,
                        hipStream_t st);
+
+// ---- patch rows (patch.hip) ----
+void launch_init_conv_patch(const RowDesc* rows, int M, const float* W, const float* bias_eff, int per_co,
+                            int HWobj, float* A, float* c, hipStream_t st);
+void launch_relu_fold_patch(const FoldArgs& a, const PatchGeom& g, const RowDesc* rows, int inst_base,
+                            hipStream_t st);
+// dense rows out[r] = shared[instance of r] + (window entries of win[r], nullable)
+void launch_patch_expand(const float* shared, const float* win, const RowDesc* rows, int M, int inst_base,
+                         const PatchGeom& g, float* out, hipStream_t st);
 void launch_copy_slots(const int32_t* src, const int32_t* dst, int n, void* base, long bytes_per_slot,
                        hipStream_t st);
 void launch_apply_split(const int32_t* child, const int32_t* off_j, const int32_t* sign, int n, float* l, float* u,

@@ -1,0 +1,152 @@
+// Receptive-field ("patch") rows of intermediate-bound passes.
+//
+// An intermediate-bound row +-e_j on the output of a convolution (the rows that recompute the
+// bounds of a ReLU layer after a split, Section 3.2) reaches, through that convolution and every
+// convolution below it (Eq. 2), only the input window that neuron j sees.  The ReLU fold (Eq. 5)
+// however adds the split and constraint terms S beta + Phat^T gamma of the row's parameter set to
+// every row of the set, inside its window or not, and these terms spread through the layers
+// below.  The pass therefore splits each row into the set's shared row (the back-substitution of
+// the zero objective: the part every row of the set has in common, one whole-layer row per set)
+// and the row's deviation from it.  By induction over the layers the deviation is zero outside
+// the row's window: outside it a row's coefficient equals the shared row's, so its relaxation
+// (which depends only on the sign of a') and hence its folded value agree too, and a transposed
+// convolution carries the window of one node into the window of the next.  The deviation rows
+// are stored as windows [C][P][P] with origin (y_j S - Q, x_j S - Q) for the objective position
+// (y_j, x_j); their transposed convolutions are plain convolutions of the window (no padding).
+// The fold and the concretisation (Eq. 6) add back the shared row where the relaxation needs
+// the full coefficient.  The adjoint runs on whole rows rebuilt from the two parts.
+#include "kernels.h"
+
+namespace mnb {
+
+__device__ __forceinline__ void patch_origin(const PatchGeom& g, int j, int& oy, int& ox) {
+    const int pos = j % g.HWobj;
+    const int yo = pos / g.Wobj, xo = pos - yo * g.Wobj;
+    oy = yo * g.S - g.Q;
+    ox = xo * g.S - g.Q;
+}
+
+// ------------------------------------------------------------------ row initialisation
+// Rows +-e_j on the output of a convolution, j = (co, position): the window on the
+// convolution's input is sign * W[co] (all Ci k k taps), the row constant sign * bias[j].
+// (The shared row is zero there.)
+__global__ __launch_bounds__(256) void k_init_conv_patch(const RowDesc* rows, int M, const float* W,
+                                                         const float* bias_eff, int per_co, int HWobj, float* A,
+                                                         float* c, int nblk) {
+    const long bid = blockIdx.x;
+    const int r = (int)(bid / nblk), eb = (int)(bid - (long)r * nblk);
+    if (r >= M) return;
+    const RowDesc rd = rows[r];
+    const float sg = (float)rd.sign;
+    const int co = rd.j / HWobj;
+    const int e = eb * 256 + threadIdx.x;
+    if (e < per_co) A[(long)r * per_co + e] = sg * W[(long)co * per_co + e];
+    if (eb == 0 && threadIdx.x == 0) c[r] = sg * bias_eff[rd.j];
+}
+
+void launch_init_conv_patch(const RowDesc* rows, int M, const float* W, const float* bias_eff, int per_co,
+                            int HWobj, float* A, float* c, hipStream_t st) {
+    if (M <= 0) return;
+    const int nblk = cdiv(per_co, 256);
+    hipLaunchKernelGGL(k_init_conv_patch, dim3((unsigned)((long)M * nblk)), dim3(256), 0, st, rows, M, W, bias_eff,
+                       per_co, HWobj, A, c, nblk);
+    MNB_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ fold (Eq. 5) of deviation windows
+// One workgroup per (row, 256 window entries).  With U' the shared row's a' and d the row's
+// deviation, the row's a' is U' + d; the deviation of ahat is (U' + d) D(U' + d) - U' D(U') (the
+// set's S beta + Phat^T gamma cancel), the deviation of the row constant
+// (U' + d) b(U' + d) - U' b(U') + dev(ahat) . bias; gamma . p is in the shared row's constant.
+// Where both sides select the same slope the deviation is formed as d D (no cancellation).
+__global__ __launch_bounds__(256) void k_relu_fold_patch(FoldArgs a, PatchGeom g, const RowDesc* rows, int inst_base,
+                                                         int nblk) {
+    const long bid = blockIdx.x;
+    const int r = (int)(bid / nblk), eb = (int)(bid - (long)r * nblk);
+    const RowDesc rd = rows[r];
+    const int li = rd.inst - inst_base;
+    const InstDesc in = a.inst[li];
+    const int width = g.C * g.P * g.P;
+    const int e = eb * 256 + threadIdx.x;
+    const bool ok = e < width;
+    int oy, ox;
+    patch_origin(g, rd.j, oy, ox);
+    const int PP = g.P * g.P;
+    const int c = ok ? e / PP : 0;
+    const int q = ok ? e - c * PP : 0;
+    const int Y = oy + q / g.P, X = ox + q % g.P;
+    const bool inside = ok && Y >= 0 && Y < g.H && X >= 0 && X < g.W;
+    const int n = inside ? (c * g.H + Y) * g.W + X : 0;
+    const long so = (long)in.slot * a.ld_state + n;
+    const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
+    float contrib = 0.f;
+    const long idx = (long)r * width + e;
+    const float dv = ok ? a.A[idx] : 0.f;
+    if (inside) {
+        const NeuronRelax nr = neuron_relax(a.l[so], a.u[so], (int)a.S[so], a.alpha[po]);
+        const float U = a.ush[(long)li * a.d + n];
+        const float ap = U + dv;
+        const bool neg = ap < 0.f, uneg = U < 0.f;
+        float dh, dc;
+        if (neg == uneg) {
+            const float D = neg ? nr.dneg : nr.dpos;
+            dh = dv * D;
+            dc = neg ? dv * nr.bneg : 0.f;
+        } else {
+            dh = ap * (neg ? nr.dneg : nr.dpos) - U * (uneg ? nr.dneg : nr.dpos);
+            dc = (neg ? ap * nr.bneg : 0.f) - (uneg ? U * nr.bneg : 0.f);
+        }
+        a.A[idx] = dh;
+        if (a.Ap) a.Ap[idx] = dv;
+        contrib = dc + dh * a.bias[n];
+    } else if (ok) {
+        a.A[idx] = 0.f;
+        if (a.Ap) a.Ap[idx] = 0.f;
+    }
+    contrib = wave_sum(contrib);
+    if ((threadIdx.x & 63) == 0) a.cpart[(long)r * a.ldcp + a.col_off + eb * 4 + (threadIdx.x >> 6)] = contrib;
+}
+
+void launch_relu_fold_patch(const FoldArgs& a, const PatchGeom& g, const RowDesc* rows, int inst_base,
+                            hipStream_t st) {
+    if (a.M <= 0) return;
+    const int nblk = cdiv(g.C * g.P * g.P, 256);
+    hipLaunchKernelGGL(k_relu_fold_patch, dim3((unsigned)((long)a.M * nblk)), dim3(256), 0, st, a, g, rows,
+                       inst_base, nblk);
+    MNB_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ whole rows from the two parts
+// out[r][n] = shared[instance of r][n] (+ the window entry of row r at n, if win and n lies in
+// the window).  One workgroup per (row, 256 neurons).
+__global__ __launch_bounds__(256) void k_patch_expand(const float* shared, const float* win, const RowDesc* rows,
+                                                      int inst_base, PatchGeom g, float* out, int nblk) {
+    const long bid = blockIdx.x;
+    const int r = (int)(bid / nblk), b = (int)(bid - (long)r * nblk);
+    const int d = g.C * g.H * g.W;
+    const int n = b * 256 + threadIdx.x;
+    if (n >= d) return;
+    const RowDesc rd = rows[r];
+    const int li = rd.inst - inst_base;
+    float v = shared[(long)li * d + n];
+    if (win) {
+        int oy, ox;
+        patch_origin(g, rd.j, oy, ox);
+        const int c = n / (g.H * g.W), rem = n - c * g.H * g.W;
+        const int dy = rem / g.W - oy, dx = rem % g.W - ox;
+        if (dy >= 0 && dy < g.P && dx >= 0 && dx < g.P)
+            v += win[(long)r * g.C * g.P * g.P + (c * g.P + dy) * g.P + dx];
+    }
+    out[(long)r * d + n] = v;
+}
+
+void launch_patch_expand(const float* shared, const float* win, const RowDesc* rows, int M, int inst_base,
+                         const PatchGeom& g, float* out, hipStream_t st) {
+    if (M <= 0) return;
+    const int nblk = cdiv((long)g.C * g.H * g.W, 256);
+    hipLaunchKernelGGL(k_patch_expand, dim3((unsigned)((long)M * nblk)), dim3(256), 0, st, shared, win, rows,
+                       inst_base, g, out, nblk);
+    MNB_HIP(hipGetLastError());
+}
+
+}  // namespace mnb

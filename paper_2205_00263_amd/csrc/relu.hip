@@ -13,35 +13,6 @@
 
 namespace mnb {
 
-// Relaxation of one neuron (the D / b-underline case table of Section 3.1 with
-// the split matrix of Eq. 4): split first, then stable, then unstable.
-struct NeuronRelax {
-    float dpos, dneg, bneg;
-    bool unstable;
-};
-
-__device__ __forceinline__ NeuronRelax neuron_relax(float l, float u, int s, float alpha) {
-    NeuronRelax r;
-    r.unstable = false;
-    r.bneg = 0.f;
-    if (s == -1) {
-        r.dpos = r.dneg = 1.f;
-    } else if (s == 1) {
-        r.dpos = r.dneg = 0.f;
-    } else if (l >= 0.f) {
-        r.dpos = r.dneg = 1.f;
-    } else if (u <= 0.f) {
-        r.dpos = r.dneg = 0.f;
-    } else {
-        r.unstable = true;
-        r.dpos = alpha;
-        float w = u - l;
-        r.dneg = u / w;
-        r.bneg = -(u * l) / w;
-    }
-    return r;
-}
-
 // ------------------------------------------------------------------ fold (Eq. 5)
 __global__ __launch_bounds__(256) void k_relu_fold(FoldArgs a, const float* gp) {
     const InstDesc in = a.inst[blockIdx.y];
@@ -181,6 +152,7 @@ void launch_relu_relax(const RelaxArgs& a, hipStream_t st) {
 // ReLU folds); a spec row's bound is lowered by the rounding margin
 // 2^-20 (sum_j |a_j| max(|lo_j|,|hi_j|) + |c_r|), an intermediate row's is not.
 // x*_j = hi_j if a_j < 0 else lo_j.
+template <bool PATCH>
 __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
     const int r = blockIdx.x;
     const RowDesc rd = a.rows[r];
@@ -188,16 +160,43 @@ __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
     const int q = a.qid[slot];
     const float* lo = a.lo + (long)q * a.d0;
     const float* hi = a.hi + (long)q * a.d0;
-    const float* A = a.A + (long)r * a.d0;
     float s = 0.f, mag = 0.f;
-    for (int j = threadIdx.x; j < a.d0; j += 256) {
-        const float c = A[j];
-        const float l = lo[j], h = hi[j];
-        s += fminf(c * l, c * h);
-        mag += fabsf(c) * fmaxf(fabsf(l), fabsf(h));
-        const bool neg = c < 0.f;
-        if (a.G0) a.G0[(long)r * a.d0 + j] = neg ? h : l;
-        if (a.xbits) a.xbits[(long)r * a.d0 + j] = neg ? 1 : 0;
+    if (PATCH) {
+        // deviation window of a receptive-field row: the row's coefficient is U + dev, with U the
+        // shared row's input coefficients; sum of min(c lo, c hi) - min(U lo, U hi) over the window
+        const PatchGeom& g = a.pg;
+        const int width = g.C * g.P * g.P;
+        const int li = rd.inst - a.inst_base;
+        const float* Ush = a.ush0 + (long)li * a.d0;
+        const float* A = a.A + (long)r * width;
+        const int pos = rd.j % g.HWobj;
+        const int oy = (pos / g.Wobj) * g.S - g.Q, ox = (pos % g.Wobj) * g.S - g.Q;
+        for (int e = threadIdx.x; e < width; e += 256) {
+            const int ch = e / (g.P * g.P), qq = e - ch * g.P * g.P;
+            const int Y = oy + qq / g.P, X = ox + qq % g.P;
+            if (Y < 0 || Y >= g.H || X < 0 || X >= g.W) continue;
+            const int j = (ch * g.H + Y) * g.W + X;
+            const float dv = A[e], U = Ush[j];
+            const float c = U + dv;
+            const float l = lo[j], h = hi[j];
+            const bool neg = c < 0.f;
+            if (neg == (U < 0.f))
+                s += dv * (neg ? h : l);
+            else
+                s += fminf(c * l, c * h) - fminf(U * l, U * h);
+            if (a.G0) a.G0[(long)r * a.d0 + j] = neg ? h : l;
+        }
+    } else {
+        const float* A = a.A + (long)r * a.d0;
+        for (int j = threadIdx.x; j < a.d0; j += 256) {
+            const float c = A[j];
+            const float l = lo[j], h = hi[j];
+            s += fminf(c * l, c * h);
+            mag += fabsf(c) * fmaxf(fabsf(l), fabsf(h));
+            const bool neg = c < 0.f;
+            if (a.G0) a.G0[(long)r * a.d0 + j] = neg ? h : l;
+            if (a.xbits) a.xbits[(long)r * a.d0 + j] = neg ? 1 : 0;
+        }
     }
     __shared__ float red[2][4];
     s = wave_sum(s);
@@ -208,7 +207,8 @@ __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
     }
     __syncthreads();
     if (threadIdx.x >= 64) return;
-    const float c = row_constant(a.c, a.cpart, a.ldcp, a.ncp, r);
+    float c = row_constant(a.c, a.cpart, a.ldcp, a.ncp, r);
+    if (PATCH) c += a.lbs[rd.inst - a.inst_base];   // the shared row's bound
     if (threadIdx.x != 0) return;
     const float tot = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) + c;
     const float m = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) + fabsf(c);
@@ -240,7 +240,10 @@ __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
 
 void launch_concretize(const ConcArgs& a, hipStream_t st) {
     if (a.M <= 0) return;
-    hipLaunchKernelGGL(k_concretize, dim3(a.M), dim3(256), 0, st, a);
+    if (a.pg.P > 0)
+        hipLaunchKernelGGL(k_concretize<true>, dim3(a.M), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_concretize<false>, dim3(a.M), dim3(256), 0, st, a);
     MNB_HIP(hipGetLastError());
 }
 
@@ -797,14 +800,11 @@ void launch_count_unstable(const int32_t* slots, int nb, const float* l, const f
 // unstable neurons in index order, lower rows (+e_j, instance 2k) then upper
 // rows (-e_j, instance 2k+1), starting at row offset row0[b].
 __global__ void k_build_rows(const int32_t* bs, const int32_t* slots, const int32_t* row0, const int32_t* inst0,
-                             const float* l, const float* u, long ld_state, int off, int d, int32_t n_of_b_total,
-                             RowDesc* rows) {
+                             const float* l, const float* u, long ld_state, int off, int d, RowDesc* rows) {
     const int k = blockIdx.x;
     const int b = bs[k];
     const int slot = slots[b];
     const int base = row0[k];
-    const int n = n_of_b_total;  // unused guard
-    (void)n;
     __shared__ int scan[256];
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
@@ -852,7 +852,7 @@ void launch_build_rows(const int32_t* bs, int nk, const int32_t* slots, const in
                        const float* l, const float* u, long ld_state, int off, int d, RowDesc* rows,
                        hipStream_t st) {
     if (nk <= 0) return;
-    hipLaunchKernelGGL(k_build_rows, dim3(nk), dim3(256), 0, st, bs, slots, row0, inst0, l, u, ld_state, off, d, 0,
+    hipLaunchKernelGGL(k_build_rows, dim3(nk), dim3(256), 0, st, bs, slots, row0, inst0, l, u, ld_state, off, d,
                        rows);
     MNB_HIP(hipGetLastError());
 }
