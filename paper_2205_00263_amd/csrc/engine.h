@@ -73,6 +73,11 @@ struct NetNode {
 // when every node below that convolution is a convolution or a ReLU: for each node of the pass
 // the window geometry of its rows, for each convolution the convolution between windows
 // (padding 0: a window holds every tap its outputs read) and its multiply-adds per row.
+//
+// The adjoint of such rows runs on forward cones: a row's forward values (Appendix of the
+// adjoint: x* pushed through the row's linearisation) differ from its set's shared row only on
+// the positions its input window reaches going up, the cone; per node its geometry fc (origin
+// y_j S - Q, side P) and per convolution the convolution between cones (no bias: deviations).
 struct PatchPlan {
     bool ok = false;
     int top = -1;                  // the objective convolution's input node
@@ -81,6 +86,11 @@ struct PatchPlan {
     std::vector<double> macs;      // per node index
     int max_width = 0;
     int width(int n) const { return g[n].C * g[n].P * g[n].P; }
+    bool cone_ok = false;          // adjoint on cones (else on whole rows)
+    std::vector<PatchGeom> fc;     // per node index
+    std::vector<ConvGeom> fconv;   // per node index (convolution nodes)
+    std::vector<double> fmacs;     // per node index
+    int cone_width(int n) const { return fc[n].C * fc[n].P * fc[n].P; }
 };
 
 }  // namespace mnb

@@ -161,6 +161,7 @@ int initial_variants() {
     if (getenv("MNB_NO_WIN_BOTTOM")) m |= MNB_VAR_NO_WINDOW;
     if (getenv("MNB_NO_FUSED_BOTTOM")) m |= MNB_VAR_NO_FUSED_BOTTOM;
     if (getenv("MNB_NO_PATCH")) m |= MNB_VAR_NO_PATCH;
+    if (getenv("MNB_NO_CONE")) m |= MNB_VAR_NO_CONE;
     return m;
 }
 std::atomic<int> g_variants{initial_variants()};
@@ -298,8 +299,59 @@ static PatchPlan make_patch_plan(mnb_net* net, int m, const std::map<int, std::v
             return PatchPlan{};
         }
     }
-    pp.ok = 2 * win <= dense;
+    // the pass buffers hold [M, max_width] and x* [M, d0]
+    pp.ok = 2 * win <= dense && pp.max_width <= net->max_width && pp.width(0) <= net->d0;
     if (!pp.ok) return PatchPlan{};
+    // forward cones, from the input up: a convolution k / s / p maps a cone [c, c + Pc) of its
+    // input to the outputs y with y s - p <= c + Pc - 1 and y s - p + k - 1 >= c; its origin stays
+    // affine in the objective position with the window's stride, so one convolution between
+    // cones (padding c + p - y_min s) serves every row
+    std::vector<int> chain;
+    for (int m = pp.top; ; m = net->nodes[m].src) {
+        chain.push_back(m);
+        if (m == 0) break;
+    }
+    std::reverse(chain.begin(), chain.end());
+    pp.fc.assign(nn, PatchGeom{});
+    pp.fconv.assign(nn, ConvGeom{});
+    pp.fmacs.assign(nn, 0.0);
+    pp.fc[0] = pp.g[0];
+    long cone = pp.fc[0].C * (long)pp.fc[0].P * pp.fc[0].P;
+    bool ok = true;
+    for (size_t t = 1; t < chain.size(); ++t) {
+        const int m = chain[t];
+        const NetNode& nd = net->nodes[m];
+        const PatchGeom& in = pp.fc[nd.src];
+        PatchGeom o = pp.g[m];
+        if (nd.kind == MNB_CONV) {
+            const int k = nd.k, s = nd.stride, p = nd.pad;
+            const int c_in = -in.Q;   // cone origin for objective position 0
+            auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+            const int y_min = -fdiv(-(c_in + p - k + 1), s);   // ceil
+            const int y_max = fdiv(c_in + in.P - 1 + p, s);
+            const int pad_v = c_in + p - y_min * s;
+            o.Q = -y_min;
+            o.P = y_max - y_min + 1;
+            o.S = in.S / s;
+            ok = ok && in.S % s == 0 && pad_v >= 0 && pad_v < k && o.P > 0;
+            if (!ok) break;
+            std::vector<float> zb(nd.C, 0.f);
+            float* zbd = upload(zb.data(), zb.size(), &net->owned);
+            fill_conv_geom(net, pp.fconv[m], net->nodes[nd.src].C, in.P, in.P, nd.C, o.P, o.P, k, s, pad_v, nd.Wd, zbd,
+                           wh.at(m));
+            pp.fmacs[m] = (double)nd.C * net->nodes[nd.src].C * k * k * o.P * o.P;
+        } else {
+            o.Q = in.Q;
+            o.P = in.P;
+            o.S = in.S;
+        }
+        // the cone holds the backward window of the node
+        ok = ok && o.S == pp.g[m].S && -o.Q <= -pp.g[m].Q && -o.Q + o.P >= -pp.g[m].Q + pp.g[m].P;
+        pp.fc[m] = o;
+        cone += o.C * (long)o.P * o.P;
+        ok = ok && o.C * (long)o.P * o.P <= net->max_width;
+    }
+    pp.cone_ok = ok && 3 * cone <= 2 * dense;
     return pp;
 }
 
@@ -793,6 +845,7 @@ struct PassChunk {
     // receptive-field rows (nullable): windows of each row's deviation from its instance's
     // shared row
     const PatchPlan* pp = nullptr;
+    bool cone = false;                // the adjoint runs on forward cones
     int inst_base = 0;                // pass-wide index of the chunk's first instance
     // the shared rows, one per instance (descriptors built on first use)
     RowDesc* sh_rows_d = nullptr;
@@ -1278,6 +1331,7 @@ struct Evaluator {
     // coefficients U0, their x* and bound.
     struct SharedRows {
         std::map<int, float*> ap;
+        std::map<int, float*> ghat;   // forward values at each ReLU's input (cone adjoint)
         float* U0 = nullptr;
         float* x0 = nullptr;
         float* lb = nullptr;
@@ -1345,6 +1399,92 @@ struct Evaluator {
         launch_concretize(ca, st);
     }
 
+    // Forward values of the shared rows (their x* through their own relaxation, whole layers),
+    // kept at every ReLU input for the cone adjoint.
+    void shared_forward(const PassChunk& ch, SharedRows& sh) {
+        mnb_net* net = pb->net;
+        hipStream_t st = stream();
+        const int n = (int)ch.inst.size();
+        const int top = chunk_top(net, ch);
+        const float* gp = sh.x0;
+        for (int m = 1; m <= top; ++m) {
+            const NetNode& nd = net->nodes[m];
+            if (nd.kind == MNB_CONV) {
+                float* out = ws.get<float>("sh_f" + std::to_string(m), (size_t)n * nd.size);
+                launch_conv_forward(nd.geom, gp, out, n, false, st);
+                gp = out;
+            } else if (nd.kind == MNB_RELU) {
+                const int r = nd.relu_m;
+                sh.ghat[m] = const_cast<float*>(gp);
+                float* gs = ws.get<float>("sh_g" + std::to_string(m), (size_t)n * nd.size);
+                RelaxArgs ra{};
+                ra.inst = ch.inst_d; ra.n_inst = n; ra.d = nd.size;
+                ra.l = pb->l + net->relu_off[r]; ra.u = pb->u + net->relu_off[r];
+                ra.S = pb->S_ + net->relu_off[r]; ra.ld_state = pb->ld_state;
+                ra.alpha = pb->alpha + net->relu_off[r]; ra.ld_param = pb->ld_param; ra.n_sets = pb->n_sets;
+                launch_relax_shared(ra, sh.ap.at(m), gp, gs, st);
+                gp = gs;
+            } else {
+                throw Error{MNB_EDEVICE, "unexpected node in a receptive-field pass"};
+            }
+        }
+    }
+
+    // Adjoint of receptive-field rows on forward cones: the rows' x* deviation (G0, cone of the
+    // input) is pushed up through the convolutions between cones; each ReLU relaxes the rows'
+    // deviations and reduces the instance's gradients with the shared rows' terms.
+    void adjoint_cone(PassCtx& cx, const PassChunk& ch, BufPool& pool, const SharedRows& sh, float* g_alpha,
+                      float* g_beta, float* g_gamma, float* gs_hat, float* gs_out) {
+        mnb_net* net = pb->net;
+        hipStream_t st = stream();
+        const int M = ch.M, n_inst = (int)ch.inst.size();
+        const int top = chunk_top(net, ch);
+        const PatchPlan& pp = *ch.pp;
+        float* g = cx.G0;
+        for (int m = 1; m <= top; ++m) {
+            const NetNode& nd = net->nodes[m];
+            if (nd.kind == MNB_CONV) {
+                float* out = pool.acquire();
+                {
+                    TimerScope ts(MNB_T_CONV_FORWARD, m, 2.0 * M * pp.fmacs[m],
+                                  4.0 * M * (pp.cone_width(m) + pp.cone_width(nd.src)));
+                    launch_conv_forward(pp.fconv[m], g, out, M, false, st);
+                }
+                if (g != cx.G0) pool.release(g);
+                g = out;
+            } else {
+                const int r = nd.relu_m;
+                RelaxArgs ra{};
+                ra.inst = ch.inst_d; ra.n_inst = n_inst; ra.slots = cx.slots_d;
+                ra.M = M; ra.d = nd.size;
+                ra.l = pb->l + net->relu_off[r]; ra.u = pb->u + net->relu_off[r];
+                ra.S = pb->S_ + net->relu_off[r]; ra.ld_state = pb->ld_state;
+                ra.alpha = pb->alpha + net->relu_off[r]; ra.ld_param = pb->ld_param; ra.n_sets = pb->n_sets;
+                ra.d_alpha = g_alpha; ra.d_beta = g_beta; ra.ldg = pb->ld_param; ra.goff = net->relu_off[r];
+                ra.gsum_hat = pb->has_mnc ? gs_hat : nullptr;
+                ra.gsum_out = pb->has_mnc ? gs_out : nullptr;
+                {
+                    TimerScope ts(MNB_T_RELAX, m, 0.0, 8.0 * M * pp.cone_width(m) + 4.0 * M * pp.width(m));
+                    launch_relax_cone(ra, pp.g[m], pp.fc[m], ch.rows, sh.ap.at(m), sh.ghat.at(m), cx.apw.at(m), g,
+                                      st);
+                }
+                if (pb->has_mnc) {
+                    auto& ml = pb->mnc[r];
+                    GammaArgs ga{};
+                    ga.inst = ch.inst_d; ga.n_inst = n_inst; ga.qid = pb->qid;
+                    ga.gamma = pb->gamma; ga.ld_gamma = pb->ld_gamma; ga.n_sets = pb->n_sets;
+                    ga.goff = r * pb->e_cap;
+                    ga.d = nd.size; ga.e_cap = pb->e_cap; ga.nnz_cap = pb->nnz_cap;
+                    ga.e_of = ml.e_of; ga.colptr = ml.colptr; ga.col_e = ml.col_e; ga.col_P = ml.col_P;
+                    ga.col_Ph = ml.col_Ph; ga.rowptr = ml.rowptr; ga.row_j = ml.row_j; ga.row_P = ml.row_P;
+                    ga.row_Ph = ml.row_Ph; ga.p = ml.p;
+                    launch_gamma_grad(ga, gs_hat, gs_out, g_gamma, pb->ld_gamma, st);
+                }
+            }
+        }
+        if (g != cx.G0) pool.release(g);
+    }
+
     bool no_write = false;   // concretise intermediate rows without touching l/u, skip Adam
     int ckpt_stride = 1;     // adjoint checkpoint stride over ReLU layers (1: keep every a')
     float *g_alpha_last = nullptr, *g_beta_last = nullptr, *g_gamma_last = nullptr;
@@ -1369,7 +1509,8 @@ struct Evaluator {
         if (want_ap)
             for (int i : net->relus)
                 if (i <= top) {
-                    cx.ap[i] = ws.get<float>("ap" + std::to_string(i), (size_t)M * net->nodes[i].size);
+                    if (!ch.cone)
+                        cx.ap[i] = ws.get<float>("ap" + std::to_string(i), (size_t)M * net->nodes[i].size);
                     if (ch.pp) cx.apw[i] = ws.get<float>("apw" + std::to_string(i), (size_t)M * ch.pp->width(i));
                 }
         if (ch.obj_layer < 0) cx.xbits = ws.get<uint8_t>("xbits", (size_t)M * net->d0);
@@ -1380,6 +1521,7 @@ struct Evaluator {
         if (ch.pp) {
             shared_rows(ch, cx, sh);
             cx.ush = sh.ap;
+            if (adjoint && ch.cone) shared_forward(ch, sh);
         }
         const int r0n = net->relus[0];
         const bool fused = net->bottom_ok && ch.obj_layer != 0 && !ch.pp &&
@@ -1550,7 +1692,8 @@ struct Evaluator {
             // whole rows for the adjoint: x* and a' of the shared row plus each row's window
             ca.pg = ch.pp->g[0];
             ca.ush0 = sh.U0; ca.lbs = sh.lb; ca.inst_base = ch.inst_base;
-            if (adjoint) {
+            ca.g0_dev = ch.cone;
+            if (adjoint && !ch.cone) {
                 launch_patch_expand(sh.x0, nullptr, ch.rows, M, ch.inst_base, ch.pp->g[0], cx.G0, st);
                 for (int i : net->relus)
                     if (i <= top)
@@ -1605,6 +1748,8 @@ struct Evaluator {
                                   ws.get<float>("gs_out0", (size_t)n_inst * net->max_width), g_gamma, pb->ld_gamma, st);
             }
             if (g_bottom) run_adjoint(cx, ch, pool, g_alpha, g_beta, g_gamma, gs_hat, gs_out, r0n, g_bottom);
+        } else if (ch.pp && ch.cone) {
+            adjoint_cone(cx, ch, pool, sh, g_alpha, g_beta, g_gamma, gs_hat, gs_out);
         } else {
             run_adjoint(cx, ch, pool, g_alpha, g_beta, g_gamma, gs_hat, gs_out);
         }

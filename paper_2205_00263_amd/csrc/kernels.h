@@ -146,6 +146,7 @@ struct ConcArgs {
     // added; G0 (dense [M, d0], already holding the shared row's x*) gets the window entries
     PatchGeom pg;
     const float* ush0; const float* lbs; int inst_base;
+    int g0_dev;            // G0 holds the windows of x* - x*(shared row) [M, C0 P P] instead
 };
 void launch_concretize(const ConcArgs& a, hipStream_t st);
 void launch_keep_best_x(const uint8_t* xbits, uint8_t* best_bits, const uint8_t* improved, int M, int d0,
@@ -225,6 +226,11 @@ void launch_init_conv_patch(const RowDesc* rows, int M, const float* W, const fl
                             int HWobj, float* A, float* c, hipStream_t st);
 void launch_relu_fold_patch(const FoldArgs& a, const PatchGeom& g, const RowDesc* rows, int inst_base,
                             hipStream_t st);
+// shared rows' forward relaxation gs = D(U') ghs + b(U') per (instance, neuron)
+void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs, float* gs, hipStream_t st);
+// adjoint relaxation of rows held as cone deviations Gd (in place) with their a' deviation windows
+void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
+                       const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st);
 // dense rows out[r] = shared[instance of r] + (window entries of win[r], nullable)
 void launch_patch_expand(const float* shared, const float* win, const RowDesc* rows, int M, int inst_base,
                          const PatchGeom& g, float* out, hipStream_t st);

@@ -17,6 +17,8 @@
 // the full coefficient.  The adjoint runs on whole rows rebuilt from the two parts.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace mnb {
 
 __device__ __forceinline__ void patch_origin(const PatchGeom& g, int j, int& oy, int& ox) {
@@ -146,6 +148,126 @@ void launch_patch_expand(const float* shared, const float* win, const RowDesc* r
     const int nblk = cdiv((long)g.C * g.H * g.W, 256);
     hipLaunchKernelGGL(k_patch_expand, dim3((unsigned)((long)M * nblk)), dim3(256), 0, st, shared, win, rows,
                        inst_base, g, out, nblk);
+    MNB_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ adjoint on forward cones
+// Shared rows' relaxation of forward values: g = D(U') ghat + b(U') per (instance, neuron).
+__global__ __launch_bounds__(256) void k_relax_shared(RelaxArgs a, const float* ush, const float* ghs, float* gs) {
+    const int li = blockIdx.y;
+    const InstDesc in = a.inst[li];
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= a.d) return;
+    const long so = (long)in.slot * a.ld_state + n;
+    const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
+    const NeuronRelax nr = neuron_relax(a.l[so], a.u[so], (int)a.S[so], a.alpha[po]);
+    const long i = (long)li * a.d + n;
+    const bool un = ush[i] < 0.f;
+    gs[i] = (un ? nr.dneg : nr.dpos) * ghs[i] + (un ? nr.bneg : 0.f);
+}
+
+void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs, float* gs, hipStream_t st) {
+    if (a.n_inst <= 0) return;
+    hipLaunchKernelGGL(k_relax_shared, dim3(cdiv(a.d, 256), a.n_inst), dim3(256), 0, st, a, ush, ghs, gs);
+    MNB_HIP(hipGetLastError());
+}
+
+// The relaxation step of the adjoint (g = D ghat + b, with the parameter-gradient sums of every
+// instance, as k_relu_relax) for rows held as deviations from their instance's shared row: Gd
+// holds each row's forward deviation on its cone, apw its a' deviation on its window.  One
+// thread per (instance, channel, position) of a frame that holds every cone; it walks the
+// instance's rows in order (their cone and window origins staged in LDS, 256 at a time), takes
+// the rows whose cone holds its position and writes their new deviation (0 outside the node);
+// every other row equals the shared row there, whose terms enter the sums once per such row.
+__global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, PatchGeom gc, const RowDesc* rows,
+                                                    const float* ush, const float* ghs, const float* apw, float* Gd,
+                                                    int y_lo, int x_lo, int FH, int FW) {
+    const int li = blockIdx.y;
+    const InstDesc in = a.inst[li];
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const bool act = t < gc.C * FH * FW;
+    const int tt = act ? t : 0;
+    const int c = tt / (FH * FW);
+    const int rem = tt - c * FH * FW;
+    const int Y = y_lo + rem / FW, X = x_lo + rem % FW;
+    const bool inside = act && Y >= 0 && Y < gc.H && X >= 0 && X < gc.W;
+    const int n = inside ? (c * gc.H + Y) * gc.W + X : 0;
+    NeuronRelax nr{0.f, 0.f, 0.f, false};
+    float U = 0.f, Gh = 0.f, Gs = 0.f;
+    int s = 0;
+    if (inside) {
+        const long so = (long)in.slot * a.ld_state + n;
+        const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
+        s = (int)a.S[so];
+        nr = neuron_relax(a.l[so], a.u[so], s, a.alpha[po]);
+        U = ush[(long)li * a.d + n];
+        Gh = ghs[(long)li * a.d + n];
+        Gs = (U < 0.f ? nr.dneg : nr.dpos) * Gh + (U < 0.f ? nr.bneg : 0.f);
+    }
+    const bool un = U < 0.f;
+    const int Pc = gc.P, Pw = gw.P;
+    const int cw = gc.C * Pc * Pc, ww = gw.C * Pw * Pw;
+    const long coff = (long)c * Pc * Pc, woff = (long)c * Pw * Pw;
+    float da = 0.f, sh = 0.f, sg = 0.f;
+    int cnt = 0;
+    __shared__ int4 org[256];
+    for (int r0 = in.r0; r0 < in.r1; r0 += 256) {
+        __syncthreads();
+        if (r0 + (int)threadIdx.x < in.r1) {
+            const int pos = rows[r0 + threadIdx.x].j % gc.HWobj;
+            const int yo = pos / gc.Wobj, xo = pos - yo * gc.Wobj;
+            org[threadIdx.x] = make_int4(yo * gc.S - gc.Q, xo * gc.S - gc.Q, yo * gw.S - gw.Q, xo * gw.S - gw.Q);
+        }
+        __syncthreads();
+        const int nrow = min(256, in.r1 - r0);
+        if (!act) continue;
+        for (int k = 0; k < nrow; ++k) {
+            const int4 o = org[k];
+            const int dy = Y - o.x, dx = X - o.y;
+            if ((unsigned)dy >= (unsigned)Pc || (unsigned)dx >= (unsigned)Pc) continue;
+            const long e = (long)(r0 + k) * cw + coff + dy * Pc + dx;
+            if (!inside) {
+                Gd[e] = 0.f;
+                continue;
+            }
+            const float dgh = Gd[e];
+            const float gh = Gh + dgh;
+            const int wy = Y - o.z, wx = X - o.w;
+            const float dv = ((unsigned)wy < (unsigned)Pw && (unsigned)wx < (unsigned)Pw)
+                                 ? apw[(long)(r0 + k) * ww + woff + wy * Pw + wx] : 0.f;
+            const float ap = U + dv;
+            const bool neg = ap < 0.f;
+            const float g = (neg ? nr.dneg : nr.dpos) * gh + (neg ? nr.bneg : 0.f);
+            Gd[e] = neg == un ? (neg ? nr.dneg : nr.dpos) * dgh : g - Gs;
+            if (nr.unstable && !neg) da += ap * gh;
+            sh += gh;
+            sg += g;
+            ++cnt;
+        }
+    }
+    if (!inside) return;
+    const float rest = (float)(in.r1 - in.r0 - cnt);
+    if (nr.unstable && !un) da += rest * (U * Gh);
+    sh += rest * Gh;
+    sg += rest * Gs;
+    const long go = (long)li * a.ldg + a.goff + n;
+    a.d_alpha[go] = da;
+    a.d_beta[go] = (float)s * sh;
+    if (a.gsum_hat) a.gsum_hat[(long)li * a.d + n] = sh;
+    if (a.gsum_out) a.gsum_out[(long)li * a.d + n] = sg;
+}
+
+void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
+                       const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st) {
+    if (a.n_inst <= 0) return;
+    // frame: the node plus every cone position any objective position reaches
+    const int Hobj = gc.HWobj / gc.Wobj;
+    const int y_lo = std::min(-gc.Q, 0), x_lo = std::min(-gc.Q, 0);
+    const int y_hi = std::max((Hobj - 1) * gc.S - gc.Q + gc.P, gc.H);
+    const int x_hi = std::max((gc.Wobj - 1) * gc.S - gc.Q + gc.P, gc.W);
+    const int FH = y_hi - y_lo, FW = x_hi - x_lo;
+    dim3 grid(cdiv((long)gc.C * FH * FW, 256), a.n_inst);
+    hipLaunchKernelGGL(k_relax_cone, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo, FH, FW);
     MNB_HIP(hipGetLastError());
 }
 

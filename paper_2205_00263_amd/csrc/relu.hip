@@ -174,17 +174,25 @@ __global__ __launch_bounds__(256) void k_concretize(ConcArgs a) {
         for (int e = threadIdx.x; e < width; e += 256) {
             const int ch = e / (g.P * g.P), qq = e - ch * g.P * g.P;
             const int Y = oy + qq / g.P, X = ox + qq % g.P;
-            if (Y < 0 || Y >= g.H || X < 0 || X >= g.W) continue;
+            if (Y < 0 || Y >= g.H || X < 0 || X >= g.W) {
+                if (a.G0 && a.g0_dev) a.G0[(long)r * width + e] = 0.f;
+                continue;
+            }
             const int j = (ch * g.H + Y) * g.W + X;
             const float dv = A[e], U = Ush[j];
             const float c = U + dv;
             const float l = lo[j], h = hi[j];
-            const bool neg = c < 0.f;
-            if (neg == (U < 0.f))
+            const bool neg = c < 0.f, uneg = U < 0.f;
+            if (neg == uneg)
                 s += dv * (neg ? h : l);
             else
                 s += fminf(c * l, c * h) - fminf(U * l, U * h);
-            if (a.G0) a.G0[(long)r * a.d0 + j] = neg ? h : l;
+            if (a.G0) {
+                if (a.g0_dev)
+                    a.G0[(long)r * width + e] = neg == uneg ? 0.f : (neg ? h - l : l - h);
+                else
+                    a.G0[(long)r * a.d0 + j] = neg ? h : l;
+            }
         }
     } else {
         const float* A = a.A + (long)r * a.d0;

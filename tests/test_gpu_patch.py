@@ -17,7 +17,7 @@ from _common import assert_parity, make_batch, oracle_query, oracle_subproblem, 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-NO_FUSED, NO_PATCH = 32, 64
+NO_FUSED, NO_PATCH, NO_CONE = 32, 64, 128
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -86,16 +86,18 @@ def _close(a, b, what, rel=2e-5):
     assert np.all(err <= rel * np.maximum(1.0, np.abs(b[fin]))), f"{what}: worst {err.max():.3e}"
 
 
+@pytest.mark.parametrize("cone", [True, False])
 @pytest.mark.parametrize("cap", [0, 60])
-def test_patch_rows_equal_whole_layer_rows(cap):
-    """The same batch (16 subproblems, 3 Adam steps) with receptive-field rows and with whole-layer
-    rows: root bounds, reported lb and every intermediate bound agree to FP32 summation order
-    (2e-5 relative), and the folds of the window path move far fewer bytes."""
+def test_patch_rows_equal_whole_layer_rows(cap, cone):
+    """The same batch (16 subproblems, 3 Adam steps) with receptive-field rows (adjoint on forward
+    cones, or on whole rows rebuilt from the windows) and with whole-layer rows: root bounds,
+    reported lb and every intermediate bound agree to FP32 summation order, and the folds of the
+    window path move far fewer bytes."""
     wl = _medium()
     net_o, q = oracle_query(wl)
     root_o, _ = oo.root_pass(q)
     splits = _splits(root_unstable(net_o, root_o), 16, seed=5 + cap)
-    a = _run(wl, NO_FUSED, splits, 3, cap)
+    a = _run(wl, NO_FUSED if cone else NO_FUSED | NO_CONE, splits, 3, cap)
     b = _run(wl, NO_FUSED | NO_PATCH, splits, 3, cap)
     _close(a["rlb"], b["rlb"], "root lb")
     for m in range(len(a["root"])):
@@ -140,7 +142,7 @@ def test_patch_gradients_match_whole_layer():
     unst = root_unstable(net_o, root_o)
     split = [[(0, int(unst[0][0]), 1), (1, int(unst[1][0]), -1), (0, int(unst[0][5]), -1)]]
     got = {}
-    for mask in (NO_FUSED, NO_FUSED | NO_PATCH):
+    for mask in (NO_FUSED, NO_FUSED | NO_CONE, NO_FUSED | NO_PATCH):
         P.set_kernel_variants(mask)
         net = P.Net(wl.nodes)
         pb = P.Problem(net, n_spec=wl.C.shape[0], capacity=16)
@@ -151,12 +153,14 @@ def test_patch_gradients_match_whole_layer():
         for s in range(1, 7):
             pb.set_params(sid, s, alpha=rng.uniform(0, 1, pb.total_d), beta=rng.uniform(0, 0.5, pb.total_d))
             got[mask].append(pb.bound_grad(sid, s))
-    for s, (x, y) in enumerate(zip(got[NO_FUSED], got[NO_FUSED | NO_PATCH])):
-        assert len(x[0]) == len(y[0]) > 0, f"set {s + 1} rows"
-        for t, name in enumerate(("lb", "g_alpha", "g_beta")):
-            xa, ya = np.asarray(x[t], np.float64), np.asarray(y[t], np.float64)
-            scale = max(1.0, np.abs(ya).max())
-            assert np.abs(xa - ya).max() <= 2e-5 * scale, f"set {s + 1} {name}: {np.abs(xa - ya).max():.3e}"
+    for mask in (NO_FUSED, NO_FUSED | NO_CONE):
+        for s, (x, y) in enumerate(zip(got[mask], got[NO_FUSED | NO_PATCH])):
+            assert len(x[0]) == len(y[0]) > 0, f"set {s + 1} rows"
+            for t, name in enumerate(("lb", "g_alpha", "g_beta")):
+                xa, ya = np.asarray(x[t], np.float64), np.asarray(y[t], np.float64)
+                scale = max(1.0, np.abs(ya).max())
+                err = np.abs(xa - ya).max()
+                assert err <= 2e-5 * scale, f"mask {mask} set {s + 1} {name}: {err:.3e}"
 
 
 def test_patch_batch_invariance():
