@@ -162,6 +162,7 @@ int initial_variants() {
     if (getenv("MNB_NO_FUSED_BOTTOM")) m |= MNB_VAR_NO_FUSED_BOTTOM;
     if (getenv("MNB_NO_PATCH")) m |= MNB_VAR_NO_PATCH;
     if (getenv("MNB_NO_CONE")) m |= MNB_VAR_NO_CONE;
+    if (getenv("MNB_NO_FIRST_CONV")) m |= MNB_VAR_NO_FIRST_CONV;
     return m;
 }
 std::atomic<int> g_variants{initial_variants()};

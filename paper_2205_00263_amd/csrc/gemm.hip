@@ -448,6 +448,7 @@ void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, boo
                          hipStream_t st) {
     if (M <= 0) return;
     if (launch_conv_backsub_rows(g, A, C, M, accumulate, st)) return;
+    if (launch_convT_first(g, A, C, M, accumulate, st)) return;
     if (launch_convT_small(g, A, C, M, accumulate, st)) return;
     if (g.Ci < 16) {
         long total = (long)M * g.Ci * g.Hi * g.Wi;
@@ -476,6 +477,7 @@ void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, boo
                          hipStream_t st) {
     if (M <= 0) return;
     if (launch_conv_forward_rows(g, G, C, M, accumulate, st)) return;
+    if (launch_conv_first(g, G, C, M, accumulate, st)) return;
     ConvFwd p;
     p.A = G; p.C = C; p.W = g.Wf; p.bias = g.b; p.ktab = g.fwd_ktab;
     p.Ci = g.Ci; p.kw = g.k; p.HiWi = g.Hi * g.Wi;

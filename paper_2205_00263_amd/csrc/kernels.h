@@ -39,6 +39,10 @@ bool launch_conv_backsub_rows(const ConvGeom& g, const float* A, float* C, int M
                               hipStream_t st);
 bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
                               hipStream_t st);
+// VALU forms for convolutions of stride 1 out of (forward) or into (transposed) at most 4
+// channels with 3x3 filters; false (nothing launched) for other shapes.
+bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st);
+bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st);
 
 // ---- forward products (adjoint and upper-bound evaluation) ----
 // C[M, dout] = G[M, din] * W^T + b  (accumulate: C += ..., bias added either way)

@@ -175,40 +175,49 @@ void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs,
 // The relaxation step of the adjoint (g = D ghat + b, with the parameter-gradient sums of every
 // instance, as k_relu_relax) for rows held as deviations from their instance's shared row: Gd
 // holds each row's forward deviation on its cone, apw its a' deviation on its window.  One
-// thread per (instance, channel, position) of a frame that holds every cone; it walks the
+// thread per (instance, CG channels, position) of a frame that holds every cone; it walks the
 // instance's rows in order (their cone and window origins staged in LDS, 256 at a time), takes
-// the rows whose cone holds its position and writes their new deviation (0 outside the node);
-// every other row equals the shared row there, whose terms enter the sums once per such row.
+// the rows whose cone holds its position and, for each of its channels, writes their new
+// deviation (0 outside the node); every other row equals the shared row there, whose terms
+// enter the sums once per such row.  Each sum therefore runs over the instance's own rows in a
+// fixed order.
+template <int CG>
 __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, PatchGeom gc, const RowDesc* rows,
                                                     const float* ush, const float* ghs, const float* apw, float* Gd,
                                                     int y_lo, int x_lo, int FH, int FW) {
     const int li = blockIdx.y;
     const InstDesc in = a.inst[li];
     const int t = blockIdx.x * 256 + threadIdx.x;
-    const bool act = t < gc.C * FH * FW;
+    const int ngrp = gc.C / CG;
+    const bool act = t < ngrp * FH * FW;
     const int tt = act ? t : 0;
-    const int c = tt / (FH * FW);
-    const int rem = tt - c * FH * FW;
+    const int c0 = (tt / (FH * FW)) * CG;
+    const int rem = tt - (c0 / CG) * FH * FW;
     const int Y = y_lo + rem / FW, X = x_lo + rem % FW;
     const bool inside = act && Y >= 0 && Y < gc.H && X >= 0 && X < gc.W;
-    const int n = inside ? (c * gc.H + Y) * gc.W + X : 0;
-    NeuronRelax nr{0.f, 0.f, 0.f, false};
-    float U = 0.f, Gh = 0.f, Gs = 0.f;
-    int s = 0;
-    if (inside) {
-        const long so = (long)in.slot * a.ld_state + n;
-        const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
-        s = (int)a.S[so];
-        nr = neuron_relax(a.l[so], a.u[so], s, a.alpha[po]);
-        U = ush[(long)li * a.d + n];
-        Gh = ghs[(long)li * a.d + n];
-        Gs = (U < 0.f ? nr.dneg : nr.dpos) * Gh + (U < 0.f ? nr.bneg : 0.f);
+    const int HW = gc.H * gc.W;
+    const int n0 = inside ? (c0 * gc.H + Y) * gc.W + X : 0;
+    NeuronRelax nr[CG];
+    float U[CG], Gh[CG], Gs[CG], da[CG], sh[CG], sg[CG];
+    bool un[CG];
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        nr[q] = NeuronRelax{0.f, 0.f, 0.f, false};
+        U[q] = Gh[q] = Gs[q] = da[q] = sh[q] = sg[q] = 0.f;
+        if (inside) {
+            const int n = n0 + q * HW;
+            const long so = (long)in.slot * a.ld_state + n;
+            const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
+            nr[q] = neuron_relax(a.l[so], a.u[so], (int)a.S[so], a.alpha[po]);
+            U[q] = ush[(long)li * a.d + n];
+            Gh[q] = ghs[(long)li * a.d + n];
+        }
+        un[q] = U[q] < 0.f;
+        Gs[q] = (un[q] ? nr[q].dneg : nr[q].dpos) * Gh[q] + (un[q] ? nr[q].bneg : 0.f);
     }
-    const bool un = U < 0.f;
     const int Pc = gc.P, Pw = gw.P;
     const int cw = gc.C * Pc * Pc, ww = gw.C * Pw * Pw;
-    const long coff = (long)c * Pc * Pc, woff = (long)c * Pw * Pw;
-    float da = 0.f, sh = 0.f, sg = 0.f;
+    const long coff = (long)c0 * Pc * Pc, woff = (long)c0 * Pw * Pw;
     int cnt = 0;
     __shared__ int4 org[256];
     for (int r0 = in.r0; r0 < in.r1; r0 += 256) {
@@ -225,36 +234,51 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
             const int4 o = org[k];
             const int dy = Y - o.x, dx = X - o.y;
             if ((unsigned)dy >= (unsigned)Pc || (unsigned)dx >= (unsigned)Pc) continue;
-            const long e = (long)(r0 + k) * cw + coff + dy * Pc + dx;
+            float* ge = Gd + (long)(r0 + k) * cw + coff + dy * Pc + dx;
             if (!inside) {
-                Gd[e] = 0.f;
+#pragma unroll
+                for (int q = 0; q < CG; ++q) ge[q * Pc * Pc] = 0.f;
                 continue;
             }
-            const float dgh = Gd[e];
-            const float gh = Gh + dgh;
             const int wy = Y - o.z, wx = X - o.w;
-            const float dv = ((unsigned)wy < (unsigned)Pw && (unsigned)wx < (unsigned)Pw)
-                                 ? apw[(long)(r0 + k) * ww + woff + wy * Pw + wx] : 0.f;
-            const float ap = U + dv;
-            const bool neg = ap < 0.f;
-            const float g = (neg ? nr.dneg : nr.dpos) * gh + (neg ? nr.bneg : 0.f);
-            Gd[e] = neg == un ? (neg ? nr.dneg : nr.dpos) * dgh : g - Gs;
-            if (nr.unstable && !neg) da += ap * gh;
-            sh += gh;
-            sg += g;
+            const bool inw = (unsigned)wy < (unsigned)Pw && (unsigned)wx < (unsigned)Pw;
+            const float* we = apw + (long)(r0 + k) * ww + woff + (inw ? wy * Pw + wx : 0);
+            float dgh[CG], dv[CG];
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+                dgh[q] = ge[q * Pc * Pc];
+                dv[q] = inw ? we[q * Pw * Pw] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+                const float gh = Gh[q] + dgh[q];
+                const float ap = U[q] + dv[q];
+                const bool neg = ap < 0.f;
+                const float D = neg ? nr[q].dneg : nr[q].dpos;
+                const float g = D * gh + (neg ? nr[q].bneg : 0.f);
+                ge[q * Pc * Pc] = neg == un[q] ? D * dgh[q] : g - Gs[q];
+                if (nr[q].unstable && !neg) da[q] += ap * gh;
+                sh[q] += gh;
+                sg[q] += g;
+            }
             ++cnt;
         }
     }
     if (!inside) return;
     const float rest = (float)(in.r1 - in.r0 - cnt);
-    if (nr.unstable && !un) da += rest * (U * Gh);
-    sh += rest * Gh;
-    sg += rest * Gs;
-    const long go = (long)li * a.ldg + a.goff + n;
-    a.d_alpha[go] = da;
-    a.d_beta[go] = (float)s * sh;
-    if (a.gsum_hat) a.gsum_hat[(long)li * a.d + n] = sh;
-    if (a.gsum_out) a.gsum_out[(long)li * a.d + n] = sg;
+#pragma unroll
+    for (int q = 0; q < CG; ++q) {
+        const int n = n0 + q * HW;
+        if (nr[q].unstable && !un[q]) da[q] += rest * (U[q] * Gh[q]);
+        sh[q] += rest * Gh[q];
+        sg[q] += rest * Gs[q];
+        const long go = (long)li * a.ldg + a.goff + n;
+        a.d_alpha[go] = da[q];
+        const long so = (long)in.slot * a.ld_state + n;
+        a.d_beta[go] = (float)a.S[so] * sh[q];
+        if (a.gsum_hat) a.gsum_hat[(long)li * a.d + n] = sh[q];
+        if (a.gsum_out) a.gsum_out[(long)li * a.d + n] = sg[q];
+    }
 }
 
 void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
@@ -266,8 +290,15 @@ void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom&
     const int y_hi = std::max((Hobj - 1) * gc.S - gc.Q + gc.P, gc.H);
     const int x_hi = std::max((gc.Wobj - 1) * gc.S - gc.Q + gc.P, gc.W);
     const int FH = y_hi - y_lo, FW = x_hi - x_lo;
-    dim3 grid(cdiv((long)gc.C * FH * FW, 256), a.n_inst);
-    hipLaunchKernelGGL(k_relax_cone, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo, FH, FW);
+    if (gc.C % 8 == 0) {
+        dim3 grid(cdiv((long)(gc.C / 8) * FH * FW, 256), a.n_inst);
+        hipLaunchKernelGGL(k_relax_cone<8>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
+                           FH, FW);
+    } else {
+        dim3 grid(cdiv((long)gc.C * FH * FW, 256), a.n_inst);
+        hipLaunchKernelGGL(k_relax_cone<1>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
+                           FH, FW);
+    }
     MNB_HIP(hipGetLastError());
 }
 

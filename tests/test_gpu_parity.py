@@ -42,6 +42,9 @@ CONV_GEOMS = [  # (Ci, H, Co, k, s, p)
     (3, 32, 32, 3, 1, 1), (32, 32, 32, 4, 2, 1), (32, 16, 64, 3, 1, 1), (64, 16, 64, 4, 2, 1),  # ConvBig
     (16, 16, 32, 3, 2, 1), (32, 8, 32, 3, 1, 1), (16, 16, 32, 1, 2, 0), (3, 32, 16, 3, 2, 1),   # ResNet6
     (5, 7, 17, 3, 2, 1), (20, 9, 24, 4, 2, 1), (18, 6, 40, 2, 1, 0),                        # ragged
+    # first layers of receptive-field windows (padding 0) and forward cones (padding 2)
+    (3, 16, 32, 3, 1, 0), (3, 16, 32, 3, 1, 2), (3, 10, 32, 3, 1, 2), (3, 6, 32, 3, 1, 0),
+    (1, 12, 8, 3, 1, 1), (4, 7, 24, 3, 1, 1), (2, 40, 8, 3, 1, 1),
 ]
 
 
