@@ -18,19 +18,24 @@ namespace mnb {
 constexpr int FT = 256;     // threads per workgroup
 constexpr int FCO = 8;      // transposed: layer output channels staged per step
 
-// Output tile of one row: TW x TH positions with TH TW <= FT; RB rows per workgroup.
+// Output tile of one row: TW x TH positions, each thread two horizontally adjacent ones
+// (TW even, TW / 2 * TH <= FT); RB rows per workgroup.
 struct FirstTile {
     int TW, TH, RB, tiles_x, tiles_y;
 };
 static FirstTile first_tile(int H, int W) {
     FirstTile t;
-    t.TW = W < 32 ? W : 32;
-    t.TH = std::min(H, FT / t.TW);
-    t.RB = std::max(1, FT / (t.TW * t.TH));
+    t.TW = std::min(32, (W + 1) & ~1);
+    t.TH = std::min(H, 2 * FT / t.TW);
+    t.RB = std::max(1, FT / (t.TW / 2 * t.TH));
     t.tiles_x = cdiv(W, t.TW);
     t.tiles_y = cdiv(H, t.TH);
     return t;
 }
+
+// i / d for 0 <= i < 2^16, 0 < d <= 2^10 through a float reciprocal: (i + 0.5) / d lies at least
+// 0.5 / d from an integer, far above the rounding of the product.
+__device__ __forceinline__ int fdivs(int i, float rd) { return (int)(((float)i + 0.5f) * rd); }
 
 // out[r][ci][Y][X] (+)= sum_{co, ky, kx} A[r][co][Y + p - ky][X + p - kx] W[co][ci][ky][kx]
 // (A positions outside [0, Ho) x [0, Wo) are absent).
@@ -39,26 +44,30 @@ __global__ __launch_bounds__(FT) void k_convT_first(const float* __restrict__ A,
                                                     const float* __restrict__ W, int M, int Hi, int Wi, int Co,
                                                     int Ho, int Wo, int p, int acc, FirstTile t) {
     extern __shared__ float sm[];
-    const int WY = t.TH + K - 1, WX = t.TW + K - 1, win = WY * WX;
-    const int rb = threadIdx.x / (t.TW * t.TH), pix = threadIdx.x - rb * (t.TW * t.TH);
+    const int WY = t.TH + K - 1, WX = t.TW + K, win = WY * WX;   // one spare column: the pair's 4th read
+    const int per = t.TW / 2 * t.TH;
+    const int rb = threadIdx.x / per, pix = threadIdx.x - rb * per;
     const int tile = blockIdx.x % (t.tiles_x * t.tiles_y);
     const long r = (long)(blockIdx.x / (t.tiles_x * t.tiles_y)) * t.RB + rb;
     const int ty0 = (tile / t.tiles_x) * t.TH, tx0 = (tile % t.tiles_x) * t.TW;
-    const int Y = ty0 + pix / t.TW, X = tx0 + pix % t.TW;
-    const bool act = rb < t.RB && r < M && pix < t.TW * t.TH;
+    const int dy0 = pix / (t.TW / 2), dx0 = 2 * (pix % (t.TW / 2));
+    const int Y = ty0 + dy0, X = tx0 + dx0;
+    const bool act = rb < t.RB && r < M;
     // window origin on the layer output: y = Y + p - ky for ky = K-1 .. 0
     const int y0 = ty0 + p - (K - 1), x0 = tx0 + p - (K - 1);
     float* s_a = sm + (rb < t.RB ? rb : 0) * FCO * win;
     const float* Ar = A + (act ? r : 0) * (long)Co * Ho * Wo;
     const int HoWo = Ho * Wo;
-    float out[CI];
+    const float rWX = 1.f / (float)WX, rWY = 1.f / (float)WY;
+    float o0[CI], o1[CI];
 #pragma unroll
-    for (int c = 0; c < CI; ++c) out[c] = 0.f;
+    for (int c = 0; c < CI; ++c) o0[c] = o1[c] = 0.f;
     for (int c0 = 0; c0 < Co; c0 += FCO) {
         __syncthreads();   // the previous channels' window is consumed
         if (rb < t.RB) {
-            for (int i = pix; i < FCO * win; i += t.TW * t.TH) {
-                const int co = i / win, rem = i - co * win, wy = rem / WX, wx = rem - wy * WX;
+            for (int i = pix; i < FCO * win; i += per) {
+                const int wr = fdivs(i, rWX), wx = i - wr * WX;
+                const int co = fdivs(wr, rWY), wy = wr - co * WY;
                 const int y = y0 + wy, x = x0 + wx;
                 float v = 0.f;
                 if (r < M && c0 + co < Co && y >= 0 && y < Ho && x >= 0 && x < Wo)
@@ -68,26 +77,35 @@ __global__ __launch_bounds__(FT) void k_convT_first(const float* __restrict__ A,
         }
         __syncthreads();
         const int nco = Co - c0 < FCO ? Co - c0 : FCO;
-        const float* ap = s_a + (Y - ty0) * WX + (X - tx0);
+        const float* ap = s_a + dy0 * WX + dx0;
+#pragma unroll 2
         for (int co = 0; co < nco; ++co) {
             const float* wrow = W + (long)(c0 + co) * CI * K * K;
 #pragma unroll
-            for (int ky = 0; ky < K; ++ky)
+            for (int ky = 0; ky < K; ++ky) {
+                // A[y][x] with y = Y + p - ky sits at window row (K - 1 - ky) + dy0; the pair's
+                // columns for taps kx are (K - 1 - kx) + dx0 + {0, 1}
+                float a[K + 1];
 #pragma unroll
-                for (int kx = 0; kx < K; ++kx) {
-                    // A[y][x] with y = Y + p - ky sits at window row (K - 1 - ky) + (Y - ty0)
-                    const float av = ap[co * win + (K - 1 - ky) * WX + (K - 1 - kx)];
+                for (int q = 0; q <= K; ++q) a[q] = ap[co * win + (K - 1 - ky) * WX + q];
 #pragma unroll
-                    for (int c = 0; c < CI; ++c) out[c] += av * wrow[(c * K + ky) * K + kx];
-                }
+                for (int kx = 0; kx < K; ++kx)
+#pragma unroll
+                    for (int c = 0; c < CI; ++c) {
+                        const float w = wrow[(c * K + ky) * K + kx];
+                        o0[c] += a[K - 1 - kx] * w;
+                        o1[c] += a[K - kx] * w;
+                    }
+            }
         }
     }
-    if (!act || Y >= Hi || X >= Wi) return;
+    if (!act || Y >= Hi) return;
     float* Cr = C + r * (long)CI * Hi * Wi + (long)Y * Wi + X;
 #pragma unroll
     for (int c = 0; c < CI; ++c) {
         float* q = Cr + (long)c * Hi * Wi;
-        *q = acc ? *q + out[c] : out[c];
+        if (X < Wi) q[0] = acc ? q[0] + o0[c] : o0[c];
+        if (X + 1 < Wi) q[1] = acc ? q[1] + o1[c] : o1[c];
     }
 }
 
@@ -99,19 +117,23 @@ __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, 
                                                    int Hi, int Wi, int Co, int Ho, int Wo, int p, int acc,
                                                    FirstTile t) {
     extern __shared__ float sm[];
-    const int WY = t.TH + K - 1, WX = t.TW + K - 1, win = WY * WX;
-    const int rb = threadIdx.x / (t.TW * t.TH), pix = threadIdx.x - rb * (t.TW * t.TH);
+    const int WY = t.TH + K - 1, WX = t.TW + K, win = WY * WX;
+    const int per = t.TW / 2 * t.TH;
+    const int rb = threadIdx.x / per, pix = threadIdx.x - rb * per;
     const int tile = blockIdx.x % (t.tiles_x * t.tiles_y);
     const long r = (long)(blockIdx.x / (t.tiles_x * t.tiles_y)) * t.RB + rb;
     const int ty0 = (tile / t.tiles_x) * t.TH, tx0 = (tile % t.tiles_x) * t.TW;
-    const int y = ty0 + pix / t.TW, x = tx0 + pix % t.TW;
-    const bool act = rb < t.RB && r < M && pix < t.TW * t.TH;
+    const int dy0 = pix / (t.TW / 2), dx0 = 2 * (pix % (t.TW / 2));
+    const int y = ty0 + dy0, x = tx0 + dx0;
+    const bool act = rb < t.RB && r < M;
     const int Y0 = ty0 - p, X0 = tx0 - p;   // input window origin
     float* s_g = sm + (rb < t.RB ? rb : 0) * CI * win;
     const float* Gr = G + (r < M ? r : 0) * (long)CI * Hi * Wi;
+    const float rWX = 1.f / (float)WX, rWY = 1.f / (float)WY;
     if (rb < t.RB) {
-        for (int i = pix; i < CI * win; i += t.TW * t.TH) {
-            const int ci = i / win, rem = i - ci * win, wy = rem / WX, wx = rem - wy * WX;
+        for (int i = pix; i < CI * win; i += per) {
+            const int wr = fdivs(i, rWX), wx = i - wr * WX;
+            const int ci = fdivs(wr, rWY), wy = wr - ci * WY;
             const int Y = Y0 + wy, X = X0 + wx;
             float v = 0.f;
             if (r < M && Y >= 0 && Y < Hi && X >= 0 && X < Wi) v = Gr[(long)ci * Hi * Wi + Y * Wi + X];
@@ -119,23 +141,35 @@ __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, 
         }
     }
     __syncthreads();
-    if (!act || y >= Ho || x >= Wo) return;
-    float in[CI * K * K];
-    const float* gp = s_g + (y - ty0) * WX + (x - tx0);
+    if (!act || y >= Ho) return;
+    // the pair's inputs: rows dy0 + ky, columns dx0 + 0 .. K
+    float in[CI * K * (K + 1)];
+    const float* gp = s_g + dy0 * WX + dx0;
 #pragma unroll
     for (int ci = 0; ci < CI; ++ci)
 #pragma unroll
         for (int ky = 0; ky < K; ++ky)
 #pragma unroll
-            for (int kx = 0; kx < K; ++kx) in[(ci * K + ky) * K + kx] = gp[ci * win + ky * WX + kx];
+            for (int q = 0; q <= K; ++q) in[(ci * K + ky) * (K + 1) + q] = gp[ci * win + ky * WX + q];
     float* Cr = C + r * (long)Co * Ho * Wo + (long)y * Wo + x;
+    const bool two = x + 1 < Wo;
+#pragma unroll 2
     for (int co = 0; co < Co; ++co) {
         const float* w = W + (long)co * CI * K * K;
-        float s = bias[co];
+        float s0 = bias[co], s1 = s0;
 #pragma unroll
-        for (int q = 0; q < CI * K * K; ++q) s += w[q] * in[q];
+        for (int ci = 0; ci < CI; ++ci)
+#pragma unroll
+            for (int ky = 0; ky < K; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < K; ++kx) {
+                    const float wv = w[(ci * K + ky) * K + kx];
+                    s0 += wv * in[(ci * K + ky) * (K + 1) + kx];
+                    s1 += wv * in[(ci * K + ky) * (K + 1) + kx + 1];
+                }
         float* o = Cr + (long)co * Ho * Wo;
-        *o = acc ? *o + s : s;
+        if (x < Wo) o[0] = acc ? o[0] + s0 : s0;
+        if (two) o[1] = acc ? o[1] + s1 : s1;
     }
 }
 
@@ -143,7 +177,7 @@ bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool
     if (g.s != 1 || g.Ci > 4 || g.k != 3 || (kernel_variants() & MNB_VAR_NO_FIRST_CONV)) return false;
     if (M <= 0) return true;
     const FirstTile t = first_tile(g.Hi, g.Wi);
-    const size_t lds = (size_t)t.RB * FCO * (t.TH + 2) * (t.TW + 2) * sizeof(float);
+    const size_t lds = (size_t)t.RB * FCO * (t.TH + 2) * (t.TW + 3) * sizeof(float);
     const long blocks = (long)cdiv(M, t.RB) * t.tiles_x * t.tiles_y;
     MNB_CHECK(blocks < (1L << 31), MNB_EDEVICE, "first-layer transposed convolution: grid too large");
 #define MNB_CTF(CI_)                                                                                              \
@@ -164,7 +198,7 @@ bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool 
     if (g.s != 1 || g.Ci > 4 || g.k != 3 || (kernel_variants() & MNB_VAR_NO_FIRST_CONV)) return false;
     if (M <= 0) return true;
     const FirstTile t = first_tile(g.Ho, g.Wo);
-    const size_t lds = (size_t)t.RB * g.Ci * (t.TH + 2) * (t.TW + 2) * sizeof(float);
+    const size_t lds = (size_t)t.RB * g.Ci * (t.TH + 2) * (t.TW + 3) * sizeof(float);
     const long blocks = (long)cdiv(M, t.RB) * t.tiles_x * t.tiles_y;
     MNB_CHECK(blocks < (1L << 31), MNB_EDEVICE, "first-layer convolution: grid too large");
 #define MNB_CF1(CI_)                                                                                              \

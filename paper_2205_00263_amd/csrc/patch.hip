@@ -230,38 +230,58 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
         __syncthreads();
         const int nrow = min(256, in.r1 - r0);
         if (!act) continue;
-        for (int k = 0; k < nrow; ++k) {
-            const int4 o = org[k];
-            const int dy = Y - o.x, dx = X - o.y;
-            if ((unsigned)dy >= (unsigned)Pc || (unsigned)dx >= (unsigned)Pc) continue;
-            float* ge = Gd + (long)(r0 + k) * cw + coff + dy * Pc + dx;
+        // RU rows at a time: the covered rows' loads of a group are in flight together
+        constexpr int RU = 4;
+        for (int k0 = 0; k0 < nrow; k0 += RU) {
+            bool cov[RU], inw[RU];
+            float* ge[RU];
+            const float* we[RU];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int k = k0 + u < nrow ? k0 + u : nrow - 1;
+                const int4 o = org[k];
+                const int dy = Y - o.x, dx = X - o.y, wy = Y - o.z, wx = X - o.w;
+                cov[u] = k0 + u < nrow && (unsigned)dy < (unsigned)Pc && (unsigned)dx < (unsigned)Pc;
+                inw[u] = (unsigned)wy < (unsigned)Pw && (unsigned)wx < (unsigned)Pw;
+                ge[u] = Gd + (long)(r0 + k) * cw + coff + (cov[u] ? dy * Pc + dx : 0);
+                we[u] = apw + (long)(r0 + k) * ww + woff + (inw[u] ? wy * Pw + wx : 0);
+                any |= cov[u];
+            }
+            if (!any) continue;
             if (!inside) {
 #pragma unroll
-                for (int q = 0; q < CG; ++q) ge[q * Pc * Pc] = 0.f;
+                for (int u = 0; u < RU; ++u)
+                    if (cov[u])
+#pragma unroll
+                        for (int q = 0; q < CG; ++q) ge[u][q * Pc * Pc] = 0.f;
                 continue;
             }
-            const int wy = Y - o.z, wx = X - o.w;
-            const bool inw = (unsigned)wy < (unsigned)Pw && (unsigned)wx < (unsigned)Pw;
-            const float* we = apw + (long)(r0 + k) * ww + woff + (inw ? wy * Pw + wx : 0);
-            float dgh[CG], dv[CG];
+            float dgh[RU][CG], dv[RU][CG];
 #pragma unroll
-            for (int q = 0; q < CG; ++q) {
-                dgh[q] = ge[q * Pc * Pc];
-                dv[q] = inw ? we[q * Pw * Pw] : 0.f;
-            }
+            for (int u = 0; u < RU; ++u)
 #pragma unroll
-            for (int q = 0; q < CG; ++q) {
-                const float gh = Gh[q] + dgh[q];
-                const float ap = U[q] + dv[q];
-                const bool neg = ap < 0.f;
-                const float D = neg ? nr[q].dneg : nr[q].dpos;
-                const float g = D * gh + (neg ? nr[q].bneg : 0.f);
-                ge[q * Pc * Pc] = neg == un[q] ? D * dgh[q] : g - Gs[q];
-                if (nr[q].unstable && !neg) da[q] += ap * gh;
-                sh[q] += gh;
-                sg[q] += g;
+                for (int q = 0; q < CG; ++q) {
+                    dgh[u][q] = cov[u] ? ge[u][q * Pc * Pc] : 0.f;
+                    dv[u][q] = (cov[u] && inw[u]) ? we[u][q * Pw * Pw] : 0.f;
+                }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!cov[u]) continue;
+#pragma unroll
+                for (int q = 0; q < CG; ++q) {
+                    const float gh = Gh[q] + dgh[u][q];
+                    const float ap = U[q] + dv[u][q];
+                    const bool neg = ap < 0.f;
+                    const float D = neg ? nr[q].dneg : nr[q].dpos;
+                    const float g = D * gh + (neg ? nr[q].bneg : 0.f);
+                    ge[u][q * Pc * Pc] = neg == un[q] ? D * dgh[u][q] : g - Gs[q];
+                    if (nr[q].unstable && !neg) da[q] += ap * gh;
+                    sh[q] += gh;
+                    sg[q] += g;
+                }
+                ++cnt;
             }
-            ++cnt;
         }
     }
     if (!inside) return;
@@ -290,9 +310,9 @@ void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom&
     const int y_hi = std::max((Hobj - 1) * gc.S - gc.Q + gc.P, gc.H);
     const int x_hi = std::max((gc.Wobj - 1) * gc.S - gc.Q + gc.P, gc.W);
     const int FH = y_hi - y_lo, FW = x_hi - x_lo;
-    if (gc.C % 8 == 0) {
-        dim3 grid(cdiv((long)(gc.C / 8) * FH * FW, 256), a.n_inst);
-        hipLaunchKernelGGL(k_relax_cone<8>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
+    if (gc.C % 4 == 0) {
+        dim3 grid(cdiv((long)(gc.C / 4) * FH * FW, 256), a.n_inst);
+        hipLaunchKernelGGL(k_relax_cone<4>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
                            FH, FW);
     } else {
         dim3 grid(cdiv((long)gc.C * FH * FW, 256), a.n_inst);
