@@ -44,26 +44,34 @@ sys.path.insert(0, ROOT)
 SPLIT_SEED_CS = 3002   # ConvSmall split sets
 SPLIT_SEED_CB = 3003   # ConvBig split sets
 MNC_CAP = 500          # multi-neuron constraints per ReLU layer (ConvBig)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bottom_convsmall_traffic.json")
-# sources that fix the fused kernel and the rows each of its launches gets
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_00263_amd", "csrc", f)
-               for f in ("bottom_mf.hip", "bottom.hip", "bottom.h", "common.h", "engine.hip")]
+# counter runs (FETCH_SIZE / WRITE_SIZE) of the roofline kernel of each workload, and the sources that
+# fix that kernel and the rows each of its launches gets
+TRAFFIC = {
+    ("convsmall", "bottom", None): ("bottom_convsmall_traffic.json",
+               ("bottom_mf.hip", "bottom.hip", "bottom.h", "common.h", "engine.hip")),
+    ("convbig", "conv_forward", 3): ("conv2_forward_convbig_traffic.json",
+                     ("gemm.hip", "kernels.h", "common.h", "engine.hip", "engine_calls.inc", "patch.hip")),
+}
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(files):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
-        h.update(open(f, "rb").read())
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2205_00263_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(workload, kernel, node=None):
     """HBM bytes per launch from the committed counter runs, or None if absent or the kernel changed since."""
-    if kernel != "bottom" or not os.path.exists(TRAFFIC_FILE):
+    if (workload, kernel, node) not in TRAFFIC:
         return None
-    d = json.load(open(TRAFFIC_FILE))
-    return d.get("bytes_per_launch") if d.get("kernel_source_sha256") == kernel_sources_sha256() else None
+    name, files = TRAFFIC[(workload, kernel, node)]
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    return d.get("bytes_per_launch") if d.get("kernel_source_sha256") == kernel_sources_sha256(files) else None
 
 
 def make_batch(P, pb, rid, splits):
@@ -564,7 +572,7 @@ def convsmall_batch(args):
     kstats = timer.stop()
     n_bounded = args.batch * args.steps
     value = n_bounded / el
-    roof = roofline_of(kstats, measured_traffic(args.roofline_kernel))
+    roof = roofline_of(kstats, measured_traffic("convsmall", args.roofline_kernel))
     out = {
         "metric": "BaB subproblems bounded/sec (alpha,beta-optimised, 20 Adam steps) + p50/p99 batch latency",
         "value": round(value, 2), "unit": "subproblems/s", "n_gpus": 1, "steps": args.steps,
@@ -696,8 +704,10 @@ def convbig_batch(args):
     import workloads as W
 
     B = args.batch or 1024
-    kind = args.roofline_kernel or "conv_backsub"
-    node = args.roofline_node
+    # the dominant kernel: the forward convolution of the adjoint at ConvBig's second convolution
+    # (every launch of that class runs the 128 x 32 gather GEMM)
+    kind = args.roofline_kernel or "conv_forward"
+    node = args.roofline_node if args.roofline_node is not None else 3
     T = args.adam_steps
 
     def log(msg):
@@ -779,7 +789,7 @@ def convbig_batch(args):
                    "step_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)},
         "bound_summary": {"root_lb_min": float(root_lb.min()), "root_ub_min": float(root_ub.min()),
                           "batch_lb_mean": float(lb.min(1).mean())},
-        "roofline": roofline_of(kstats),
+        "roofline": roofline_of(kstats, measured_traffic("convbig", kind, node)),
     }
     if args.stream_queries > 0:
         log(f"query stream: {args.stream_queries} queries")

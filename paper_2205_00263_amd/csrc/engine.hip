@@ -907,9 +907,11 @@ struct PassCtx {
     const float* fold_W = nullptr;
     const float* fold_b = nullptr;
     const RowDesc* fold_rows = nullptr;
-    // receptive-field rows: a' deviation windows per relu node [M, window] and the shared rows'
-    // a' per relu node [n_inst, d]
-    std::map<int, float*> apw, ush;
+    // receptive-field rows: a' deviation windows per relu node [M, window]; the shared rows'
+    // relaxation table per relu node [n_inst, d] (read by the deviation folds, or written by the
+    // folds of the shared rows)
+    std::map<int, float*> apw;
+    std::map<int, float4*> rt_in, rt_out;
 };
 
 static int fold_cols(int d) { return cdiv(d, 256) * 4; }
@@ -1019,8 +1021,9 @@ static void walk_backsub(PassCtx& cx, const PassChunk& ch, BufPool& pool, std::m
                 }
                 {
                     TimerScope ts(MNB_T_FOLD, n, 0.0, (double)M * node_width(net, ch, n) * (store_ap ? 12 : 8));
+                    fa.rt_out = cx.rt_out.count(n) ? cx.rt_out[n] : nullptr;
                     if (ch.pp) {
-                        fa.ush = cx.ush.at(n);
+                        fa.rt_in = cx.rt_in.at(n);
                         launch_relu_fold_patch(fa, ch.pp->g[n], ch.rows, ch.inst_base, st);
                     } else
                         launch_relu_fold(fa, st, cx.gp.count(m) ? cx.gp[m] : nullptr);
@@ -1285,8 +1288,9 @@ static size_t chunk_bytes(const mnb_net* net, int top, long M, int n_inst, bool 
             if (i <= top) b += (size_t)M * net->nodes[i].size * 4;   // a'
     b += (size_t)n_inst * net->total_d * 4 * 4;         // gradients / sums
     if (pp) {
-        // shared rows (one per instance, whole layers) and the deviation windows of a'
-        b += (size_t)n_inst * (3 * (size_t)net->max_width + net->total_d + net->d0 + pass_cols(net, top) + 2) * 4;
+        // shared rows (one per instance, whole layers, with their relaxation tables and forward
+        // values) and the deviation windows of a'
+        b += (size_t)n_inst * (3 * (size_t)net->max_width + 7 * (size_t)net->total_d + net->d0 + pass_cols(net, top) + 2) * 4;
         if (adjoint)
             for (int i : net->relus)
                 if (i <= top) b += (size_t)M * pp->width(i) * 4;
@@ -1332,6 +1336,7 @@ struct Evaluator {
     // coefficients U0, their x* and bound.
     struct SharedRows {
         std::map<int, float*> ap;
+        std::map<int, float4*> rt;    // relaxation table per ReLU node
         std::map<int, float*> ghat;   // forward values at each ReLU's input (cone adjoint)
         float* U0 = nullptr;
         float* x0 = nullptr;
@@ -1381,13 +1386,17 @@ struct Evaluator {
         cs.vh = rcx.vh;
         cs.gp = rcx.gp;
         for (int i : net->relus)
-            if (i <= top) cs.ap[i] = ws.get<float>("sh_ap" + std::to_string(i), (size_t)n * net->nodes[i].size);
+            if (i <= top) {
+                cs.ap[i] = ws.get<float>("sh_ap" + std::to_string(i), (size_t)n * net->nodes[i].size);
+                cs.rt_out[i] = ws.get<float4>("sh_rt" + std::to_string(i), (size_t)n * net->nodes[i].size);
+            }
         for (int i = 0; i < 3; ++i) {
             sh.pool.bufs.push_back(ws.get<float>("sh_pool" + std::to_string(i), (size_t)n * net->max_width));
             sh.pool.ref.push_back(0);
         }
         sh.U0 = run_backsub(cs, sc, sh.pool, true);
         sh.ap = cs.ap;
+        sh.rt = cs.rt_out;
         sh.x0 = ws.get<float>("sh_x0", (size_t)n * net->d0);
         sh.lb = ws.get<float>("sh_lb", n);
         ConcArgs ca{};
@@ -1412,7 +1421,11 @@ struct Evaluator {
             const NetNode& nd = net->nodes[m];
             if (nd.kind == MNB_CONV) {
                 float* out = ws.get<float>("sh_f" + std::to_string(m), (size_t)n * nd.size);
-                launch_conv_forward(nd.geom, gp, out, n, false, st);
+                {
+                    TimerScope ts(MNB_T_CONV_FORWARD, m, 2.0 * n * nd.macs_per_row,
+                                  4.0 * n * (nd.size + net->nodes[nd.src].size));
+                    launch_conv_forward(nd.geom, gp, out, n, false, st);
+                }
                 gp = out;
             } else if (nd.kind == MNB_RELU) {
                 const int r = nd.relu_m;
@@ -1521,7 +1534,7 @@ struct Evaluator {
         SharedRows sh;
         if (ch.pp) {
             shared_rows(ch, cx, sh);
-            cx.ush = sh.ap;
+            cx.rt_in = sh.rt;
             if (adjoint && ch.cone) shared_forward(ch, sh);
         }
         const int r0n = net->relus[0];

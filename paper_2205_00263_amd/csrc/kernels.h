@@ -109,9 +109,11 @@ struct FoldArgs {
     // a = sign W[j] is read from Wsrc instead of A, and c[r] = sign bias_obj[j] is written
     // (nullable: a is read from A)
     const float* Wsrc; const RowDesc* rows; float* c; const float* bias_obj;
-    // receptive-field rows: a' of each instance's shared row [n_inst, d] (A holds windows of the
-    // deviation from it)
-    const float* ush;
+    // receptive-field rows: per instance and neuron {D(a' >= 0), D(a' < 0), b-underline, a'} of the
+    // instance's shared row [n_inst, d] (A holds windows of the deviation from it); rt_out
+    // (nullable) receives that table from a fold of the shared rows (one row per instance)
+    const float4* rt_in;
+    float4* rt_out;
 };
 void launch_relu_fold(const FoldArgs& a, hipStream_t st);
 

@@ -79,24 +79,23 @@ __global__ __launch_bounds__(256) void k_relu_fold_patch(FoldArgs a, PatchGeom g
     const int Y = oy + q / g.P, X = ox + q % g.P;
     const bool inside = ok && Y >= 0 && Y < g.H && X >= 0 && X < g.W;
     const int n = inside ? (c * g.H + Y) * g.W + X : 0;
-    const long so = (long)in.slot * a.ld_state + n;
-    const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
+    (void)in;
     float contrib = 0.f;
     const long idx = (long)r * width + e;
     const float dv = ok ? a.A[idx] : 0.f;
     if (inside) {
-        const NeuronRelax nr = neuron_relax(a.l[so], a.u[so], (int)a.S[so], a.alpha[po]);
-        const float U = a.ush[(long)li * a.d + n];
+        const float4 t = a.rt_in[(long)li * a.d + n];   // {D(a' >= 0), D(a' < 0), b, U'}
+        const float U = t.w;
         const float ap = U + dv;
         const bool neg = ap < 0.f, uneg = U < 0.f;
         float dh, dc;
         if (neg == uneg) {
-            const float D = neg ? nr.dneg : nr.dpos;
+            const float D = neg ? t.y : t.x;
             dh = dv * D;
-            dc = neg ? dv * nr.bneg : 0.f;
+            dc = neg ? dv * t.z : 0.f;
         } else {
-            dh = ap * (neg ? nr.dneg : nr.dpos) - U * (uneg ? nr.dneg : nr.dpos);
-            dc = (neg ? ap * nr.bneg : 0.f) - (uneg ? U * nr.bneg : 0.f);
+            dh = ap * (neg ? t.y : t.x) - U * (uneg ? t.y : t.x);
+            dc = (neg ? ap * t.z : 0.f) - (uneg ? U * t.z : 0.f);
         }
         a.A[idx] = dh;
         if (a.Ap) a.Ap[idx] = dv;

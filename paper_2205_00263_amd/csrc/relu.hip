@@ -81,6 +81,7 @@ __global__ __launch_bounds__(256) void k_relu_fold(FoldArgs a, const float* gp) 
                 const float ah = ap * D + add;
                 a.A[e] = ah;
                 if (a.Ap) a.Ap[e] = ap;
+                if (a.rt_out) a.rt_out[(long)blockIdx.y * a.d + j] = make_float4(nr.dpos, nr.dneg, nr.bneg, ap);
                 contrib = (neg ? ap * nr.bneg : 0.f) + ah * bias;
             }
             contrib -= gpv;
