@@ -220,6 +220,19 @@ static void fill_conv_geom(mnb_net* net, ConvGeom& g, int Ci, int Hi, int Wi, in
             }
     g.fwd_ktab = upload(ft.data(), ft.size(), &net->owned);
     g.Wf = upload(wf.data(), wf.size(), &net->owned);
+    g.Wg = nullptr;
+    if (g.Ci % 16 == 0) {
+        // the forward GEMM's K order: 16-channel groups outermost, so that the taps reading one
+        // group's input region follow each other
+        std::vector<float> wg(wf.size());
+        for (int co = 0; co < g.Co; ++co)
+            for (int cg = 0; cg < g.Ci / 16; ++cg)
+                for (int t = 0; t < k * k; ++t)
+                    for (int c = 0; c < 16; ++c)
+                        wg[(size_t)co * g.Ci * k * k + ((size_t)cg * k * k + t) * 16 + c] =
+                            wf[(size_t)co * g.Ci * k * k + (size_t)t * g.Ci + cg * 16 + c];
+        g.Wg = upload(wg.data(), wg.size(), &net->owned);
+    }
     // stride phases of the transposed convolution
     MNB_CHECK(s * s <= 16, MNB_EINVAL, "conv stride above 4 is not supported");
     g.n_phase = 0;
@@ -251,6 +264,18 @@ static void fill_conv_geom(mnb_net* net, ConvGeom& g, int Ci, int Hi, int Wi, in
                         }
                 ph.Wp = upload(wp.data(), wp.size(), &net->owned);
                 ph.ktab = upload(kt.data(), kt.size(), &net->owned);
+                ph.Wpg = nullptr;
+                if (g.Co % 16 == 0) {
+                    // the transposed GEMM's K order: 16-channel groups outermost
+                    std::vector<float> wg(wp.size());
+                    for (int cg = 0; cg < g.Co / 16; ++cg)
+                        for (int tt = 0; tt < T; ++tt)
+                            for (int c = 0; c < 16; ++c)
+                                for (int ci = 0; ci < g.Ci; ++ci)
+                                    wg[(((size_t)cg * T + tt) * 16 + c) * g.Ci + ci] =
+                                        wp[((size_t)tt * g.Co + cg * 16 + c) * g.Ci + ci];
+                    ph.Wpg = upload(wg.data(), wg.size(), &net->owned);
+                }
             }
             g.ph[g.n_phase++] = ph;
         }

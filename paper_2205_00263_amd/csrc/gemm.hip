@@ -92,13 +92,15 @@ struct ConvBack {
         return A[c.base + t.x];
     }
     __device__ float b(int k, int n) const { return (k < K && n < N) ? Wp[(long)k * N + n] : 0.f; }
-    // A elements k0 + ks[i] of one K-tile that lies within a single tap (Co % 16 == 0)
-    int tile_ok, Co, Tx, HoWo;
+    // A elements k0 + ks[i] of one K-tile that lies within a single tap (Co % 16 == 0); K ordered
+    // (co / 16, ty, tx, co % 16): the k-tiles of one 16-channel group are its taps in a row
+    int tile_ok, Co, Tx, Ty, HoWo;
     template <int NA>
     __device__ void a_tile(const MCtx& c, int k0, const int* ks, float* out) const {
-        const int tap = k0 / Co;
+        const int kt = k0 >> 4;
+        const int cg = kt / (Ty * Tx), tap = kt - cg * Ty * Tx;
         const int ty = tap / Tx, tx = tap - ty * Tx;
-        const int co0 = k0 - tap * Co;
+        const int co0 = cg * 16 + (k0 & 15);   // k0 carries the thread's first k within the tile
         const int y = c.yb - ty, x = c.xb - tx;
         const bool ok = c.ok && k0 < K && (unsigned)y < (unsigned)Ho && (unsigned)x < (unsigned)Wo;
         const float* src = A + (c.base + (long)co0 * HoWo - ty * Wo - tx);
@@ -143,13 +145,15 @@ struct ConvFwd {
         return A[c.base + t.x];
     }
     __device__ float b(int k, int n) const { return (k < K && n < N) ? W[(long)n * K + k] : 0.f; }
-    // A elements of one K-tile within a single tap (Ci % 16 == 0)
+    // A elements of one K-tile within a single tap (Ci % 16 == 0); K ordered (ci / 16, ky, kx,
+    // ci % 16): the k-tiles of one 16-channel group are its taps, one after the other
     int tile_ok, Ci, kw, HiWi;
     template <int NA>
     __device__ void a_tile(const MCtx& c, int k0, const int* ks, float* out) const {
-        const int tap = k0 / Ci;
+        const int kt = k0 >> 4;
+        const int cg = kt / (kw * kw), tap = kt - cg * kw * kw;
         const int ky = tap / kw, kx = tap - ky * kw;
-        const int ci0 = k0 - tap * Ci;
+        const int ci0 = cg * 16 + (k0 & 15);   // k0 carries the thread's first k within the tile
         const int y = c.iy + ky, x = c.ix + kx;
         const bool ok = c.ok && k0 < K && (unsigned)y < (unsigned)Hi && (unsigned)x < (unsigned)Wi;
         const float* src = A + (c.base + (long)ci0 * HiWi + ky * Wi + kx);
@@ -461,14 +465,15 @@ void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, boo
         const ConvPhase& ph = g.ph[f];
         if (ph.nY <= 0 || ph.nX <= 0) continue;
         ConvBack p;
-        p.A = A; p.C = C; p.Wp = ph.Wp; p.ktab = ph.ktab;
+        p.A = A; p.C = C; p.ktab = ph.ktab;
         p.M = M * ph.nY * ph.nX; p.N = g.Ci; p.K = g.Co * ph.Ty * ph.Tx;
         p.nY = ph.nY; p.nX = ph.nX; p.Ho = g.Ho; p.Wo = g.Wo;
         p.ldA = g.Co * g.Ho * g.Wo; p.ldC = g.Ci * g.Hi * g.Wi; p.HiWi = g.Hi * g.Wi; p.Wi = g.Wi;
         p.Y0 = ph.Y0; p.X0 = ph.X0; p.s = g.s; p.q0y = ph.q0y; p.q0x = ph.q0x;
         p.acc = accumulate;
-        p.Co = g.Co; p.Tx = ph.Tx; p.HoWo = g.Ho * g.Wo;
-        p.tile_ok = (g.Co % BK) == 0;
+        p.Co = g.Co; p.Tx = ph.Tx; p.Ty = ph.Ty; p.HoWo = g.Ho * g.Wo;
+        p.tile_ok = (g.Co % BK) == 0 && ph.Wpg != nullptr;
+        p.Wp = p.tile_ok ? ph.Wpg : ph.Wp;
         run_gemm(p, st);
     }
 }
@@ -479,9 +484,10 @@ void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, boo
     if (launch_conv_forward_rows(g, G, C, M, accumulate, st)) return;
     if (launch_conv_first(g, G, C, M, accumulate, st)) return;
     ConvFwd p;
-    p.A = G; p.C = C; p.W = g.Wf; p.bias = g.b; p.ktab = g.fwd_ktab;
+    p.A = G; p.C = C; p.bias = g.b; p.ktab = g.fwd_ktab;
     p.Ci = g.Ci; p.kw = g.k; p.HiWi = g.Hi * g.Wi;
-    p.tile_ok = (g.Ci % BK) == 0;
+    p.tile_ok = (g.Ci % BK) == 0 && g.Wg != nullptr;
+    p.W = p.tile_ok ? g.Wg : g.Wf;
     p.M = M * g.Ho * g.Wo; p.N = g.Co; p.K = g.Ci * g.k * g.k;
     p.Ho = g.Ho; p.Wo = g.Wo; p.Hi = g.Hi; p.Wi = g.Wi;
     p.ldA = g.Ci * g.Hi * g.Wi; p.ldC = g.Co * g.Ho * g.Wo; p.s = g.s; p.p = g.p;

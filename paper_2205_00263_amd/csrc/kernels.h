@@ -13,6 +13,7 @@ struct ConvPhase {
     int Ty, Tx;         // taps of the phase
     int q0y, q0x;       // (Y0 + pad - rho)/stride
     const float* Wp;    // [Ty][Tx][Co][Ci] weights of the phase
+    const float* Wpg;   // the same with K ordered (co / 16, ty, tx, co % 16) (Co % 16 == 0)
     const int2* ktab;   // [Ty*Tx*Co] {co*Ho*Wo - ty*Wo - tx, (ty<<16)|tx}
 };
 
@@ -22,6 +23,7 @@ struct ConvGeom {
     const float* b;     // [Co]
     const int2* fwd_ktab;  // [k*k*Ci] {ci*Hi*Wi + ky*Wi + kx, (ky<<16)|kx}, K ordered (ky, kx, ci)
     const float* Wf;       // [Co][k*k*Ci] weights in that K order
+    const float* Wg;       // [Co][k*k*Ci] weights with K ordered (ci / 16, ky, kx, ci % 16) (Ci % 16 == 0)
     int n_phase;
     ConvPhase ph[16];   // stride <= 4
 };
