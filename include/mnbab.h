@@ -380,15 +380,18 @@ int mnb_timer_end(int64_t* launches, double* ms, double* flops, double* bytes);
  *                            of forward cones
  *   MNB_VAR_NO_FIRST_CONV    first-layer convolutions (stride 1, at most 4 input
  *                            channels) through the general kernels
+ *   MNB_VAR_NO_WIN_CONV      forward convolutions through the gather GEMM instead of
+ *                            the input-window kernel
  * The initial mask comes from the environment variables MNB_BOTTOM_VALU,
  * MNB_NO_TAP_CONVT, MNB_NO_PAIR_CONV, MNB_NO_ROW_CONV, MNB_NO_WIN_BOTTOM,
- * MNB_NO_FUSED_BOTTOM, MNB_NO_PATCH, MNB_NO_CONE and MNB_NO_FIRST_CONV (set: bit on).  The
+ * MNB_NO_FUSED_BOTTOM, MNB_NO_PATCH, MNB_NO_CONE, MNB_NO_FIRST_CONV and
+ * MNB_NO_WIN_CONV (set: bit on).  The
  * receptive-field bits are read when a pass is planned (bound_init,
  * bound_optimize, bound_optimize_begin).  mnb_set_kernel_variants returns the
  * previous mask; neither call fails. */
 enum { MNB_VAR_VALU_BOTTOM = 1, MNB_VAR_NO_TAP_CONVT = 2, MNB_VAR_NO_PAIR_CONV = 4, MNB_VAR_NO_ROW_CONV = 8,
        MNB_VAR_NO_WINDOW = 16, MNB_VAR_NO_FUSED_BOTTOM = 32, MNB_VAR_NO_PATCH = 64, MNB_VAR_NO_CONE = 128,
-       MNB_VAR_NO_FIRST_CONV = 256 };
+       MNB_VAR_NO_FIRST_CONV = 256, MNB_VAR_NO_WIN_CONV = 512 };
 int mnb_set_kernel_variants(int mask);
 int mnb_get_kernel_variants(void);
 

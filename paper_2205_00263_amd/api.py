@@ -171,7 +171,7 @@ class Net:
 # kernel variants (mnb_set_kernel_variants): bits forcing the more general kernel of a step
 VARIANTS = {"valu_bottom": 1, "no_tap_convt": 2, "no_pair_conv": 4, "no_row_conv": 8, "no_window": 16,
             "no_fused_bottom": 32, "no_patch": 64, "no_cone": 128,
-            "no_first_conv": 256}
+            "no_first_conv": 256, "no_win_conv": 512}
 
 
 def set_kernel_variants(mask):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmnbab.so")
-SOURCES = ["hull.cpp", "gemm.hip", "relu.hip", "bottom.hip", "bottom_mf.hip", "bottom_win.hip", "conv_rows.hip", "conv_first.hip", "patch.hip", "engine.hip", "serve.hip"]
+SOURCES = ["hull.cpp", "gemm.hip", "relu.hip", "bottom.hip", "bottom_mf.hip", "bottom_win.hip", "conv_rows.hip", "conv_first.hip", "conv_win.hip", "patch.hip", "engine.hip", "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -163,6 +163,7 @@ int initial_variants() {
     if (getenv("MNB_NO_PATCH")) m |= MNB_VAR_NO_PATCH;
     if (getenv("MNB_NO_CONE")) m |= MNB_VAR_NO_CONE;
     if (getenv("MNB_NO_FIRST_CONV")) m |= MNB_VAR_NO_FIRST_CONV;
+    if (getenv("MNB_NO_WIN_CONV")) m |= MNB_VAR_NO_WIN_CONV;
     return m;
 }
 std::atomic<int> g_variants{initial_variants()};
@@ -233,6 +234,19 @@ static void fill_conv_geom(mnb_net* net, ConvGeom& g, int Ci, int Hi, int Wi, in
                             wf[(size_t)co * g.Ci * k * k + (size_t)t * g.Ci + cg * 16 + c];
         g.Wg = upload(wg.data(), wg.size(), &net->owned);
     }
+    g.Wt = nullptr;
+    if (g.Ci % 8 == 0) {
+        // the input-window kernel stages 8 input channels at a time: per group, per tap, per
+        // channel a row of Co filter weights
+        std::vector<float> wt(wf.size());
+        for (int cg = 0; cg < g.Ci / 8; ++cg)
+            for (int t = 0; t < k * k; ++t)
+                for (int c = 0; c < 8; ++c)
+                    for (int co = 0; co < g.Co; ++co)
+                        wt[(((size_t)cg * k * k + t) * 8 + c) * g.Co + co] =
+                            Wh[((size_t)co * g.Ci + cg * 8 + c) * k * k + t];
+        g.Wt = upload(wt.data(), wt.size(), &net->owned);
+    }
     // stride phases of the transposed convolution
     MNB_CHECK(s * s <= 16, MNB_EINVAL, "conv stride above 4 is not supported");
     g.n_phase = 0;
@@ -275,6 +289,22 @@ static void fill_conv_geom(mnb_net* net, ConvGeom& g, int Ci, int Hi, int Wi, in
                                     wg[(((size_t)cg * T + tt) * 16 + c) * g.Ci + ci] =
                                         wp[((size_t)tt * g.Co + cg * 16 + c) * g.Ci + ci];
                     ph.Wpg = upload(wg.data(), wg.size(), &net->owned);
+                }
+                ph.Wt = nullptr;
+                if (g.Co % 8 == 0) {
+                    // the phase as a stride-1 correlation for the input-window kernel: tap
+                    // (Ty-1-ty, Tx-1-tx) reads coefficient (q0y + i - ty, q0x + j - tx)
+                    std::vector<float> wt(wp.size());
+                    for (int cg = 0; cg < g.Co / 8; ++cg)
+                        for (int ty = 0; ty < ph.Ty; ++ty)
+                            for (int tx = 0; tx < ph.Tx; ++tx)
+                                for (int c = 0; c < 8; ++c)
+                                    for (int ci = 0; ci < g.Ci; ++ci) {
+                                        const int t = (ph.Ty - 1 - ty) * ph.Tx + (ph.Tx - 1 - tx);
+                                        wt[(((size_t)cg * T + t) * 8 + c) * g.Ci + ci] =
+                                            wp[((size_t)(ty * ph.Tx + tx) * g.Co + cg * 8 + c) * g.Ci + ci];
+                                    }
+                    ph.Wt = upload(wt.data(), wt.size(), &net->owned);
                 }
             }
             g.ph[g.n_phase++] = ph;

@@ -461,6 +461,7 @@ void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, boo
         MNB_HIP(hipGetLastError());
         return;
     }
+    if (launch_conv_backsub_win(g, A, C, M, accumulate, st)) return;
     for (int f = 0; f < g.n_phase; ++f) {
         const ConvPhase& ph = g.ph[f];
         if (ph.nY <= 0 || ph.nX <= 0) continue;
@@ -483,6 +484,7 @@ void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, boo
     if (M <= 0) return;
     if (launch_conv_forward_rows(g, G, C, M, accumulate, st)) return;
     if (launch_conv_first(g, G, C, M, accumulate, st)) return;
+    if (launch_conv_forward_win(g, G, C, M, accumulate, st)) return;
     ConvFwd p;
     p.A = G; p.C = C; p.bias = g.b; p.ktab = g.fwd_ktab;
     p.Ci = g.Ci; p.kw = g.k; p.HiWi = g.Hi * g.Wi;

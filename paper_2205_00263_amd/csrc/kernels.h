@@ -15,6 +15,7 @@ struct ConvPhase {
     const float* Wp;    // [Ty][Tx][Co][Ci] weights of the phase
     const float* Wpg;   // the same with K ordered (co / 16, ty, tx, co % 16) (Co % 16 == 0)
     const int2* ktab;   // [Ty*Tx*Co] {co*Ho*Wo - ty*Wo - tx, (ty<<16)|tx}
+    const float* Wt;    // [Co/8][Ty*Tx][8][Ci] flipped taps for the input-window kernel (Co % 8 == 0)
 };
 
 struct ConvGeom {
@@ -24,6 +25,7 @@ struct ConvGeom {
     const int2* fwd_ktab;  // [k*k*Ci] {ci*Hi*Wi + ky*Wi + kx, (ky<<16)|kx}, K ordered (ky, kx, ci)
     const float* Wf;       // [Co][k*k*Ci] weights in that K order
     const float* Wg;       // [Co][k*k*Ci] weights with K ordered (ci / 16, ky, kx, ci % 16) (Ci % 16 == 0)
+    const float* Wt;       // [Ci/8][k*k][8][Co] weights of the input-window kernel (Ci % 8 == 0)
     int n_phase;
     ConvPhase ph[16];   // stride <= 4
 };
@@ -45,6 +47,13 @@ bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M
 // channels with 3x3 filters; false (nothing launched) for other shapes.
 bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st);
 bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st);
+// Forward convolution from input windows staged in LDS (8 input channels at a time, Co % 32 == 0,
+// 3x3 / 1, 3x3 / 2 or 4x4 / 2 filters); false (nothing launched) for other shapes.
+bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st);
+// Transposed convolution by the same kernel, one stride phase at a time (each phase is a stride-1
+// correlation of the coefficient grid with the phase's flipped taps; square phases of 2x2 or 3x3
+// taps, Co % 8 == 0, Ci % 32 == 0); false (nothing launched) for other shapes.
+bool launch_conv_backsub_win(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st);
 
 // ---- forward products (adjoint and upper-bound evaluation) ----
 // C[M, dout] = G[M, din] * W^T + b  (accumulate: C += ..., bias added either way)

@@ -87,6 +87,73 @@ def test_conv_kernels_match_oracle(geom):
         np.testing.assert_allclose(o_d.cpu().numpy(), reff, rtol=0, atol=1e-5 * np.abs(reff).max() + 1e-5)
 
 
+WIN_GEOMS = [  # (Ci, H, Co, k, s, p): input-window kernels, whole tiles and ragged ones
+    (32, 32, 32, 4, 2, 1), (32, 16, 64, 3, 1, 1), (64, 16, 64, 4, 2, 1),     # ConvBig, float4 staging
+    (32, 18, 32, 4, 2, 2), (32, 10, 64, 3, 1, 2),                           # its forward cones
+    (16, 13, 32, 4, 2, 0), (8, 20, 96, 3, 1, 1), (8, 24, 128, 3, 1, 0),      # ragged tiles, channel tiles
+    (16, 12, 32, 4, 2, 3), (16, 16, 32, 3, 2, 1),
+    (64, 32, 32, 4, 2, 1), (32, 40, 64, 4, 2, 1), (32, 16, 32, 3, 1, 1),     # transposed: 2x2 and 3x3 phases
+]
+
+
+@pytest.mark.parametrize("geom", WIN_GEOMS)
+def test_window_conv_matches_oracle(geom):
+    """Forward and transposed convolutions through the input-window kernels (the default where they
+    apply) against the FP64 convolution and its adjoint (the transposed one also accumulating),
+    bitwise the same for a row alone and inside a batch (the lone row also sits at an address that
+    is not 16-byte aligned for most shapes, so it is staged element by element), and equal to FP32
+    rounding to the gather GEMMs (MNB_VAR_NO_WIN_CONV)."""
+    P = _P()
+    ci, h, co, k, s, p = geom
+    rng = np.random.default_rng(hash(geom) % 2**32)
+    ho = (h + 2 * p - k) // s + 1
+    nodes = [{"kind": "input", "shape": (ci, h, h)},
+             {"kind": "conv", "src": 0, "W": rng.normal(size=(co, ci, k, k)).astype(np.float32),
+              "b": rng.normal(size=co).astype(np.float32), "stride": s, "pad": p},
+             {"kind": "relu", "src": 1},
+             {"kind": "fc", "src": 2, "W": np.ones((2, co * ho * ho), np.float32), "b": np.zeros(2, np.float32)}]
+    prev = P.get_kernel_variants()
+    try:
+        P.set_kernel_variants(prev & ~P.VARIANTS["no_win_conv"])
+        net = P.Net(nodes)
+        onet_ = onet.Net(nodes)
+        din, dout = onet_.sizes[0], onet_.sizes[1]
+        M = 203
+        G = rng.normal(size=(M, din)).astype(np.float32)
+        ref = onet.conv_apply(onet_.nodes[1]["W"], G.astype(np.float64), onet_.shapes[0], onet_.shapes[1], s, p) \
+            + onet.bias_vector(onet_, 1)
+        A = rng.normal(size=(M, dout)).astype(np.float32)
+        refb = onet.conv_adjoint(onet_.nodes[1]["W"], A.astype(np.float64), onet_.shapes[0], onet_.shapes[1], s, p)
+        g_d, o_d = _dev(G), torch.zeros((M, dout), device="cuda")
+        a_d, c_d = _dev(A), torch.full((M, din), 7.0, device="cuda")
+        torch.cuda.synchronize()
+        net.conv_forward(1, g_d.data_ptr(), o_d.data_ptr(), M)
+        net.conv_backsub(1, a_d.data_ptr(), c_d.data_ptr(), M)
+        net.sync()
+        out, outb = o_d.cpu().numpy(), c_d.cpu().numpy()
+        tol, tolb = 1e-5 * np.abs(ref).max() + 1e-5, 1e-5 * np.abs(refb).max() + 1e-5
+        np.testing.assert_allclose(out, ref, rtol=0, atol=tol)
+        np.testing.assert_allclose(outb, refb, rtol=0, atol=tolb)
+        net.conv_backsub(1, a_d.data_ptr(), c_d.data_ptr(), M, accumulate=True)
+        net.sync()
+        np.testing.assert_allclose(c_d.cpu().numpy(), 2 * refb, rtol=0, atol=2 * tolb)
+        one, oneb = torch.zeros((1, dout), device="cuda"), torch.zeros((1, din), device="cuda")
+        net.conv_forward(1, g_d[117:118].data_ptr(), one.data_ptr(), 1)
+        net.conv_backsub(1, a_d[117:118].data_ptr(), oneb.data_ptr(), 1)
+        net.sync()
+        assert np.array_equal(one.cpu().numpy()[0], out[117])
+        assert np.array_equal(oneb.cpu().numpy()[0], outb[117])
+        P.set_kernel_variants(prev | P.VARIANTS["no_win_conv"])
+        o2, c2 = torch.zeros((M, dout), device="cuda"), torch.zeros((M, din), device="cuda")
+        net.conv_forward(1, g_d.data_ptr(), o2.data_ptr(), M)
+        net.conv_backsub(1, a_d.data_ptr(), c2.data_ptr(), M)
+        net.sync()
+        np.testing.assert_allclose(o2.cpu().numpy(), out, rtol=0, atol=tol)
+        np.testing.assert_allclose(c2.cpu().numpy(), outb, rtol=0, atol=tolb)
+    finally:
+        P.set_kernel_variants(prev)
+
+
 @pytest.mark.parametrize("dims", [(1, 10, 100), (37, 100, 784), (576, 100, 100), (300, 512, 4096), (129, 33, 65),
                                   (64, 7, 3)])
 def test_fc_kernels_match_numpy(dims):
