@@ -245,9 +245,14 @@ void launch_relu_fold_patch(const FoldArgs& a, const PatchGeom& g, const RowDesc
                             hipStream_t st);
 // shared rows' forward relaxation gs = D(U') ghs + b(U') per (instance, neuron)
 void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs, float* gs, hipStream_t st);
-// adjoint relaxation of rows held as cone deviations Gd (in place) with their a' deviation windows
+// adjoint relaxation of rows held as cone deviations Gd (in place) with their a' deviation windows;
+// an instance's rows run in slices of kConeRows (slice z of instance i at zoff[i] + z, at most nz_max
+// per instance) whose gradient sums go to part [zoff[n_inst]][3][d] and are then added up in slice
+// order, so every sum has an order fixed by the instance alone
+constexpr int kConeRows = 64;
 void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
-                       const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st);
+                       const float* ush, const float* ghs, const float* apw, float* Gd, const int* zoff,
+                       int nz_max, float* part, hipStream_t st);
 // dense rows out[r] = shared[instance of r] + (window entries of win[r], nullable)
 void launch_patch_expand(const float* shared, const float* win, const RowDesc* rows, int M, int inst_base,
                          const PatchGeom& g, float* out, hipStream_t st);
