@@ -337,8 +337,10 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     return true;
 }
 
-// Input planes of at most this many elements stay in the caches between the gather GEMM's re-reads,
-// and that kernel is faster there (measured on ConvBig's 10x10 forward cones).
+// Forward convolutions of input planes of at most this many elements stay with the gather GEMM: the
+// plane stays in the caches between its re-reads, and the window kernel's filter staging weighs
+// more on the few positions of a tile (measured on ConvBig's 10x10 -> 12x12 forward cones).  The
+// transposed convolutions gain from the window kernel at every plane size measured (8x8 and up).
 constexpr int WIN_MIN_PLANE = 129;
 
 }  // namespace
@@ -355,7 +357,7 @@ bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M,
 }
 
 bool launch_conv_backsub_win(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st) {
-    if ((kernel_variants() & MNB_VAR_NO_WIN_CONV) != 0 || g.Ho * g.Wo < WIN_MIN_PLANE) return false;
+    if ((kernel_variants() & MNB_VAR_NO_WIN_CONV) != 0) return false;
     // every phase must be covered before any is launched
     WinConv ws[16];
     int n = 0;

@@ -907,7 +907,7 @@ struct PassChunk {
     RowDesc* sh_rows_d = nullptr;
     InstDesc* sh_inst_d = nullptr;
     bool zero_rows = false;           // rows are the zero objective (a chunk of shared rows)
-    // cone adjoint: instance i's rows run in kConeRows-row slices, slice z of it writing partial
+    // cone adjoint: instance i's rows run in kRowSlice-row slices, slice z of it writing partial
     // gradient sums at slot zoff[i] + z (nz_max slices at most per instance, nz_total in all)
     int* zoff_d = nullptr;
     int nz_total = 0, nz_max = 0;
@@ -1353,8 +1353,8 @@ static size_t chunk_bytes(const mnb_net* net, int top, long M, int n_inst, bool 
         if (adjoint) {
             for (int i : net->relus)
                 if (i <= top) b += (size_t)M * pp->width(i) * 4;
-            // partial gradient sums of the cone adjoint's row slices
-            b += (size_t)(M / kConeRows + n_inst) * 3 * net->max_width * 4;
+            // partial gradient sums of the cone relaxation's row slices
+            b += (size_t)(M / kRowSlice + n_inst) * 3 * net->max_width * 4;
         }
     }
     return b;
@@ -1541,9 +1541,11 @@ struct Evaluator {
                 ra.gsum_out = pb->has_mnc ? gs_out : nullptr;
                 {
                     TimerScope ts(MNB_T_RELAX, m, 0.0, 8.0 * M * pp.cone_width(m) + 4.0 * M * pp.width(m));
-                    float* part = ws.get<float>("cone_part", (size_t)ch.nz_total * 3 * nd.size);
+                    MNB_CHECK(ch.zoff_d != nullptr, MNB_EDEVICE, "row slices missing");
+                    ra.zoff = ch.zoff_d; ra.n_slices = ch.nz_max;
+                    ra.part = ws.get<float>("relax_part", (size_t)ch.nz_total * 3 * nd.size);
                     launch_relax_cone(ra, pp.g[m], pp.fc[m], ch.rows, sh.ap.at(m), sh.ghat.at(m), cx.apw.at(m), g,
-                                      ch.zoff_d, ch.nz_max, part, st);
+                                      st);
                 }
                 if (pb->has_mnc) {
                     auto& ml = pb->mnc[r];

@@ -139,8 +139,16 @@ struct RelaxArgs {
     // gradient outputs per instance [n_inst, ldg] at column offset goff
     float* d_alpha; float* d_beta; long ldg; long goff;
     float* gsum_hat; float* gsum_out;  // nullable, [n_inst, d] (for gamma)
+    // row slices of the cone relaxation (kRowSlice rows each on the third grid dimension, so that
+    // an instance's rows are spread over many wavefronts): slice z of instance i writes partial sums
+    // at slot zoff[i] + z of part [zoff[n_inst]][3][d], which launch_relax_sum adds in slice order,
+    // so every sum has an order fixed by the instance alone; n_slices: most slices of an instance
+    const int* zoff; int n_slices; float* part;
 };
+constexpr int kRowSlice = 64;
 void launch_relu_relax(const RelaxArgs& a, hipStream_t st);
+// d_alpha, d_beta and the gamma sums from the slices' partial sums in a.part
+void launch_relax_sum(const RelaxArgs& a, hipStream_t st);
 void launch_relu_fold(const FoldArgs& a, hipStream_t st, const float* gp);
 
 struct ConcArgs {
@@ -245,14 +253,10 @@ void launch_relu_fold_patch(const FoldArgs& a, const PatchGeom& g, const RowDesc
                             hipStream_t st);
 // shared rows' forward relaxation gs = D(U') ghs + b(U') per (instance, neuron)
 void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs, float* gs, hipStream_t st);
-// adjoint relaxation of rows held as cone deviations Gd (in place) with their a' deviation windows;
-// an instance's rows run in slices of kConeRows (slice z of instance i at zoff[i] + z, at most nz_max
-// per instance) whose gradient sums go to part [zoff[n_inst]][3][d] and are then added up in slice
-// order, so every sum has an order fixed by the instance alone
-constexpr int kConeRows = 64;
+// adjoint relaxation of rows held as cone deviations Gd (in place) with their a' deviation windows,
+// in row slices (RelaxArgs)
 void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
-                       const float* ush, const float* ghs, const float* apw, float* Gd, const int* zoff,
-                       int nz_max, float* part, hipStream_t st);
+                       const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st);
 // dense rows out[r] = shared[instance of r] + (window entries of win[r], nullable)
 void launch_patch_expand(const float* shared, const float* win, const RowDesc* rows, int M, int inst_base,
                          const PatchGeom& g, float* out, hipStream_t st);

@@ -183,16 +183,15 @@ void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs,
 template <int CG>
 __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, PatchGeom gc, const RowDesc* rows,
                                                     const float* ush, const float* ghs, const float* apw, float* Gd,
-                                                    int y_lo, int x_lo, int FH, int FW, const int* zoff,
-                                                    float* part) {
+                                                    int y_lo, int x_lo, int FH, int FW) {
     const int li = blockIdx.y;
     InstDesc in = a.inst[li];
     // this workgroup's slice of the instance's rows
     const int z = blockIdx.z;
     const int nrows = in.r1 - in.r0;
-    if (z * kConeRows >= nrows) return;
-    in.r0 += z * kConeRows;
-    in.r1 = min(in.r1, in.r0 + kConeRows);
+    if (z * kRowSlice >= nrows) return;
+    in.r0 += z * kRowSlice;
+    in.r1 = min(in.r1, in.r0 + kRowSlice);
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int ngrp = gc.C / CG;
     const bool act = t < ngrp * FH * FW;
@@ -293,7 +292,7 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
     if (!inside) return;
     // rows of the slice whose cone misses this position carry the shared row's terms
     const float rest = (float)(in.r1 - in.r0 - cnt);
-    float* pz = part + (long)(zoff[li] + z) * 3 * a.d;
+    float* pz = a.part + (long)(a.zoff[li] + z) * 3 * a.d;
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
         const int n = n0 + q * HW;
@@ -306,30 +305,8 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
     }
 }
 
-// Gradient sums of the cone adjoint: the slices' partial sums of each (instance, neuron) added in
-// slice order.
-__global__ __launch_bounds__(256) void k_relax_cone_sum(RelaxArgs a, const int* zoff, const float* part) {
-    const int li = blockIdx.y;
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= a.d) return;
-    const InstDesc in = a.inst[li];
-    float da = 0.f, sh = 0.f, sg = 0.f;
-    for (int z = zoff[li]; z < zoff[li + 1]; ++z) {
-        const float* pz = part + (long)z * 3 * a.d;
-        da += pz[n];
-        sh += pz[a.d + n];
-        sg += pz[2 * a.d + n];
-    }
-    const long go = (long)li * a.ldg + a.goff + n;
-    a.d_alpha[go] = da;
-    a.d_beta[go] = (float)a.S[(long)in.slot * a.ld_state + n] * sh;
-    if (a.gsum_hat) a.gsum_hat[(long)li * a.d + n] = sh;
-    if (a.gsum_out) a.gsum_out[(long)li * a.d + n] = sg;
-}
-
 void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
-                       const float* ush, const float* ghs, const float* apw, float* Gd, const int* zoff,
-                       int nz_max, float* part, hipStream_t st) {
+                       const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st) {
     if (a.n_inst <= 0) return;
     // frame: the node plus every cone position any objective position reaches
     const int Hobj = gc.HWobj / gc.Wobj;
@@ -337,20 +314,19 @@ void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom&
     const int y_hi = std::max((Hobj - 1) * gc.S - gc.Q + gc.P, gc.H);
     const int x_hi = std::max((gc.Wobj - 1) * gc.S - gc.Q + gc.P, gc.W);
     const int FH = y_hi - y_lo, FW = x_hi - x_lo;
-    if (nz_max <= 0) {
+    if (a.n_slices <= 0) {
         // no rows: the sums below are zero
     } else if (gc.C % 4 == 0) {
-        dim3 grid(cdiv((long)(gc.C / 4) * FH * FW, 256), a.n_inst, nz_max);
+        dim3 grid(cdiv((long)(gc.C / 4) * FH * FW, 256), a.n_inst, a.n_slices);
         hipLaunchKernelGGL(k_relax_cone<4>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
-                           FH, FW, zoff, part);
+                           FH, FW);
     } else {
-        dim3 grid(cdiv((long)gc.C * FH * FW, 256), a.n_inst, nz_max);
+        dim3 grid(cdiv((long)gc.C * FH * FW, 256), a.n_inst, a.n_slices);
         hipLaunchKernelGGL(k_relax_cone<1>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
-                           FH, FW, zoff, part);
+                           FH, FW);
     }
     MNB_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_relax_cone_sum, dim3(cdiv(a.d, 256), a.n_inst), dim3(256), 0, st, a, zoff, part);
-    MNB_HIP(hipGetLastError());
+    launch_relax_sum(a, st);
 }
 
 }  // namespace mnb

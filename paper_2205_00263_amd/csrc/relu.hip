@@ -141,6 +141,32 @@ __global__ __launch_bounds__(256) void k_relu_relax(RelaxArgs a) {
     if (a.gsum_out) a.gsum_out[(long)blockIdx.y * a.d + j] = sg;
 }
 
+// Gradient sums of a relaxation run in row slices (the cone relaxation): the slices' partial sums
+// of each (instance, neuron) added in slice order.
+__global__ __launch_bounds__(256) void k_relax_sum(RelaxArgs a) {
+    const int li = blockIdx.y;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= a.d) return;
+    const InstDesc in = a.inst[li];
+    float da = 0.f, sh = 0.f, sg = 0.f;
+    for (int z = a.zoff[li]; z < a.zoff[li + 1]; ++z) {
+        const float* pz = a.part + (long)z * 3 * a.d;
+        da += pz[n];
+        sh += pz[a.d + n];
+        sg += pz[2 * a.d + n];
+    }
+    const long go = (long)li * a.ldg + a.goff + n;
+    a.d_alpha[go] = da;
+    a.d_beta[go] = (float)a.S[(long)in.slot * a.ld_state + n] * sh;
+    if (a.gsum_hat) a.gsum_hat[(long)li * a.d + n] = sh;
+    if (a.gsum_out) a.gsum_out[(long)li * a.d + n] = sg;
+}
+
+void launch_relax_sum(const RelaxArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_relax_sum, dim3(cdiv(a.d, 256), a.n_inst), dim3(256), 0, st, a);
+    MNB_HIP(hipGetLastError());
+}
+
 void launch_relu_relax(const RelaxArgs& a, hipStream_t st) {
     if (a.n_inst <= 0) return;
     dim3 grid(cdiv(a.d, 256), a.n_inst);
