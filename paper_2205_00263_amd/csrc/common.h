@@ -44,6 +44,15 @@ __device__ __forceinline__ float dpp_src(float v) {
 // 16-lane row, row shifts by 1, 2, 4 and 8 leave the row total in the row's last lane; row
 // broadcasts of lanes 15 and 31 then combine the four rows in lane 63, which is read back.
 // Every lane of the wavefront must be active.
+// Sums over each 16-lane row of the wavefront, valid in the row's last lane (15, 31, 47, 63).
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_src<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_src<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_src<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_src<0x118, 0xF>(v);   // row_shr:8
+    return v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
     v += dpp_src<0x111, 0xF>(v);   // row_shr:1
     v += dpp_src<0x112, 0xF>(v);   // row_shr:2

@@ -108,12 +108,89 @@ __global__ __launch_bounds__(256) void k_relu_fold_patch(FoldArgs a, PatchGeom g
     if ((threadIdx.x & 63) == 0) a.cpart[(long)r * a.ldcp + a.col_off + eb * 4 + (threadIdx.x >> 6)] = contrib;
 }
 
+// The same fold with four consecutive window entries per lane (windows of a multiple of 4 entries):
+// one wavefront per 256 entries, 16-byte loads and stores, index arithmetic by float reciprocals
+// (exact here: entries and window sides are far below 2^22), and the partial constants still one
+// per 64 entries (the sum over each 16-lane row).
+__global__ __launch_bounds__(256) void k_relu_fold_patch4(FoldArgs a, PatchGeom g, const RowDesc* rows,
+                                                          int inst_base, int nblk, float inv_pp, float inv_p) {
+    const long bid = blockIdx.x;
+    const int r = (int)(bid / nblk), eb = (int)(bid - (long)r * nblk);
+    const int lane = threadIdx.x & 63, chunk = eb * 4 + (threadIdx.x >> 6);
+    const int width = g.C * g.P * g.P;
+    if (chunk * 256 >= width) return;   // wavefront-uniform
+    const RowDesc rd = rows[r];
+    const int li = rd.inst - inst_base;
+    int oy, ox;
+    patch_origin(g, rd.j, oy, ox);
+    const int PP = g.P * g.P;
+    const int e0 = chunk * 256 + 4 * lane;
+    const bool ok = e0 < width;
+    const long idx = (long)r * width + (ok ? e0 : 0);
+    const float4 dv4 = ok ? *reinterpret_cast<const float4*>(a.A + idx) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float dvs[4] = {dv4.x, dv4.y, dv4.z, dv4.w};
+    float dh[4], contrib = 0.f;
+    bool ins[4];
+    int nn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = e0 + k;
+        const int c = (int)(((float)e + 0.5f) * inv_pp);
+        const int q = e - c * PP;
+        const int qy = (int)(((float)q + 0.5f) * inv_p);
+        const int Y = oy + qy, X = ox + q - qy * g.P;
+        ins[k] = ok && Y >= 0 && Y < g.H && X >= 0 && X < g.W;
+        nn[k] = ins[k] ? (c * g.H + Y) * g.W + X : 0;
+    }
+    float4 tt[4];
+    float bb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        tt[k] = a.rt_in[(long)li * a.d + nn[k]];   // {D(a' >= 0), D(a' < 0), b, U'}
+        bb[k] = a.bias[nn[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dh[k] = 0.f;
+        if (!ins[k]) continue;
+        const float4 t = tt[k];
+        const float U = t.w, d = dvs[k];
+        const float ap = U + d;
+        const bool neg = ap < 0.f, uneg = U < 0.f;
+        float dc;
+        if (neg == uneg) {
+            const float D = neg ? t.y : t.x;
+            dh[k] = d * D;
+            dc = neg ? d * t.z : 0.f;
+        } else {
+            dh[k] = ap * (neg ? t.y : t.x) - U * (uneg ? t.y : t.x);
+            dc = (neg ? ap * t.z : 0.f) - (uneg ? U * t.z : 0.f);
+        }
+        contrib += dc + dh[k] * bb[k];
+    }
+    if (ok) {
+        *reinterpret_cast<float4*>(a.A + idx) = make_float4(dh[0], dh[1], dh[2], dh[3]);
+        if (a.Ap)
+            *reinterpret_cast<float4*>(a.Ap + idx) = make_float4(ins[0] ? dvs[0] : 0.f, ins[1] ? dvs[1] : 0.f,
+                                                                 ins[2] ? dvs[2] : 0.f, ins[3] ? dvs[3] : 0.f);
+    }
+    contrib = row16_sum(contrib);
+    if ((lane & 15) == 15) a.cpart[(long)r * a.ldcp + a.col_off + chunk * 4 + (lane >> 4)] = contrib;
+}
+
 void launch_relu_fold_patch(const FoldArgs& a, const PatchGeom& g, const RowDesc* rows, int inst_base,
                             hipStream_t st) {
     if (a.M <= 0) return;
-    const int nblk = cdiv(g.C * g.P * g.P, 256);
-    hipLaunchKernelGGL(k_relu_fold_patch, dim3((unsigned)((long)a.M * nblk)), dim3(256), 0, st, a, g, rows,
-                       inst_base, nblk);
+    const int width = g.C * g.P * g.P;
+    if (width % 4 == 0 && ((uintptr_t)a.A & 15) == 0 && (!a.Ap || ((uintptr_t)a.Ap & 15) == 0)) {
+        const int nblk = cdiv(width, 1024);
+        hipLaunchKernelGGL(k_relu_fold_patch4, dim3((unsigned)((long)a.M * nblk)), dim3(256), 0, st, a, g, rows,
+                           inst_base, nblk, 1.f / (float)(g.P * g.P), 1.f / (float)g.P);
+    } else {
+        const int nblk = cdiv(width, 256);
+        hipLaunchKernelGGL(k_relu_fold_patch, dim3((unsigned)((long)a.M * nblk)), dim3(256), 0, st, a, g, rows,
+                           inst_base, nblk);
+    }
     MNB_HIP(hipGetLastError());
 }
 
