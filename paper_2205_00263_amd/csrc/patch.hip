@@ -251,16 +251,16 @@ void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs,
 // The relaxation step of the adjoint (g = D ghat + b, with the parameter-gradient sums of every
 // instance, as k_relu_relax) for rows held as deviations from their instance's shared row: Gd
 // holds each row's forward deviation on its cone, apw its a' deviation on its window.  One
-// thread per (instance, CG channels, position) of a frame that holds every cone; it walks the
-// instance's rows in order (their cone and window origins staged in LDS, 256 at a time), takes
-// the rows whose cone holds its position and, for each of its channels, writes their new
-// deviation (0 outside the node); every other row equals the shared row there, whose terms
-// enter the sums once per such row.  Each sum therefore runs over the instance's own rows in a
-// fixed order.
+// thread per (instance, CG channels, node position, slice of kRowSlice rows); it walks the
+// slice's rows in order (their cone and window origins staged in LDS), takes the rows whose cone
+// holds its position and, for each of its channels, writes their new deviation; every other row
+// equals the shared row there, whose terms enter the slice's sums once per such row.  A
+// wavefront first tests, with scalar instructions, whether a row's cone reaches the band of node
+// rows its positions lie in, and skips it otherwise.  Cone entries outside the node are left to
+// k_cone_zero.
 template <int CG>
 __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, PatchGeom gc, const RowDesc* rows,
-                                                    const float* ush, const float* ghs, const float* apw, float* Gd,
-                                                    int y_lo, int x_lo, int FH, int FW) {
+                                                    const float* ush, const float* ghs, const float* apw, float* Gd) {
     const int li = blockIdx.y;
     InstDesc in = a.inst[li];
     // this workgroup's slice of the instance's rows
@@ -269,106 +269,111 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
     if (z * kRowSlice >= nrows) return;
     in.r0 += z * kRowSlice;
     in.r1 = min(in.r1, in.r0 + kRowSlice);
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    const int ngrp = gc.C / CG;
-    const bool act = t < ngrp * FH * FW;
-    const int tt = act ? t : 0;
-    const int c0 = (tt / (FH * FW)) * CG;
-    const int rem = tt - (c0 / CG) * FH * FW;
-    const int Y = y_lo + rem / FW, X = x_lo + rem % FW;
-    const bool inside = act && Y >= 0 && Y < gc.H && X >= 0 && X < gc.W;
     const int HW = gc.H * gc.W;
-    const int n0 = inside ? (c0 * gc.H + Y) * gc.W + X : 0;
+    const int ngrp = gc.C / CG;
+    const int total = ngrp * HW;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const bool act = t < total;
+    const int tt = act ? t : 0;
+    const int cg = tt / HW;
+    const int rem = tt - cg * HW;
+    const int c0 = cg * CG;
+    const int Y = rem / gc.W, X = rem - Y * gc.W;
+    const int n0 = (c0 * gc.H + Y) * gc.W + X;
+    // node rows of this wavefront's positions (all rows if it spans two channel groups)
+    const int tw0 = __builtin_amdgcn_readfirstlane(blockIdx.x * 256 + (threadIdx.x & ~63));
+    const int tw1 = min(tw0 + 63, total - 1);
+    const int g0 = tw0 / HW, g1 = tw1 / HW;
+    const int Ya = g0 == g1 ? (tw0 - g0 * HW) / gc.W : 0;
+    const int Yb = g0 == g1 ? (tw1 - g1 * HW) / gc.W : gc.H - 1;
     NeuronRelax nr[CG];
     float U[CG], Gh[CG], Gs[CG], da[CG], sh[CG], sg[CG];
     bool un[CG];
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
-        nr[q] = NeuronRelax{0.f, 0.f, 0.f, false};
-        U[q] = Gh[q] = Gs[q] = da[q] = sh[q] = sg[q] = 0.f;
-        if (inside) {
-            const int n = n0 + q * HW;
-            const long so = (long)in.slot * a.ld_state + n;
-            const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
-            nr[q] = neuron_relax(a.l[so], a.u[so], (int)a.S[so], a.alpha[po]);
-            U[q] = ush[(long)li * a.d + n];
-            Gh[q] = ghs[(long)li * a.d + n];
-        }
+        const int n = n0 + q * HW;
+        const long so = (long)in.slot * a.ld_state + n;
+        const long po = ((long)in.slot * a.n_sets + in.set) * a.ld_param + n;
+        nr[q] = neuron_relax(a.l[so], a.u[so], (int)a.S[so], a.alpha[po]);
+        U[q] = ush[(long)li * a.d + n];
+        Gh[q] = ghs[(long)li * a.d + n];
         un[q] = U[q] < 0.f;
         Gs[q] = (un[q] ? nr[q].dneg : nr[q].dpos) * Gh[q] + (un[q] ? nr[q].bneg : 0.f);
+        da[q] = sh[q] = sg[q] = 0.f;
     }
     const int Pc = gc.P, Pw = gw.P;
     const int cw = gc.C * Pc * Pc, ww = gw.C * Pw * Pw;
     const long coff = (long)c0 * Pc * Pc, woff = (long)c0 * Pw * Pw;
     int cnt = 0;
-    __shared__ int4 org[256];
-    for (int r0 = in.r0; r0 < in.r1; r0 += 256) {
-        __syncthreads();
-        if (r0 + (int)threadIdx.x < in.r1) {
-            const int pos = rows[r0 + threadIdx.x].j % gc.HWobj;
-            const int yo = pos / gc.Wobj, xo = pos - yo * gc.Wobj;
-            org[threadIdx.x] = make_int4(yo * gc.S - gc.Q, xo * gc.S - gc.Q, yo * gw.S - gw.Q, xo * gw.S - gw.Q);
+    __shared__ int4 org[kRowSlice];
+    const int nrow = in.r1 - in.r0;
+    if ((int)threadIdx.x < nrow) {
+        const int pos = rows[in.r0 + threadIdx.x].j % gc.HWobj;
+        const int yo = pos / gc.Wobj, xo = pos - yo * gc.Wobj;
+        org[threadIdx.x] = make_int4(yo * gc.S - gc.Q, xo * gc.S - gc.Q, yo * gw.S - gw.Q, xo * gw.S - gw.Q);
+    }
+    __syncthreads();
+    if (!act) return;
+    // RU rows at a time: the covered rows' loads of a group are in flight together
+    constexpr int RU = 4;
+    for (int k0 = 0; k0 < nrow; k0 += RU) {
+        bool cov[RU], inw[RU], band[RU];
+        float* ge[RU];
+        const float* we[RU];
+        bool anyband = false;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int k = k0 + u < nrow ? k0 + u : nrow - 1;
+            const int oy = __builtin_amdgcn_readfirstlane(org[k].x);
+            band[u] = k0 + u < nrow && oy <= Yb && oy + Pc > Ya;   // wavefront-uniform
+            anyband |= band[u];
         }
-        __syncthreads();
-        const int nrow = min(256, in.r1 - r0);
-        if (!act) continue;
-        // RU rows at a time: the covered rows' loads of a group are in flight together
-        constexpr int RU = 4;
-        for (int k0 = 0; k0 < nrow; k0 += RU) {
-            bool cov[RU], inw[RU];
-            float* ge[RU];
-            const float* we[RU];
-            bool any = false;
+        if (!anyband) continue;
+        bool any = false;
 #pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                const int k = k0 + u < nrow ? k0 + u : nrow - 1;
-                const int4 o = org[k];
-                const int dy = Y - o.x, dx = X - o.y, wy = Y - o.z, wx = X - o.w;
-                cov[u] = k0 + u < nrow && (unsigned)dy < (unsigned)Pc && (unsigned)dx < (unsigned)Pc;
-                inw[u] = (unsigned)wy < (unsigned)Pw && (unsigned)wx < (unsigned)Pw;
-                ge[u] = Gd + (long)(r0 + k) * cw + coff + (cov[u] ? dy * Pc + dx : 0);
-                we[u] = apw + (long)(r0 + k) * ww + woff + (inw[u] ? wy * Pw + wx : 0);
-                any |= cov[u];
+        for (int u = 0; u < RU; ++u) {
+            cov[u] = false;
+            inw[u] = false;
+            ge[u] = Gd;
+            we[u] = apw;
+            if (!band[u]) continue;
+            const int4 o = org[k0 + u];
+            const int dy = Y - o.x, dx = X - o.y, wy = Y - o.z, wx = X - o.w;
+            cov[u] = (unsigned)dy < (unsigned)Pc && (unsigned)dx < (unsigned)Pc;
+            inw[u] = (unsigned)wy < (unsigned)Pw && (unsigned)wx < (unsigned)Pw;
+            ge[u] = Gd + (long)(in.r0 + k0 + u) * cw + coff + (cov[u] ? dy * Pc + dx : 0);
+            we[u] = apw + (long)(in.r0 + k0 + u) * ww + woff + (inw[u] ? wy * Pw + wx : 0);
+            any |= cov[u];
+        }
+        if (!any) continue;
+        float dgh[RU][CG], dv[RU][CG];
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int q = 0; q < CG; ++q) {
+                dgh[u][q] = cov[u] ? ge[u][q * Pc * Pc] : 0.f;
+                dv[u][q] = (cov[u] && inw[u]) ? we[u][q * Pw * Pw] : 0.f;
             }
-            if (!any) continue;
-            if (!inside) {
 #pragma unroll
-                for (int u = 0; u < RU; ++u)
-                    if (cov[u])
+        for (int u = 0; u < RU; ++u) {
+            if (!cov[u]) continue;
 #pragma unroll
-                        for (int q = 0; q < CG; ++q) ge[u][q * Pc * Pc] = 0.f;
-                continue;
+            for (int q = 0; q < CG; ++q) {
+                const float gh = Gh[q] + dgh[u][q];
+                const float ap = U[q] + dv[u][q];
+                const bool neg = ap < 0.f;
+                const float D = neg ? nr[q].dneg : nr[q].dpos;
+                const float g = D * gh + (neg ? nr[q].bneg : 0.f);
+                ge[u][q * Pc * Pc] = neg == un[q] ? D * dgh[u][q] : g - Gs[q];
+                if (nr[q].unstable && !neg) da[q] += ap * gh;
+                sh[q] += gh;
+                sg[q] += g;
             }
-            float dgh[RU][CG], dv[RU][CG];
-#pragma unroll
-            for (int u = 0; u < RU; ++u)
-#pragma unroll
-                for (int q = 0; q < CG; ++q) {
-                    dgh[u][q] = cov[u] ? ge[u][q * Pc * Pc] : 0.f;
-                    dv[u][q] = (cov[u] && inw[u]) ? we[u][q * Pw * Pw] : 0.f;
-                }
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                if (!cov[u]) continue;
-#pragma unroll
-                for (int q = 0; q < CG; ++q) {
-                    const float gh = Gh[q] + dgh[u][q];
-                    const float ap = U[q] + dv[u][q];
-                    const bool neg = ap < 0.f;
-                    const float D = neg ? nr[q].dneg : nr[q].dpos;
-                    const float g = D * gh + (neg ? nr[q].bneg : 0.f);
-                    ge[u][q * Pc * Pc] = neg == un[q] ? D * dgh[u][q] : g - Gs[q];
-                    if (nr[q].unstable && !neg) da[q] += ap * gh;
-                    sh[q] += gh;
-                    sg[q] += g;
-                }
-                ++cnt;
-            }
+            ++cnt;
         }
     }
-    if (!inside) return;
     // rows of the slice whose cone misses this position carry the shared row's terms
-    const float rest = (float)(in.r1 - in.r0 - cnt);
+    const float rest = (float)(nrow - cnt);
     float* pz = a.part + (long)(a.zoff[li] + z) * 3 * a.d;
 #pragma unroll
     for (int q = 0; q < CG; ++q) {
@@ -382,25 +387,45 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
     }
 }
 
+// Cone entries outside the node hold 0 (the next convolution reads them as padding): one thread per
+// (row, channel, cone row), writing the entries of its cone row that fall outside the node.
+__global__ __launch_bounds__(256) void k_cone_zero(PatchGeom gc, const RowDesc* rows, int M, float* Gd) {
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    const int Pc = gc.P;
+    const long per = (long)gc.C * Pc;
+    if (t >= (long)M * per) return;
+    const int r = (int)(t / per);
+    const int rem = (int)(t - (long)r * per);
+    const int c = rem / Pc, dy = rem - c * Pc;
+    int oy, ox;
+    patch_origin(gc, rows[r].j, oy, ox);
+    float* p = Gd + (long)r * gc.C * Pc * Pc + ((long)c * Pc + dy) * Pc;
+    const int Y = oy + dy;
+    if (Y < 0 || Y >= gc.H) {
+        for (int dx = 0; dx < Pc; ++dx) p[dx] = 0.f;
+    } else {
+        for (int dx = 0; dx < -ox && dx < Pc; ++dx) p[dx] = 0.f;
+        for (int dx = max(0, gc.W - ox); dx < Pc; ++dx) p[dx] = 0.f;
+    }
+}
+
 void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
                        const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st) {
     if (a.n_inst <= 0) return;
-    // frame: the node plus every cone position any objective position reaches
-    const int Hobj = gc.HWobj / gc.Wobj;
-    const int y_lo = std::min(-gc.Q, 0), x_lo = std::min(-gc.Q, 0);
-    const int y_hi = std::max((Hobj - 1) * gc.S - gc.Q + gc.P, gc.H);
-    const int x_hi = std::max((gc.Wobj - 1) * gc.S - gc.Q + gc.P, gc.W);
-    const int FH = y_hi - y_lo, FW = x_hi - x_lo;
+    if (a.M > 0) {
+        const long nt = (long)a.M * gc.C * gc.P;
+        hipLaunchKernelGGL(k_cone_zero, dim3((unsigned)cdiv(nt, 256)), dim3(256), 0, st, gc, rows, a.M, Gd);
+        MNB_HIP(hipGetLastError());
+    }
+    const int HW = gc.H * gc.W;
     if (a.n_slices <= 0) {
         // no rows: the sums below are zero
     } else if (gc.C % 4 == 0) {
-        dim3 grid(cdiv((long)(gc.C / 4) * FH * FW, 256), a.n_inst, a.n_slices);
-        hipLaunchKernelGGL(k_relax_cone<4>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
-                           FH, FW);
+        dim3 grid(cdiv((long)(gc.C / 4) * HW, 256), a.n_inst, a.n_slices);
+        hipLaunchKernelGGL(k_relax_cone<4>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd);
     } else {
-        dim3 grid(cdiv((long)gc.C * FH * FW, 256), a.n_inst, a.n_slices);
-        hipLaunchKernelGGL(k_relax_cone<1>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd, y_lo, x_lo,
-                           FH, FW);
+        dim3 grid(cdiv((long)gc.C * HW, 256), a.n_inst, a.n_slices);
+        hipLaunchKernelGGL(k_relax_cone<1>, grid, dim3(256), 0, st, a, gw, gc, rows, ush, ghs, apw, Gd);
     }
     MNB_HIP(hipGetLastError());
     launch_relax_sum(a, st);
