@@ -43,20 +43,28 @@ struct ConvWinArgs {
     int CO, RS, WS, PL;
     // output position (y, x) of channel n at n*out_ns + (out_y0 + out_s y)*out_rs + out_x0 + out_s x
     int out_ns, out_rs, out_y0, out_x0, out_s;
+    // four stride phases of a transposed convolution in one workgroup (NPH = 4), wavefront f on
+    // phase f: its row / column padding and output origin (p / px above are their maxima, which
+    // place the shared window; wh_extra = the spread of the row paddings)
+    int ph_py[4], ph_px[4], ph_y0[4], ph_x0[4];
+    int wh_extra;
 };
 
 template <int BN> struct WinB { static constexpr int BNP = BN + 16; };   // filter row stride: 16 mod 32 banks
 
-template <int K, int S, int BM, int BN, int VEC>
+template <int K, int S, int BM, int BN, int VEC, int NPH>
 __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     constexpr int KK = K * K;
-    constexpr int WAVES_N = BN / 32, WAVES_M = 4 / WAVES_N;
-    constexpr int FN = 2, FM = BM / (16 * WAVES_M);
+    // NPH == 1: the four wavefronts split the tile's positions and channels; NPH == 4: wavefront f
+    // computes the whole tile of stride phase f
+    constexpr int WAVES_N = NPH == 1 ? BN / 32 : 1, WAVES_M = NPH == 1 ? 4 / WAVES_N : 1;
+    constexpr int FN = NPH == 1 ? 2 : BN / 16, FM = BM / (16 * WAVES_M);
     static_assert(FM >= 1 && FM * 16 * WAVES_M == BM, "tile");
+    static_assert(NPH == 1 || (NPH == 4 && S == 1), "phases");
     constexpr int NLD = VEC == 4 ? NLD4 : NLD1;
     constexpr int BNP = WinB<BN>::BNP;
     constexpr int BQ = BN / 4;                       // float4 per filter row of the tile
-    constexpr int WROWS = KK * CG;                   // filter rows (tap, channel) per stage
+    constexpr int WROWS = NPH * KK * CG;             // filter rows (phase, tap, channel) per stage
     constexpr int NW = (WROWS * BQ + 255) / 256;     // float4 filter loads per thread and stage
     // native vectors: copies of HIP's float4 struct out of an array keep the array in scratch
     typedef typename std::conditional<VEC == 4, floatx4, float>::type vec_t;
@@ -66,13 +74,14 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     float* s_x = sm + WROWS * BNP;      // [CG][PL]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+    // wavefront's position and channel block (NPH == 4: the whole tile, for phase `wave`)
+    const int wm = NPH == 1 ? wave % WAVES_M : 0, wn = NPH == 1 ? wave / WAVES_M : 0;
     const int r = blockIdx.x / a.mtiles, mt = blockIdx.x - r * a.mtiles;
     const int n0 = blockIdx.y * BN;
     const int P = a.Ho * a.Wo, m0 = mt * BM;
     const int y_first = m0 / a.Wo;
     const int y_last = (min(m0 + BM, P) - 1) / a.Wo;
-    const int WH = S * (y_last - y_first) + K;
+    const int WH = S * (y_last - y_first) + K + a.wh_extra;
     const int iy0 = S * y_first - a.p;                   // input row of window row 0
     const int wy_lo = max(0, -iy0), wy_hi = min(WH, a.Hi - iy0);
     const int nvr = max(0, wy_hi - wy_lo);
@@ -149,6 +158,18 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
         }
     }
     const int wb = (lane >> 4) * BNP + wn * 32 + (lane & 15);
+    // this wavefront's phase: extra window rows above its first one, column offset, output origin
+    int row_off = 0, c0p = a.CO - a.px, out_y0 = a.out_y0, out_x0 = a.out_x0;
+    if constexpr (NPH == 4) {
+        const int f = __builtin_amdgcn_readfirstlane(wave);
+        const int py = f == 0 ? a.ph_py[0] : f == 1 ? a.ph_py[1] : f == 2 ? a.ph_py[2] : a.ph_py[3];
+        const int px = f == 0 ? a.ph_px[0] : f == 1 ? a.ph_px[1] : f == 2 ? a.ph_px[2] : a.ph_px[3];
+        out_y0 = f == 0 ? a.ph_y0[0] : f == 1 ? a.ph_y0[1] : f == 2 ? a.ph_y0[2] : a.ph_y0[3];
+        out_x0 = f == 0 ? a.ph_x0[0] : f == 1 ? a.ph_x0[1] : f == 2 ? a.ph_x0[2] : a.ph_x0[3];
+        row_off = a.p - py;
+        c0p = a.CO - px;
+    }
+    const float* s_wf = s_w + (NPH == 4 ? wave : 0) * KK * CG * BNP;
 
     floatx4 acc[FN][FM];
 #pragma unroll
@@ -162,7 +183,6 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     __syncthreads();
     MNB_WIN_STORE()
     __syncthreads();
-    const int c0p = a.CO - a.px;
     for (int g = 0; g < ng; ++g) {
         if (g + 1 < ng) MNB_WIN_LOAD(g + 1)
         // taps as a loop (not unrolled): unrolled, the compiler keeps every tap's LDS addresses in
@@ -171,8 +191,8 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
         for (int t = 0; t < KK; ++t) {
             const int ky = t / K, kx = t - ky * K;
             const int tc = kx + c0p;
-            const int toff = ky * a.RS + (tc % S) * a.WS + tc / S;
-            const float* wt = s_w + t * CG * BNP + wb;
+            const int toff = (ky + row_off) * a.RS + (tc % S) * a.WS + tc / S;
+            const float* wt = s_wf + t * CG * BNP + wb;
             const float* xt = s_x + toff;
 #pragma unroll
             for (int cq = 0; cq < CG / 4; ++cq) {
@@ -210,7 +230,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     for (int i = 0; i < FM; ++i) {
         const int m = m0 + wm * FM * 16 + i * 16 + (lane & 15);
         const int y = m / a.Wo, x = m - y * a.Wo;
-        moff[i] = m < P ? (a.out_y0 + a.out_s * y) * a.out_rs + a.out_x0 + a.out_s * x : -1;
+        moff[i] = m < P ? (out_y0 + a.out_s * y) * a.out_rs + out_x0 + a.out_s * x : -1;
     }
     if (a.acc) {
 #pragma unroll
@@ -270,35 +290,61 @@ struct WinConv {
     int Cin, Hi, Wi, Cout, Ho, Wo, K, S, py, px;
     long ldG, ldC;
     int out_ns, out_rs, out_y0, out_x0, out_s;
+    // nph = 4: the four stride phases at once (filters Wt [Cin/8][4][K*K][8][Cout]); py / px and
+    // out_y0 / out_x0 above are then unused
+    int nph;
+    int ph_py[4], ph_px[4], ph_y0[4], ph_x0[4];
 };
 
 bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool check_only) {
     if (w.Wt == nullptr || w.Cin % CG != 0) return false;
     const int BN = w.Cout % 64 == 0 ? 64 : (w.Cout % 32 == 0 ? 32 : 0);
     if (BN == 0) return false;
-    const int K = w.K, S = w.S;
+    const int K = w.K, S = w.S, nph = w.nph == 4 ? 4 : 1;
     const bool ks31 = K == 3 && S == 1, ks42 = K == 4 && S == 2, ks32 = K == 3 && S == 2, ks21 = K == 2 && S == 1;
     if (!(ks31 || ks42 || ks32 || ks21) || w.Ho <= 0 || w.Wo <= 0) return false;
+    if (nph == 4 && !ks21) return false;
     const int P = w.Ho * w.Wo;
-    // positions per workgroup: 128, unless 64 wastes fewer lanes on the last tile
-    const int BM = cdiv(P, 64) * 64 < cdiv(P, 128) * 128 ? 64 : 128;
+    // positions per workgroup: 128, unless 64 wastes fewer lanes on the last tile (or a wavefront
+    // holding a whole tile of 64 channels would need more accumulators)
+    const int BM = cdiv(P, 64) * 64 < cdiv(P, 128) * 128 || (nph == 4 && BN == 64) ? 64 : 128;
+    // phases in one workgroup: the window spans every phase's rows and columns
+    int py = w.py, px = w.px, extra = 0;
+    if (nph == 4) {
+        int lo = w.ph_py[0];
+        py = w.ph_py[0];
+        px = w.ph_px[0];
+        for (int f = 1; f < 4; ++f) {
+            py = std::max(py, w.ph_py[f]);
+            lo = std::min(lo, w.ph_py[f]);
+            px = std::max(px, w.ph_px[f]);
+        }
+        extra = py - lo;
+    }
     const int mtiles = cdiv(P, BM);
     const bool vec = w.Wi % 4 == 0 && w.ldG % 4 == 0 && ((uintptr_t)w.G & 15) == 0;
     // rows of the largest window over the tiles
     int WHmax = 0;
     for (int mt = 0; mt < mtiles; ++mt) {
         const int yf = mt * BM / w.Wo, yl = (std::min((mt + 1) * BM, P) - 1) / w.Wo;
-        WHmax = std::max(WHmax, S * (yl - yf) + K);
+        WHmax = std::max(WHmax, S * (yl - yf) + K + extra);
     }
     ConvWinArgs a{};
     a.G = w.G; a.C = w.C; a.Wt = w.Wt; a.bias = w.bias;
     a.ldG = w.ldG; a.ldC = w.ldC;
-    a.Hi = w.Hi; a.Wi = w.Wi; a.Co = w.Cout; a.Ho = w.Ho; a.Wo = w.Wo; a.p = w.py; a.px = w.px;
+    a.Hi = w.Hi; a.Wi = w.Wi; a.Co = w.Cout; a.Ho = w.Ho; a.Wo = w.Wo; a.p = py; a.px = px;
+    a.wh_extra = extra;
+    for (int f = 0; f < 4; ++f) {
+        a.ph_py[f] = w.ph_py[f]; a.ph_px[f] = w.ph_px[f]; a.ph_y0[f] = w.ph_y0[f]; a.ph_x0[f] = w.ph_x0[f];
+    }
     a.n_groups = w.Cin / CG;
     a.mtiles = mtiles; a.acc = accumulate;
     a.out_ns = w.out_ns; a.out_rs = w.out_rs; a.out_y0 = w.out_y0; a.out_x0 = w.out_x0; a.out_s = w.out_s;
-    a.CO = w.px > 0 ? (w.px + 3) & ~3 : 0;
-    const int need = std::max(a.CO + w.Wi, a.CO - w.px + S * (w.Wo - 1) + K);
+    a.CO = px > 0 ? (px + 3) & ~3 : 0;
+    int pxlo = px;
+    if (nph == 4)
+        for (int f = 0; f < 4; ++f) pxlo = std::min(pxlo, w.ph_px[f]);
+    const int need = std::max(a.CO + w.Wi, a.CO - pxlo + S * (w.Wo - 1) + K);
     const int JW = cdiv(need, 4 * S) * 4 * S;
     a.RS = JW;
     a.WS = JW / S;
@@ -310,7 +356,7 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     }
     a.PL = best;
     const int BNP = BN + 16;
-    const size_t lds = ((size_t)K * K * CG * BNP + (size_t)CG * a.PL) * sizeof(float);
+    const size_t lds = ((size_t)nph * K * K * CG * BNP + (size_t)CG * a.PL) * sizeof(float);
     if (lds > WIN_LDS_MAX) return false;
     // window loads per thread and stage
     const int Q = vec ? w.Wi / 4 : w.Wi;
@@ -319,8 +365,17 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     if ((long)M * mtiles > 0x7fffffffL) return false;
     if (check_only || M <= 0) return true;
     const dim3 grid((unsigned)(M * mtiles), w.Cout / BN), blk(256);
+    if (nph == 4) {
+#define MNB_WIN4(BM_, BN_, V_) hipLaunchKernelGGL((k_conv_win<2, 1, BM_, BN_, V_, 4>), grid, blk, lds, st, a)
+        if (BN == 64) { if (vec) MNB_WIN4(64, 64, 4); else MNB_WIN4(64, 64, 1); }
+        else if (BM == 128) { if (vec) MNB_WIN4(128, 32, 4); else MNB_WIN4(128, 32, 1); }
+        else { if (vec) MNB_WIN4(64, 32, 4); else MNB_WIN4(64, 32, 1); }
+#undef MNB_WIN4
+        MNB_HIP(hipGetLastError());
+        return true;
+    }
 #define MNB_WIN(K_, S_, BM_, BN_, V_) \
-    hipLaunchKernelGGL((k_conv_win<K_, S_, BM_, BN_, V_>), grid, blk, lds, st, a)
+    hipLaunchKernelGGL((k_conv_win<K_, S_, BM_, BN_, V_, 1>), grid, blk, lds, st, a)
 #define MNB_WIN_V(K_, S_, BM_, BN_) \
     if (vec) MNB_WIN(K_, S_, BM_, BN_, 4); else MNB_WIN(K_, S_, BM_, BN_, 1)
 #define MNB_WIN_T(K_, S_)                                                   \
@@ -358,6 +413,27 @@ bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M,
 
 bool launch_conv_backsub_win(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st) {
     if ((kernel_variants() & MNB_VAR_NO_WIN_CONV) != 0) return false;
+    // the four phases of a stride-2 layer in one launch, where they share taps and grid
+    if (g.s == 2 && g.n_phase == 4 && g.Wt4 != nullptr) {
+        WinConv w{};
+        w.G = A; w.C = C; w.Wt = g.Wt4; w.bias = nullptr;
+        w.Cin = g.Co; w.Hi = g.Ho; w.Wi = g.Wo; w.Cout = g.Ci; w.Ho = g.ph[0].nY; w.Wo = g.ph[0].nX;
+        w.K = g.ph[0].Ty; w.S = 1;
+        w.ldG = (long)g.Co * g.Ho * g.Wo; w.ldC = (long)g.Ci * g.Hi * g.Wi;
+        w.out_ns = g.Hi * g.Wi; w.out_rs = g.Wi; w.out_s = g.s;
+        w.nph = 4;
+        for (int f = 0; f < 4; ++f) {
+            const ConvPhase& ph = g.ph[f];
+            w.ph_py[f] = ph.Ty - 1 - ph.q0y;
+            w.ph_px[f] = ph.Tx - 1 - ph.q0x;
+            w.ph_y0[f] = ph.Y0;
+            w.ph_x0[f] = ph.X0;
+        }
+        if (launch_win(w, M, accumulate, st, true)) {
+            launch_win(w, M, accumulate, st, false);
+            return true;
+        }
+    }
     // every phase must be covered before any is launched
     WinConv ws[16];
     int n = 0;

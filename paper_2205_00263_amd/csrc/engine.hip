@@ -309,6 +309,31 @@ static void fill_conv_geom(mnb_net* net, ConvGeom& g, int Ci, int Hi, int Wi, in
             }
             g.ph[g.n_phase++] = ph;
         }
+    g.Wt4 = nullptr;
+    bool same = s == 2 && g.n_phase == 4 && g.Co % 8 == 0;
+    for (int f = 0; same && f < 4; ++f)
+        same = g.ph[f].Wt && g.ph[f].Ty > 0 && g.ph[f].Ty == g.ph[f].Tx && g.ph[f].Ty == g.ph[0].Ty &&
+               g.ph[f].nY == g.ph[0].nY && g.ph[f].nX == g.ph[0].nX && g.ph[f].nY > 0 && g.ph[f].nX > 0;
+    if (same) {
+        // phase f's block of each 8-channel group follows phase f - 1's (the host copy of ph[f].Wt is
+        // rebuilt here from the same weights)
+        const int T = g.ph[0].Ty * g.ph[0].Tx;
+        std::vector<float> w4((size_t)g.Co * 4 * T * g.Ci);
+        for (int f = 0; f < 4; ++f) {
+            const ConvPhase& ph = g.ph[f];
+            for (int cg = 0; cg < g.Co / 8; ++cg)
+                for (int ty = 0; ty < ph.Ty; ++ty)
+                    for (int tx = 0; tx < ph.Tx; ++tx)
+                        for (int c = 0; c < 8; ++c)
+                            for (int ci = 0; ci < g.Ci; ++ci) {
+                                const int t = (ph.Ty - 1 - ty) * ph.Tx + (ph.Tx - 1 - tx);
+                                const int co = cg * 8 + c;
+                                w4[((((size_t)cg * 4 + f) * T + t) * 8 + c) * g.Ci + ci] =
+                                    Wh[(((size_t)co * g.Ci + ci) * k + (ph.rho_y + s * ty)) * k + (ph.rho_x + s * tx)];
+                            }
+        }
+        g.Wt4 = upload(w4.data(), w4.size(), &net->owned);
+    }
 }
 
 static void build_conv_geom(mnb_net* net, NetNode& nd, const std::vector<float>& Wh) {

@@ -26,6 +26,9 @@ struct ConvGeom {
     const float* Wf;       // [Co][k*k*Ci] weights in that K order
     const float* Wg;       // [Co][k*k*Ci] weights with K ordered (ci / 16, ky, kx, ci % 16) (Ci % 16 == 0)
     const float* Wt;       // [Ci/8][k*k][8][Co] weights of the input-window kernel (Ci % 8 == 0)
+    // stride 2 with four phases of equal grid and square taps T x T: their flipped taps side by
+    // side, [Co/8][4][T*T][8][Ci] (Co % 8 == 0), for the transposed window kernel; else null
+    const float* Wt4;
     int n_phase;
     ConvPhase ph[16];   // stride <= 4
 };
