@@ -59,12 +59,39 @@ __global__ __launch_bounds__(FT) void k_convT_first(const float* __restrict__ A,
     const float* Ar = A + (act ? r : 0) * (long)Co * Ho * Wo;
     const int HoWo = Ho * Wo;
     const float rWX = 1.f / (float)WX, rWY = 1.f / (float)WY;
+    // staging map: thread pix owns window column scol of rows srow, srow + RP, ...
+    const int RP = per / WX;
+    const int srow = fdivs(pix, rWX), scol = pix - srow * WX;
+    const int sx = x0 + scol;
+    const bool sxok = r < M && sx >= 0 && sx < Wo;
+    int sco = 0, swy = srow;
+    while (swy >= WY) {
+        swy -= WY;
+        ++sco;
+    }
     float o0[CI], o1[CI];
 #pragma unroll
     for (int c = 0; c < CI; ++c) o0[c] = o1[c] = 0.f;
     for (int c0 = 0; c0 < Co; c0 += FCO) {
         __syncthreads();   // the previous channels' window is consumed
-        if (rb < t.RB) {
+        if (rb < t.RB && RP > 0) {
+            // a fixed window column per thread, RP window rows per pass, the (channel, row) of the
+            // next pass by stepping
+            if (srow < RP) {
+                int co = sco, wy = swy;
+                for (int rr = srow; rr < FCO * WY; rr += RP) {
+                    const int y = y0 + wy;
+                    float v = 0.f;
+                    if (sxok && c0 + co < Co && y >= 0 && y < Ho) v = Ar[(long)(c0 + co) * HoWo + y * Wo + sx];
+                    s_a[rr * WX + scol] = v;
+                    wy += RP;
+                    while (wy >= WY) {
+                        wy -= WY;
+                        ++co;
+                    }
+                }
+            }
+        } else if (rb < t.RB) {
             for (int i = pix; i < FCO * win; i += per) {
                 const int wr = fdivs(i, rWX), wx = i - wr * WX;
                 const int co = fdivs(wr, rWY), wy = wr - co * WY;

@@ -387,25 +387,22 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
     }
 }
 
-// Cone entries outside the node hold 0 (the next convolution reads them as padding): one thread per
-// (row, channel, cone row), writing the entries of its cone row that fall outside the node.
-__global__ __launch_bounds__(256) void k_cone_zero(PatchGeom gc, const RowDesc* rows, int M, float* Gd) {
-    const long t = (long)blockIdx.x * 256 + threadIdx.x;
-    const int Pc = gc.P;
-    const long per = (long)gc.C * Pc;
-    if (t >= (long)M * per) return;
-    const int r = (int)(t / per);
-    const int rem = (int)(t - (long)r * per);
-    const int c = rem / Pc, dy = rem - c * Pc;
+// Cone entries outside the node hold 0 (the next convolution reads them as padding): one workgroup
+// per row, its lanes over the cone positions (consecutive lanes, consecutive entries), each
+// position outside the node zeroed in every channel.
+__global__ __launch_bounds__(256) void k_cone_zero(PatchGeom gc, const RowDesc* rows, float* Gd, float inv_p) {
+    const long r = blockIdx.x;
+    const int Pc = gc.P, PP = Pc * Pc;
     int oy, ox;
     patch_origin(gc, rows[r].j, oy, ox);
-    float* p = Gd + (long)r * gc.C * Pc * Pc + ((long)c * Pc + dy) * Pc;
-    const int Y = oy + dy;
-    if (Y < 0 || Y >= gc.H) {
-        for (int dx = 0; dx < Pc; ++dx) p[dx] = 0.f;
-    } else {
-        for (int dx = 0; dx < -ox && dx < Pc; ++dx) p[dx] = 0.f;
-        for (int dx = max(0, gc.W - ox); dx < Pc; ++dx) p[dx] = 0.f;
+    // a cone inside the node has nothing to clear
+    if (oy >= 0 && ox >= 0 && oy + Pc <= gc.H && ox + Pc <= gc.W) return;
+    float* base = Gd + r * gc.C * PP;
+    for (int q = threadIdx.x; q < PP; q += 256) {
+        const int dy = (int)(((float)q + 0.5f) * inv_p), dx = q - dy * Pc;
+        const int Y = oy + dy, X = ox + dx;
+        if (Y >= 0 && Y < gc.H && X >= 0 && X < gc.W) continue;
+        for (int c = 0; c < gc.C; ++c) base[(long)c * PP + q] = 0.f;
     }
 }
 
@@ -413,8 +410,7 @@ void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom&
                        const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st) {
     if (a.n_inst <= 0) return;
     if (a.M > 0) {
-        const long nt = (long)a.M * gc.C * gc.P;
-        hipLaunchKernelGGL(k_cone_zero, dim3((unsigned)cdiv(nt, 256)), dim3(256), 0, st, gc, rows, a.M, Gd);
+        hipLaunchKernelGGL(k_cone_zero, dim3((unsigned)a.M), dim3(256), 0, st, gc, rows, Gd, 1.f / (float)gc.P);
         MNB_HIP(hipGetLastError());
     }
     const int HW = gc.H * gc.W;
