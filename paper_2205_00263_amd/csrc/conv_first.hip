@@ -64,31 +64,21 @@ __global__ __launch_bounds__(FT) void k_convT_first(const float* __restrict__ A,
     const int srow = fdivs(pix, rWX), scol = pix - srow * WX;
     const int sx = x0 + scol;
     const bool sxok = r < M && sx >= 0 && sx < Wo;
-    int sco = 0, swy = srow;
-    while (swy >= WY) {
-        swy -= WY;
-        ++sco;
-    }
     float o0[CI], o1[CI];
 #pragma unroll
     for (int c = 0; c < CI; ++c) o0[c] = o1[c] = 0.f;
     for (int c0 = 0; c0 < Co; c0 += FCO) {
         __syncthreads();   // the previous channels' window is consumed
         if (rb < t.RB && RP > 0) {
-            // a fixed window column per thread, RP window rows per pass, the (channel, row) of the
-            // next pass by stepping
+            // a fixed window column per thread, RP window rows per pass
             if (srow < RP) {
-                int co = sco, wy = swy;
+#pragma unroll 4
                 for (int rr = srow; rr < FCO * WY; rr += RP) {
+                    const int co = fdivs(rr, rWY), wy = rr - co * WY;   // independent passes: loads batch
                     const int y = y0 + wy;
                     float v = 0.f;
                     if (sxok && c0 + co < Co && y >= 0 && y < Ho) v = Ar[(long)(c0 + co) * HoWo + y * Wo + sx];
                     s_a[rr * WX + scol] = v;
-                    wy += RP;
-                    while (wy >= WY) {
-                        wy -= WY;
-                        ++co;
-                    }
                 }
             }
         } else if (rb < t.RB) {
@@ -142,7 +132,7 @@ template <int CI, int K>
 __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, float* __restrict__ C,
                                                    const float* __restrict__ W, const float* __restrict__ bias, int M,
                                                    int Hi, int Wi, int Co, int Ho, int Wo, int p, int acc,
-                                                   FirstTile t) {
+                                                   FirstTile t, ConeClip clip) {
     extern __shared__ float sm[];
     const int WY = t.TH + K - 1, WX = t.TW + K, win = WY * WX;
     const int per = t.TW / 2 * t.TH;
@@ -180,6 +170,15 @@ __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, 
             for (int q = 0; q <= K; ++q) in[(ci * K + ky) * (K + 1) + q] = gp[ci * win + ky * WX + q];
     float* Cr = C + r * (long)Co * Ho * Wo + (long)y * Wo + x;
     const bool two = x + 1 < Wo;
+    // cone rows: positions outside the node are written 0
+    bool z0 = false, z1 = false;
+    if (clip.rows) {
+        int oy, ox;
+        cone_origin(clip, r, oy, ox);
+        const bool yin = oy + y >= 0 && oy + y < clip.H;
+        z0 = !(yin && ox + x >= 0 && ox + x < clip.W);
+        z1 = !(yin && ox + x + 1 >= 0 && ox + x + 1 < clip.W);
+    }
 #pragma unroll 2
     for (int co = 0; co < Co; ++co) {
         const float* w = W + (long)co * CI * K * K;
@@ -195,6 +194,8 @@ __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, 
                     s1 += wv * in[(ci * K + ky) * (K + 1) + kx + 1];
                 }
         float* o = Cr + (long)co * Ho * Wo;
+        if (z0) s0 = 0.f;
+        if (z1) s1 = 0.f;
         if (x < Wo) o[0] = acc ? o[0] + s0 : s0;
         if (two) o[1] = acc ? o[1] + s1 : s1;
     }
@@ -221,7 +222,8 @@ bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool
     return true;
 }
 
-bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st) {
+bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st,
+                       const ConeClip* clip) {
     if (g.s != 1 || g.Ci > 4 || g.k != 3 || (kernel_variants() & MNB_VAR_NO_FIRST_CONV)) return false;
     if (M <= 0) return true;
     const FirstTile t = first_tile(g.Ho, g.Wo);
@@ -230,7 +232,7 @@ bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool 
     MNB_CHECK(blocks < (1L << 31), MNB_EDEVICE, "first-layer convolution: grid too large");
 #define MNB_CF1(CI_)                                                                                              \
     hipLaunchKernelGGL((k_conv_first<CI_, 3>), dim3((unsigned)blocks), dim3(FT), lds, st, G, C, g.W, g.b, M, g.Hi,   \
-                       g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t)
+                       g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, clip ? *clip : ConeClip{})
     switch (g.Ci) {
         case 1: MNB_CF1(1); break;
         case 2: MNB_CF1(2); break;

@@ -48,6 +48,7 @@ struct ConvWinArgs {
     // place the shared window; wh_extra = the spread of the row paddings)
     int ph_py[4], ph_px[4], ph_y0[4], ph_x0[4];
     int wh_extra;
+    ConeClip clip;   // forward convolutions of cone rows (clip.rows null: none)
 };
 
 template <int BN> struct WinB { static constexpr int BNP = BN + 16; };   // filter row stride: 16 mod 32 banks
@@ -226,11 +227,15 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
             bias[j][v] = a.bias ? a.bias[n0 + wn * 32 + j * 16 + 4 * (lane >> 4) + v] : 0.f;
     float* Cr = a.C + (long)r * a.ldC + (long)(n0 + wn * 32 + 4 * (lane >> 4)) * a.out_ns;
     int moff[FM];
+    bool mzero[FM];   // position outside the node of a cone row: written 0
+    int coy = 0, cox = 0;
+    if (a.clip.rows) cone_origin(a.clip, r, coy, cox);
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int m = m0 + wm * FM * 16 + i * 16 + (lane & 15);
         const int y = m / a.Wo, x = m - y * a.Wo;
         moff[i] = m < P ? (out_y0 + a.out_s * y) * a.out_rs + out_x0 + a.out_s * x : -1;
+        mzero[i] = a.clip.rows && !(coy + y >= 0 && coy + y < a.clip.H && cox + x >= 0 && cox + x < a.clip.W);
     }
     if (a.acc) {
 #pragma unroll
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     float* q = Cr + (long)(j * 16 + v) * a.out_ns + moff[i];
-                    *q += acc[j][i][v] + bias[j][v];
+                    *q += mzero[i] ? 0.f : acc[j][i][v] + bias[j][v];
                 }
         }
     } else {
@@ -251,7 +256,8 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Cr[(long)(j * 16 + v) * a.out_ns + moff[i]] = acc[j][i][v] + bias[j][v];
+                for (int v = 0; v < 4; ++v)
+                    Cr[(long)(j * 16 + v) * a.out_ns + moff[i]] = mzero[i] ? 0.f : acc[j][i][v] + bias[j][v];
         }
     }
 }
@@ -290,6 +296,7 @@ struct WinConv {
     int Cin, Hi, Wi, Cout, Ho, Wo, K, S, py, px;
     long ldG, ldC;
     int out_ns, out_rs, out_y0, out_x0, out_s;
+    ConeClip clip;
     // nph = 4: the four stride phases at once (filters Wt [Cin/8][4][K*K][8][Cout]); py / px and
     // out_y0 / out_x0 above are then unused
     int nph;
@@ -340,6 +347,7 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     a.n_groups = w.Cin / CG;
     a.mtiles = mtiles; a.acc = accumulate;
     a.out_ns = w.out_ns; a.out_rs = w.out_rs; a.out_y0 = w.out_y0; a.out_x0 = w.out_x0; a.out_s = w.out_s;
+    a.clip = w.clip;
     a.CO = px > 0 ? (px + 3) & ~3 : 0;
     int pxlo = px;
     if (nph == 4)
@@ -400,7 +408,8 @@ constexpr int WIN_MIN_PLANE = 129;
 
 }  // namespace
 
-bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st) {
+bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st,
+                             const ConeClip* clip) {
     if ((kernel_variants() & MNB_VAR_NO_WIN_CONV) != 0 || g.Hi * g.Wi < WIN_MIN_PLANE || g.p < 0) return false;
     WinConv w{};
     w.G = G; w.C = C; w.Wt = g.Wt; w.bias = g.b;
@@ -408,6 +417,7 @@ bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M,
     w.K = g.k; w.S = g.s; w.py = g.p; w.px = g.p;
     w.ldG = (long)g.Ci * g.Hi * g.Wi; w.ldC = (long)g.Co * g.Ho * g.Wo;
     w.out_ns = g.Ho * g.Wo; w.out_rs = g.Wo; w.out_y0 = 0; w.out_x0 = 0; w.out_s = 1;
+    w.clip = clip ? *clip : ConeClip{};
     return launch_win(w, M, accumulate, st, false);
 }
 

@@ -1542,6 +1542,7 @@ struct Evaluator {
         const int top = chunk_top(net, ch);
         const PatchPlan& pp = *ch.pp;
         float* g = cx.G0;
+        bool clipped = false;   // g's cone entries outside the node hold 0
         for (int m = 1; m <= top; ++m) {
             const NetNode& nd = net->nodes[m];
             if (nd.kind == MNB_CONV) {
@@ -1549,11 +1550,15 @@ struct Evaluator {
                 {
                     TimerScope ts(MNB_T_CONV_FORWARD, m, 2.0 * M * pp.fmacs[m],
                                   4.0 * M * (pp.cone_width(m) + pp.cone_width(nd.src)));
-                    launch_conv_forward(pp.fconv[m], g, out, M, false, st);
+                    const PatchGeom& fc = pp.fc[m];
+                    const ConeClip clip{ch.rows, nd.H, nd.W, fc.S, fc.Q, fc.HWobj, fc.Wobj};
+                    launch_conv_forward(pp.fconv[m], g, out, M, false, st, &clip);
                 }
                 if (g != cx.G0) pool.release(g);
                 g = out;
+                clipped = true;
             } else {
+                if (!clipped) launch_cone_zero(pp.fc[m], ch.rows, M, g, st);
                 const int r = nd.relu_m;
                 RelaxArgs ra{};
                 ra.inst = ch.inst_d; ra.n_inst = n_inst; ra.slots = cx.slots_d;

@@ -122,7 +122,8 @@ struct ConvFwd {
     int M, N, K;          // M = rows*Ho*Wo, N = Co, K = Ci*k*k
     int Ho, Wo, Hi, Wi, ldA, ldC, s, p;
     int acc;
-    struct MCtx { long base, cbase; int iy, ix; bool ok; };
+    ConeClip clip;   // clip.rows null: none
+    struct MCtx { long base, cbase; int iy, ix; bool ok, in; };
     __device__ MCtx mctx(int m) const {
         MCtx c;
         c.ok = m < M;
@@ -134,6 +135,12 @@ struct ConvFwd {
         c.ix = s * x - p;
         c.base = (long)r * ldA + (long)c.iy * Wi + c.ix;
         c.cbase = (long)r * ldC + rem;
+        c.in = true;
+        if (clip.rows) {
+            int oy, ox;
+            cone_origin(clip, r, oy, ox);
+            c.in = oy + y >= 0 && oy + y < clip.H && ox + x >= 0 && ox + x < clip.W;
+        }
         return c;
     }
     __device__ float a(const MCtx& c, int k) const {
@@ -163,7 +170,7 @@ struct ConvFwd {
     __device__ void store_ctx(const MCtx& c, int n, float v) const {
         if (c.ok && n < N) {
             float* q = C + c.cbase + (long)n * Ho * Wo;
-            v += bias[n];
+            v = c.in ? v + bias[n] : 0.f;
             *q = acc ? *q + v : v;
         }
     }
@@ -480,12 +487,14 @@ void launch_conv_backsub(const ConvGeom& g, const float* A, float* C, int M, boo
 }
 
 void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
-                         hipStream_t st) {
+                         hipStream_t st, const ConeClip* clip) {
     if (M <= 0) return;
-    if (launch_conv_forward_rows(g, G, C, M, accumulate, st)) return;
-    if (launch_conv_first(g, G, C, M, accumulate, st)) return;
-    if (launch_conv_forward_win(g, G, C, M, accumulate, st)) return;
+    // the row-resident kernels write no clip
+    if (!clip && launch_conv_forward_rows(g, G, C, M, accumulate, st)) return;
+    if (launch_conv_first(g, G, C, M, accumulate, st, clip)) return;
+    if (launch_conv_forward_win(g, G, C, M, accumulate, st, clip)) return;
     ConvFwd p;
+    p.clip = clip ? *clip : ConeClip{};
     p.A = G; p.C = C; p.bias = g.b; p.ktab = g.fwd_ktab;
     p.Ci = g.Ci; p.kw = g.k; p.HiWi = g.Hi * g.Wi;
     p.tile_ok = (g.Ci % BK) == 0 && g.Wg != nullptr;

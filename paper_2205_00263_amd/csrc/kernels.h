@@ -33,6 +33,22 @@ struct ConvGeom {
     ConvPhase ph[16];   // stride <= 4
 };
 
+// Rows held on forward cones (receptive-field rows): a forward convolution given a clip writes 0
+// at every position of row r's output cone that lies outside the node, so that the next
+// convolution reads those entries as padding.  Row r's cone origin on the node is
+// (yo S - Q, xo S - Q) for its objective position (yo, xo) = (j mod HWobj) / Wobj, % Wobj.
+struct ConeClip {
+    const RowDesc* rows;       // null: no clip
+    int H, W;                  // node
+    int S, Q, HWobj, Wobj;
+};
+__device__ __forceinline__ void cone_origin(const ConeClip& k, long r, int& oy, int& ox) {
+    const int pos = k.rows[r].j % k.HWobj;
+    const int yo = pos / k.Wobj, xo = pos - yo * k.Wobj;
+    oy = yo * k.S - k.Q;
+    ox = xo * k.S - k.Q;
+}
+
 // ---- back-substitution products (Eq. 2) ----
 // C[M, din] (+)= A[M, dout] * W[dout, din]
 void launch_fc_backsub(const float* A, const float* W, float* C, int M, int dout, int din,
@@ -49,10 +65,12 @@ bool launch_conv_forward_rows(const ConvGeom& g, const float* G, float* C, int M
 // VALU forms for convolutions of stride 1 out of (forward) or into (transposed) at most 4
 // channels with 3x3 filters; false (nothing launched) for other shapes.
 bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool accumulate, hipStream_t st);
-bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st);
+bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st,
+                       const ConeClip* clip = nullptr);
 // Forward convolution from input windows staged in LDS (8 input channels at a time, Co % 32 == 0,
 // 3x3 / 1, 3x3 / 2 or 4x4 / 2 filters); false (nothing launched) for other shapes.
-bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st);
+bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st,
+                             const ConeClip* clip = nullptr);
 // Transposed convolution by the same kernel, one stride phase at a time (each phase is a stride-1
 // correlation of the coefficient grid with the phase's flipped taps; square phases of 2x2 or 3x3
 // taps, Co % 8 == 0, Ci % 32 == 0); false (nothing launched) for other shapes.
@@ -63,7 +81,7 @@ bool launch_conv_backsub_win(const ConvGeom& g, const float* A, float* C, int M,
 void launch_fc_forward(const float* G, const float* W, const float* b, float* C, int M, int din,
                        int dout, bool accumulate, hipStream_t st);
 void launch_conv_forward(const ConvGeom& g, const float* G, float* C, int M, bool accumulate,
-                         hipStream_t st);
+                         hipStream_t st, const ConeClip* clip = nullptr);
 
 // Relaxation of one neuron (the D / b-underline case table of Section 3.1 with
 // the split matrix of Eq. 4): split first, then stable, then unstable.
@@ -260,6 +278,9 @@ void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs,
 // in row slices (RelaxArgs)
 void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
                        const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st);
+// zero the cone entries of rows [0, M) outside the node (for cones not written by a clipped
+// convolution)
+void launch_cone_zero(const PatchGeom& gc, const RowDesc* rows, int M, float* Gd, hipStream_t st);
 // dense rows out[r] = shared[instance of r] + (window entries of win[r], nullable)
 void launch_patch_expand(const float* shared, const float* win, const RowDesc* rows, int M, int inst_base,
                          const PatchGeom& g, float* out, hipStream_t st);

@@ -257,7 +257,7 @@ void launch_relax_shared(const RelaxArgs& a, const float* ush, const float* ghs,
 // equals the shared row there, whose terms enter the slice's sums once per such row.  A
 // wavefront first tests, with scalar instructions, whether a row's cone reaches the band of node
 // rows its positions lie in, and skips it otherwise.  Cone entries outside the node are left to
-// k_cone_zero.
+// the convolution that wrote the cone (or k_cone_zero).
 template <int CG>
 __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, PatchGeom gc, const RowDesc* rows,
                                                     const float* ush, const float* ghs, const float* apw, float* Gd) {
@@ -387,32 +387,36 @@ __global__ __launch_bounds__(256) void k_relax_cone(RelaxArgs a, PatchGeom gw, P
     }
 }
 
-// Cone entries outside the node hold 0 (the next convolution reads them as padding): one workgroup
-// per row, its lanes over the cone positions (consecutive lanes, consecutive entries), each
-// position outside the node zeroed in every channel.
-__global__ __launch_bounds__(256) void k_cone_zero(PatchGeom gc, const RowDesc* rows, float* Gd, float inv_p) {
-    const long r = blockIdx.x;
+// Cone entries outside the node hold 0 (the next convolution reads them as padding): workgroups
+// stride over the rows, their lanes over a row's cone positions (consecutive lanes, consecutive
+// entries), each position outside the node zeroed in every channel.
+__global__ __launch_bounds__(256) void k_cone_zero(PatchGeom gc, const RowDesc* rows, int M, float* Gd, float inv_p) {
     const int Pc = gc.P, PP = Pc * Pc;
-    int oy, ox;
-    patch_origin(gc, rows[r].j, oy, ox);
-    // a cone inside the node has nothing to clear
-    if (oy >= 0 && ox >= 0 && oy + Pc <= gc.H && ox + Pc <= gc.W) return;
-    float* base = Gd + r * gc.C * PP;
-    for (int q = threadIdx.x; q < PP; q += 256) {
-        const int dy = (int)(((float)q + 0.5f) * inv_p), dx = q - dy * Pc;
-        const int Y = oy + dy, X = ox + dx;
-        if (Y >= 0 && Y < gc.H && X >= 0 && X < gc.W) continue;
-        for (int c = 0; c < gc.C; ++c) base[(long)c * PP + q] = 0.f;
+    for (long r = blockIdx.x; r < M; r += gridDim.x) {
+        int oy, ox;
+        patch_origin(gc, rows[r].j, oy, ox);
+        // a cone inside the node has nothing to clear
+        if (oy >= 0 && ox >= 0 && oy + Pc <= gc.H && ox + Pc <= gc.W) continue;
+        float* base = Gd + r * gc.C * PP;
+        for (int q = threadIdx.x; q < PP; q += 256) {
+            const int dy = (int)(((float)q + 0.5f) * inv_p), dx = q - dy * Pc;
+            const int Y = oy + dy, X = ox + dx;
+            if (Y >= 0 && Y < gc.H && X >= 0 && X < gc.W) continue;
+            for (int c = 0; c < gc.C; ++c) base[(long)c * PP + q] = 0.f;
+        }
     }
+}
+
+void launch_cone_zero(const PatchGeom& gc, const RowDesc* rows, int M, float* Gd, hipStream_t st) {
+    if (M <= 0) return;
+    hipLaunchKernelGGL(k_cone_zero, dim3((unsigned)std::min(M, 2048)), dim3(256), 0, st, gc, rows, M, Gd,
+                       1.f / (float)gc.P);
+    MNB_HIP(hipGetLastError());
 }
 
 void launch_relax_cone(const RelaxArgs& a, const PatchGeom& gw, const PatchGeom& gc, const RowDesc* rows,
                        const float* ush, const float* ghs, const float* apw, float* Gd, hipStream_t st) {
     if (a.n_inst <= 0) return;
-    if (a.M > 0) {
-        hipLaunchKernelGGL(k_cone_zero, dim3((unsigned)a.M), dim3(256), 0, st, gc, rows, Gd, 1.f / (float)gc.P);
-        MNB_HIP(hipGetLastError());
-    }
     const int HW = gc.H * gc.W;
     if (a.n_slices <= 0) {
         // no rows: the sums below are zero
