@@ -50,7 +50,8 @@ TRAFFIC = {
     ("convsmall", "bottom", None): ("bottom_convsmall_traffic.json",
                ("bottom_mf.hip", "bottom.hip", "bottom.h", "common.h", "engine.hip")),
     ("convbig", "conv_forward", 3): ("conv2_forward_convbig_traffic.json",
-                     ("gemm.hip", "kernels.h", "common.h", "engine.hip", "engine_calls.inc", "patch.hip")),
+                     ("conv_win.hip", "gemm.hip", "kernels.h", "common.h", "engine.hip", "engine_calls.inc",
+                      "patch.hip")),
 }
 
 

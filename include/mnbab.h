@@ -352,7 +352,7 @@ int mnb_sync(void);
  * gradient / a' row written plus d0 x* bytes; MNB_T_BOTTOM_WIN (its
  * window-sparse form for rows whose objective is ReLU layer 1) 2 * rows *
  * (window positions x first-layer channels x taps) flops, doubled with the
- * adjoint. */
+ * adjoint.  Calls without rows (nothing launched) are not counted. */
 enum { MNB_T_FC_BACKSUB = 1, MNB_T_CONV_BACKSUB = 2, MNB_T_FC_FORWARD = 3, MNB_T_CONV_FORWARD = 4,
        MNB_T_FOLD = 5, MNB_T_RELAX = 6, MNB_T_CONCRETIZE = 7, MNB_T_BOTTOM = 8,
        MNB_T_BOTTOM_WIN = 9 };

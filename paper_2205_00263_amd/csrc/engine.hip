@@ -89,6 +89,7 @@ static thread_local int t_timer_node = -1;
 
 TimerScope::TimerScope(int kind, int node, double flops, double bytes) {
     if (!g_timer.running || g_timer.kind != kind || (g_timer.node >= 0 && g_timer.node != node)) return;
+    if (flops <= 0.0 && bytes <= 0.0) return;   // no rows: nothing is launched
     if (g_timer.used == g_timer.ev.size()) {
         hipEvent_t a, b;
         MNB_HIP(hipEventCreate(&a));
