@@ -31,9 +31,6 @@ constexpr int CG = 8;          // input channels per LDS stage
 constexpr int NLD4 = 6;        // float4 window loads per thread and stage, at most
 constexpr int NLD1 = 12;       // scalar window loads per thread and stage, at most
 constexpr size_t WIN_LDS_MAX = 64 * 1024;
-#ifndef MNB_WIN_TAP_UNROLL
-#define MNB_WIN_TAP_UNROLL 1
-#endif
 
 struct ConvWinArgs {
     const float* G; float* C; const float* Wt; const float* bias;   // bias nullable
@@ -53,13 +50,16 @@ struct ConvWinArgs {
 
 template <int BN> struct WinB { static constexpr int BNP = BN + 16; };   // filter row stride: 16 mod 32 banks
 
-template <int K, int S, int BM, int BN, int VEC, int NPH>
+template <int K, int S, int BM, int BN, int VEC, int NPH, int NSPLIT>
 __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     constexpr int KK = K * K;
-    // NPH == 1: the four wavefronts split the tile's positions and channels; NPH == 4: wavefront f
-    // computes the whole tile of stride phase f
-    constexpr int WAVES_N = NPH == 1 ? BN / 32 : 1, WAVES_M = NPH == 1 ? 4 / WAVES_N : 1;
-    constexpr int FN = NPH == 1 ? 2 : BN / 16, FM = BM / (16 * WAVES_M);
+    // NPH == 1: the four wavefronts split the tile's positions and channels (NSPLIT: channels
+    // only, each wavefront taking every position of the tile); NPH == 4: wavefront f computes the
+    // whole tile of stride phase f
+    constexpr int WAVES_N = NSPLIT ? 4 : NPH == 1 ? BN / 32 : 1;
+    constexpr int WAVES_M = NSPLIT ? 1 : NPH == 1 ? 4 / WAVES_N : 1;
+    constexpr int FN = NSPLIT ? BN / 64 : NPH == 1 ? 2 : BN / 16, FM = BM / (16 * WAVES_M);
+    static_assert(!NSPLIT || (NPH == 1 && FN >= 1 && FN * 64 == BN), "channel split");
     static_assert(FM >= 1 && FM * 16 * WAVES_M == BM, "tile");
     static_assert(NPH == 1 || (NPH == 4 && S == 1), "phases");
     constexpr int NLD = VEC == 4 ? NLD4 : NLD1;
@@ -77,6 +77,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // wavefront's position and channel block (NPH == 4: the whole tile, for phase `wave`)
     const int wm = NPH == 1 ? wave % WAVES_M : 0, wn = NPH == 1 ? wave / WAVES_M : 0;
+    constexpr int WNC = FN * 16;   // channels per wavefront
     const int r = blockIdx.x / a.mtiles, mt = blockIdx.x - r * a.mtiles;
     const int n0 = blockIdx.y * BN;
     const int P = a.Ho * a.Wo, m0 = mt * BM;
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
             xb[i] += S * (y - y_first) * a.RS + x;
         }
     }
-    const int wb = (lane >> 4) * BNP + wn * 32 + (lane & 15);
+    const int wb = (lane >> 4) * BNP + wn * WNC + (lane & 15);
     // this wavefront's phase: extra window rows above its first one, column offset, output origin
     int row_off = 0, c0p = a.CO - a.px, out_y0 = a.out_y0, out_x0 = a.out_x0;
     if constexpr (NPH == 4) {
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
         if (g + 1 < ng) MNB_WIN_LOAD(g + 1)
         // taps as a loop (not unrolled): unrolled, the compiler keeps every tap's LDS addresses in
         // registers across the stages, which halves the wavefronts a SIMD can hold
-#pragma unroll MNB_WIN_TAP_UNROLL
+#pragma unroll 1
         for (int t = 0; t < KK; ++t) {
             const int ky = t / K, kx = t - ky * K;
             const int tc = kx + c0p;
@@ -224,8 +225,8 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            bias[j][v] = a.bias ? a.bias[n0 + wn * 32 + j * 16 + 4 * (lane >> 4) + v] : 0.f;
-    float* Cr = a.C + (long)r * a.ldC + (long)(n0 + wn * 32 + 4 * (lane >> 4)) * a.out_ns;
+            bias[j][v] = a.bias ? a.bias[n0 + wn * WNC + j * 16 + 4 * (lane >> 4) + v] : 0.f;
+    float* Cr = a.C + (long)r * a.ldC + (long)(n0 + wn * WNC + 4 * (lane >> 4)) * a.out_ns;
     int moff[FM];
     bool mzero[FM];   // position outside the node of a cone row: written 0
     int coy = 0, cox = 0;
@@ -301,6 +302,9 @@ struct WinConv {
     // out_y0 / out_x0 above are then unused
     int nph;
     int ph_py[4], ph_px[4], ph_y0[4], ph_x0[4];
+    // only the whole-grid tile (grids of 129 to 144 positions, 64 channels at a time, 3x3 / 1):
+    // every position of a row in one workgroup, its wavefronts split along the channels
+    bool only_grid;
 };
 
 bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool check_only) {
@@ -312,9 +316,13 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     if (!(ks31 || ks42 || ks32 || ks21) || w.Ho <= 0 || w.Wo <= 0) return false;
     if (nph == 4 && !ks21) return false;
     const int P = w.Ho * w.Wo;
-    // positions per workgroup: 128, unless 64 wastes fewer lanes on the last tile (or a wavefront
-    // holding a whole tile of 64 channels would need more accumulators)
-    const int BM = cdiv(P, 64) * 64 < cdiv(P, 128) * 128 || (nph == 4 && BN == 64) ? 64 : 128;
+    // grids of 129 to 144 positions: one workgroup per row holds them all (9 fragments per
+    // wavefront, no idle tile), its filters staged once per row
+    const bool grid = nph == 1 && BN == 64 && ks31 && P > 128 && P <= 144;
+    if (w.only_grid && !grid) return false;
+    // otherwise positions per workgroup: 128, unless 64 wastes fewer lanes on the last tile (or a
+    // wavefront holding a whole tile of 64 channels would need more accumulators)
+    const int BM = grid ? 144 : cdiv(P, 64) * 64 < cdiv(P, 128) * 128 || (nph == 4 && BN == 64) ? 64 : 128;
     // phases in one workgroup: the window spans every phase's rows and columns
     int py = w.py, px = w.px, extra = 0;
     if (nph == 4) {
@@ -372,9 +380,15 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     if (loads > 256L * (vec ? NLD4 : NLD1)) return false;
     if ((long)M * mtiles > 0x7fffffffL) return false;
     if (check_only || M <= 0) return true;
-    const dim3 grid((unsigned)(M * mtiles), w.Cout / BN), blk(256);
+    const dim3 dgrid((unsigned)(M * mtiles), w.Cout / BN), blk(256);
+    if (grid) {
+        if (vec) hipLaunchKernelGGL((k_conv_win<3, 1, 144, 64, 4, 1, 1>), dgrid, blk, lds, st, a);
+        else hipLaunchKernelGGL((k_conv_win<3, 1, 144, 64, 1, 1, 1>), dgrid, blk, lds, st, a);
+        MNB_HIP(hipGetLastError());
+        return true;
+    }
     if (nph == 4) {
-#define MNB_WIN4(BM_, BN_, V_) hipLaunchKernelGGL((k_conv_win<2, 1, BM_, BN_, V_, 4>), grid, blk, lds, st, a)
+#define MNB_WIN4(BM_, BN_, V_) hipLaunchKernelGGL((k_conv_win<2, 1, BM_, BN_, V_, 4, 0>), dgrid, blk, lds, st, a)
         if (BN == 64) { if (vec) MNB_WIN4(64, 64, 4); else MNB_WIN4(64, 64, 1); }
         else if (BM == 128) { if (vec) MNB_WIN4(128, 32, 4); else MNB_WIN4(128, 32, 1); }
         else { if (vec) MNB_WIN4(64, 32, 4); else MNB_WIN4(64, 32, 1); }
@@ -383,7 +397,7 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
         return true;
     }
 #define MNB_WIN(K_, S_, BM_, BN_, V_) \
-    hipLaunchKernelGGL((k_conv_win<K_, S_, BM_, BN_, V_, 1>), grid, blk, lds, st, a)
+    hipLaunchKernelGGL((k_conv_win<K_, S_, BM_, BN_, V_, 1, 0>), dgrid, blk, lds, st, a)
 #define MNB_WIN_V(K_, S_, BM_, BN_) \
     if (vec) MNB_WIN(K_, S_, BM_, BN_, 4); else MNB_WIN(K_, S_, BM_, BN_, 1)
 #define MNB_WIN_T(K_, S_)                                                   \
@@ -400,18 +414,20 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     return true;
 }
 
-// Forward convolutions of input planes of at most this many elements stay with the gather GEMM: the
+// Forward convolutions of input planes of at most this many elements stay with the gather GEMM (the
 // plane stays in the caches between its re-reads, and the window kernel's filter staging weighs
-// more on the few positions of a tile (measured on ConvBig's 10x10 -> 12x12 forward cones).  The
-// transposed convolutions gain from the window kernel at every plane size measured (8x8 and up).
+// more on the few positions of a tile), unless the whole output grid fits one workgroup's tile
+// (ConvBig's 10x10 -> 12x12 forward cones).  The transposed convolutions gain from the window
+// kernel at every plane size measured (8x8 and up).
 constexpr int WIN_MIN_PLANE = 129;
 
 }  // namespace
 
 bool launch_conv_forward_win(const ConvGeom& g, const float* G, float* C, int M, bool accumulate, hipStream_t st,
                              const ConeClip* clip) {
-    if ((kernel_variants() & MNB_VAR_NO_WIN_CONV) != 0 || g.Hi * g.Wi < WIN_MIN_PLANE || g.p < 0) return false;
+    if ((kernel_variants() & MNB_VAR_NO_WIN_CONV) != 0 || g.p < 0) return false;
     WinConv w{};
+    w.only_grid = g.Hi * g.Wi < WIN_MIN_PLANE;
     w.G = G; w.C = C; w.Wt = g.Wt; w.bias = g.b;
     w.Cin = g.Ci; w.Hi = g.Hi; w.Wi = g.Wi; w.Cout = g.Co; w.Ho = g.Ho; w.Wo = g.Wo;
     w.K = g.k; w.S = g.s; w.py = g.p; w.px = g.p;
