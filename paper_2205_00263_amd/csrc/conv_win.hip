@@ -46,7 +46,13 @@ struct ConvWinArgs {
     int ph_py[4], ph_px[4], ph_y0[4], ph_x0[4];
     int wh_extra;
     ConeClip clip;   // forward convolutions of cone rows (clip.rows null: none)
+    float rWo, rQ;   // 1 / Wo and 1 / (window entries per input row staged): see qdiv
 };
+
+// i / d for 0 <= i < 2^21 through r = 1 / d (correctly rounded): (i + 0.5) / d lies at least
+// 0.5 / d from an integer, and the product's error, about 2^-22 of the quotient, stays far below
+// that; an integer division by a runtime divisor would cost ~30 instructions per use.
+__device__ __forceinline__ int qdiv(int i, float r) { return (int)(((float)i + 0.5f) * r); }
 
 template <int BN> struct WinB { static constexpr int BNP = BN + 16; };   // filter row stride: 16 mod 32 banks
 
@@ -93,6 +99,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     // such a slot still loads the row's first element, so that no load is conditional)
     const int Q = a.Wi / VEC;
     const int per_c = nvr * Q, total = CG * per_c;
+    const float rpc = 1.f / (float)max(per_c, 1);
     int goff[NLD], loff[NLD];
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
@@ -100,8 +107,8 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
         goff[i] = 0;
         loff[i] = -1;
         if (e < total) {
-            const int c = e / per_c, rem = e - c * per_c;
-            const int row = rem / Q, q = rem - row * Q;
+            const int c = qdiv(e, rpc), rem = e - c * per_c;
+            const int row = qdiv(rem, a.rQ), q = rem - row * Q;
             const int j = q * VEC + a.CO;
             goff[i] = (int)(c * HiWi) + (iy0 + wy_lo + row) * a.Wi + q * VEC;
             loff[i] = c * a.PL + (wy_lo + row) * a.RS + (VEC == 4 ? j / S : (j % S) * a.WS + j / S);
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
         const int m = m0 + wm * FM * 16 + i * 16 + (lane & 15);
         xb[i] = (lane >> 4) * a.PL;
         if (m < P) {
-            const int y = m / a.Wo, x = m - y * a.Wo;
+            const int y = qdiv(m, a.rWo), x = m - y * a.Wo;
             xb[i] += S * (y - y_first) * a.RS + x;
         }
     }
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int m = m0 + wm * FM * 16 + i * 16 + (lane & 15);
-        const int y = m / a.Wo, x = m - y * a.Wo;
+        const int y = qdiv(m, a.rWo), x = m - y * a.Wo;
         moff[i] = m < P ? (out_y0 + a.out_s * y) * a.out_rs + out_x0 + a.out_s * x : -1;
         mzero[i] = a.clip.rows && !(coy + y >= 0 && coy + y < a.clip.H && cox + x >= 0 && cox + x < a.clip.W);
     }
@@ -356,6 +363,7 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     a.mtiles = mtiles; a.acc = accumulate;
     a.out_ns = w.out_ns; a.out_rs = w.out_rs; a.out_y0 = w.out_y0; a.out_x0 = w.out_x0; a.out_s = w.out_s;
     a.clip = w.clip;
+    a.rWo = 1.f / (float)w.Wo;
     a.CO = px > 0 ? (px + 3) & ~3 : 0;
     int pxlo = px;
     if (nph == 4)
@@ -376,6 +384,7 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     if (lds > WIN_LDS_MAX) return false;
     // window loads per thread and stage
     const int Q = vec ? w.Wi / 4 : w.Wi;
+    a.rQ = 1.f / (float)Q;
     const long loads = (long)CG * std::min(WHmax, w.Hi) * Q;
     if (loads > 256L * (vec ? NLD4 : NLD1)) return false;
     if ((long)M * mtiles > 0x7fffffffL) return false;
