@@ -1,5 +1,6 @@
 // Windowed implicit-GEMM convolution: the forward product of the adjoint (x* through a
-// convolutional layer, the transpose of the back-substitution of Eq. 2).
+// convolutional layer) and, one stride phase at a time or four phases per workgroup, the
+// transposed convolution of back-substitution (Eq. 2).
 //
 // One workgroup owns one row and a tile of BM output positions of the layer (whole output rows
 // where they fit).  For 8 input channels at a time it stages the input window those positions
