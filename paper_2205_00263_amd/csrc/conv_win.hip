@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     typedef typename std::conditional<VEC == 4, floatx4, float>::type vec_t;
 
     extern __shared__ float sm[];
-    float* s_w = sm;                    // [KK][CG][BNP]
+    float* s_w = sm;                    // [NPH][KK][CG][BNP]
     float* s_x = sm + WROWS * BNP;      // [CG][PL]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
