@@ -17,6 +17,7 @@ namespace mnb {
 
 constexpr int FT = 256;     // threads per workgroup
 constexpr int FCO = 8;      // transposed: layer output channels staged per step
+constexpr int SB = 8;       // staging loads in flight per thread
 
 // Output tile of one row: TW x TH positions, each thread two horizontally adjacent ones
 // (TW even, TW / 2 * TH <= FT); RB rows per workgroup.
@@ -36,6 +37,62 @@ static FirstTile first_tile(int H, int W) {
 // i / d for 0 <= i < 2^16, 0 < d <= 2^10 through a float reciprocal: (i + 0.5) / d lies at least
 // 0.5 / d from an integer, far above the rounding of the product.
 __device__ __forceinline__ int fdivs(int i, float rd) { return (int)(((float)i + 0.5f) * rd); }
+
+// The transposed convolution's products for one thread's output pair over nco staged channels:
+// ap points at the pair's window (rows dy0.., columns dx0..) of the first staged channel, channel
+// planes win floats apart.  Channels, then ky, then kx: every tile shape sums in this order.
+template <int CI, int K>
+__device__ __forceinline__ void convT_first_taps(const float* ap, int win, int WX, const float* __restrict__ W,
+                                                 int c0, int nco, float (&o0)[CI], float (&o1)[CI]) {
+#pragma unroll 2
+    for (int co = 0; co < nco; ++co) {
+        const float* wrow = W + (long)(c0 + co) * CI * K * K;
+#pragma unroll
+        for (int ky = 0; ky < K; ++ky) {
+            // A[y][x] with y = Y + p - ky sits at window row (K - 1 - ky) + dy0; the pair's
+            // columns for taps kx are (K - 1 - kx) + dx0 + {0, 1}
+            float a[K + 1];
+#pragma unroll
+            for (int q = 0; q <= K; ++q) a[q] = ap[co * win + (K - 1 - ky) * WX + q];
+#pragma unroll
+            for (int kx = 0; kx < K; ++kx)
+#pragma unroll
+                for (int c = 0; c < CI; ++c) {
+                    const float w = wrow[(c * K + ky) * K + kx];
+                    o0[c] += a[K - 1 - kx] * w;
+                    o1[c] += a[K - kx] * w;
+                }
+        }
+    }
+}
+
+// Store (or add to) one thread's output pair at (Y, X), X + 1 of row r.
+template <int CI>
+__device__ __forceinline__ void convT_first_store(float* __restrict__ C, long r, int Hi, int Wi, int Y, int X,
+                                                  int acc, float (&o0)[CI], float (&o1)[CI]) {
+    float* Cr = C + r * (long)CI * Hi * Wi + (long)Y * Wi + X;
+    if (acc) {
+        // all previous values in flight together (a position past the plane reads its row's last)
+        const int e0 = X < Wi ? 0 : Wi - 1 - X, e1 = X + 1 < Wi ? 1 : Wi - 1 - X;
+        float p0[CI], p1[CI];
+#pragma unroll
+        for (int c = 0; c < CI; ++c) {
+            p0[c] = Cr[(long)c * Hi * Wi + e0];
+            p1[c] = Cr[(long)c * Hi * Wi + e1];
+        }
+#pragma unroll
+        for (int c = 0; c < CI; ++c) {
+            o0[c] += p0[c];
+            o1[c] += p1[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CI; ++c) {
+        float* q = Cr + (long)c * Hi * Wi;
+        if (X < Wi) q[0] = o0[c];
+        if (X + 1 < Wi) q[1] = o1[c];
+    }
+}
 
 // out[r][ci][Y][X] (+)= sum_{co, ky, kx} A[r][co][Y + p - ky][X + p - kx] W[co][ci][ky][kx]
 // (A positions outside [0, Ho) x [0, Wo) are absent).
@@ -67,18 +124,28 @@ __global__ __launch_bounds__(FT) void k_convT_first(const float* __restrict__ A,
     float o0[CI], o1[CI];
 #pragma unroll
     for (int c = 0; c < CI; ++c) o0[c] = o1[c] = 0.f;
+    const int nrr = FCO * WY;
     for (int c0 = 0; c0 < Co; c0 += FCO) {
         __syncthreads();   // the previous channels' window is consumed
         if (rb < t.RB && RP > 0) {
-            // a fixed window column per thread, RP window rows per pass
+            // a fixed window column per thread, RP window rows per pass; SB passes' loads in flight
+            // together (every lane loads, from element 0 of its row where the position is absent,
+            // and selects afterwards: a load under a branch would wait before the next one)
             if (srow < RP) {
-#pragma unroll 4
-                for (int rr = srow; rr < FCO * WY; rr += RP) {
-                    const int co = fdivs(rr, rWY), wy = rr - co * WY;   // independent passes: loads batch
-                    const int y = y0 + wy;
-                    float v = 0.f;
-                    if (sxok && c0 + co < Co && y >= 0 && y < Ho) v = Ar[(long)(c0 + co) * HoWo + y * Wo + sx];
-                    s_a[rr * WX + scol] = v;
+                for (int rr0 = srow; rr0 < nrr; rr0 += SB * RP) {
+                    float v[SB];
+#pragma unroll
+                    for (int u = 0; u < SB; ++u) {
+                        const int rr = rr0 + u * RP;
+                        const int co = fdivs(rr, rWY), wy = rr - co * WY;
+                        const int y = y0 + wy;
+                        const bool ok = sxok && rr < nrr && c0 + co < Co && y >= 0 && y < Ho;
+                        const float x = Ar[ok ? (long)(c0 + co) * HoWo + y * Wo + sx : 0];
+                        v[u] = ok ? x : 0.f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < SB; ++u)
+                        if (rr0 + u * RP < nrr) s_a[(rr0 + u * RP) * WX + scol] = v[u];
                 }
             }
         } else if (rb < t.RB) {
@@ -94,36 +161,85 @@ __global__ __launch_bounds__(FT) void k_convT_first(const float* __restrict__ A,
         }
         __syncthreads();
         const int nco = Co - c0 < FCO ? Co - c0 : FCO;
-        const float* ap = s_a + dy0 * WX + dx0;
-#pragma unroll 2
-        for (int co = 0; co < nco; ++co) {
-            const float* wrow = W + (long)(c0 + co) * CI * K * K;
-#pragma unroll
-            for (int ky = 0; ky < K; ++ky) {
-                // A[y][x] with y = Y + p - ky sits at window row (K - 1 - ky) + dy0; the pair's
-                // columns for taps kx are (K - 1 - kx) + dx0 + {0, 1}
-                float a[K + 1];
-#pragma unroll
-                for (int q = 0; q <= K; ++q) a[q] = ap[co * win + (K - 1 - ky) * WX + q];
-#pragma unroll
-                for (int kx = 0; kx < K; ++kx)
-#pragma unroll
-                    for (int c = 0; c < CI; ++c) {
-                        const float w = wrow[(c * K + ky) * K + kx];
-                        o0[c] += a[K - 1 - kx] * w;
-                        o1[c] += a[K - kx] * w;
-                    }
-            }
-        }
+        convT_first_taps<CI, K>(s_a + dy0 * WX + dx0, win, WX, W, c0, nco, o0, o1);
     }
     if (!act || Y >= Hi) return;
-    float* Cr = C + r * (long)CI * Hi * Wi + (long)Y * Wi + X;
+    convT_first_store<CI>(C, r, Hi, Wi, Y, X, acc, o0, o1);
+}
+
+// Zero source for the direct staging below: window positions outside the layer output (and rows
+// past the batch) load from here.
+__device__ float g_first_zero[64] = {};
+
+// The same transposed convolution for tiles whose row blocks fill whole wavefronts (per a
+// multiple of 64): the window is staged by direct global-to-LDS loads (no registers hold the data
+// in flight, so a stage's loads all issue at once), FC channels per stage, double-buffered: the
+// next stage's loads are in flight while this stage's products run.  Thread pix stages window
+// column scol of rows srow, srow + RP, ...; a wavefront's lanes then write consecutive LDS words,
+// which is the direct load's layout.  Lanes with srow >= RP write rows that a lower lane writes
+// again one pass later, with the same value; rows past the stage read the zero source and land
+// past the window (the buffer holds RWP >= every pass's slots).  A pass's source offset within
+// the stage's channels is the same for every stage, so it is computed once (NP <= NPX passes, Co
+// a multiple of FC: both checked by the launch).  Sums in the order above.
+template <int CI, int K, int FC, int NPX>
+__global__ __launch_bounds__(FT) void k_convT_first_dma(const float* __restrict__ A, float* __restrict__ C,
+                                                        const float* __restrict__ W, int M, int Hi, int Wi, int Co,
+                                                        int Ho, int Wo, int p, int acc, FirstTile t, int RWP) {
+    extern __shared__ float sm[];
+    const int WY = t.TH + K - 1, WX = t.TW + K, win = WY * WX;
+    const int per = t.TW / 2 * t.TH;
+    const int rb = threadIdx.x / per, pix = threadIdx.x - rb * per;
+    const int tile = blockIdx.x % (t.tiles_x * t.tiles_y);
+    const long r = (long)(blockIdx.x / (t.tiles_x * t.tiles_y)) * t.RB + rb;
+    const int ty0 = (tile / t.tiles_x) * t.TH, tx0 = (tile % t.tiles_x) * t.TW;
+    const int dy0 = pix / (t.TW / 2), dx0 = 2 * (pix % (t.TW / 2));
+    const int Y = ty0 + dy0, X = tx0 + dx0;
+    const bool live = rb < t.RB;   // uniform per wavefront
+    const bool act = live && r < M;
+    const int y0 = ty0 + p - (K - 1), x0 = tx0 + p - (K - 1);
+    float* s_a = sm + (live ? rb : 0) * RWP;   // buffer 0 of this row; buffer 1 t.RB * RWP further
+    const int bstride = t.RB * RWP;
+    const float* Ar = A + (act ? r : 0) * (long)Co * Ho * Wo;
+    const int HoWo = Ho * Wo;
+    const float rWX = 1.f / (float)WX, rWY = 1.f / (float)WY;
+    const int RP = per / WX;   // >= 1 (checked by the launch)
+    const int srow = fdivs(pix, rWX), scol = pix - srow * WX;
+    const int sx = x0 + scol;
+    const bool sxok = r < M && sx >= 0 && sx < Wo;
+    const int nrr = FC * WY, NP = (nrr + RP - 1) / RP;
+    const int wbase = __builtin_amdgcn_readfirstlane(pix & ~63);
+    const float* zero = g_first_zero + (threadIdx.x & 63);
+    int poff[NPX];   // offset of pass u's element from the stage's first channel plane, or -1
 #pragma unroll
-    for (int c = 0; c < CI; ++c) {
-        float* q = Cr + (long)c * Hi * Wi;
-        if (X < Wi) q[0] = acc ? q[0] + o0[c] : o0[c];
-        if (X + 1 < Wi) q[1] = acc ? q[1] + o1[c] : o1[c];
+    for (int u = 0; u < NPX; ++u) {
+        const int rr = srow + u * RP;
+        const int co = fdivs(rr, rWY), wy = rr - co * WY;
+        const int y = y0 + wy;
+        poff[u] = sxok && rr < nrr && y >= 0 && y < Ho ? co * HoWo + y * Wo + sx : -1;
     }
+    auto stage = [&](int c0, float* buf) {
+        if (!live) return;
+        const float* base = Ar + (long)c0 * HoWo;
+#pragma unroll
+        for (int u = 0; u < NPX; ++u)
+            if (u < NP)
+                __builtin_amdgcn_global_load_lds(poff[u] >= 0 ? base + poff[u] : zero, buf + wbase + u * RP * WX, 4,
+                                                 0, 0);
+    };
+    float o0[CI], o1[CI];
+#pragma unroll
+    for (int c = 0; c < CI; ++c) o0[c] = o1[c] = 0.f;
+    stage(0, s_a);
+    int cur = 0;
+    for (int c0 = 0; c0 < Co; c0 += FC) {
+        vmem_drain();      // this thread's loads of the stage have reached LDS
+        __syncthreads();   // everyone's; and the other buffer's products are done
+        if (c0 + FC < Co) stage(c0 + FC, s_a + (cur ^ 1) * bstride);
+        if (live) convT_first_taps<CI, K>(s_a + cur * bstride + dy0 * WX + dx0, win, WX, W, c0, FC, o0, o1);
+        cur ^= 1;
+    }
+    if (!act || Y >= Hi) return;
+    convT_first_store<CI>(C, r, Hi, Wi, Y, X, acc, o0, o1);
 }
 
 // out[r][co][y][x] (+)= b[co] + sum_{ci, ky, kx} W[co][ci][ky][kx] G[r][ci][y - p + ky][x - p + kx]
@@ -148,13 +264,23 @@ __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, 
     const float* Gr = G + (r < M ? r : 0) * (long)CI * Hi * Wi;
     const float rWX = 1.f / (float)WX, rWY = 1.f / (float)WY;
     if (rb < t.RB) {
-        for (int i = pix; i < CI * win; i += per) {
-            const int wr = fdivs(i, rWX), wx = i - wr * WX;
-            const int ci = fdivs(wr, rWY), wy = wr - ci * WY;
-            const int Y = Y0 + wy, X = X0 + wx;
-            float v = 0.f;
-            if (r < M && Y >= 0 && Y < Hi && X >= 0 && X < Wi) v = Gr[(long)ci * Hi * Wi + Y * Wi + X];
-            s_g[i] = v;
+        // SB loads in flight together, selected afterwards (as in the transposed kernel)
+        const int n = CI * win;
+        for (int i0 = pix; i0 < n; i0 += SB * per) {
+            float v[SB];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int i = i0 + u * per;
+                const int wr = fdivs(i, rWX), wx = i - wr * WX;
+                const int ci = fdivs(wr, rWY), wy = wr - ci * WY;
+                const int Y = Y0 + wy, X = X0 + wx;
+                const bool ok = r < M && i < n && Y >= 0 && Y < Hi && X >= 0 && X < Wi;
+                const float x = Gr[ok ? (long)ci * Hi * Wi + Y * Wi + X : 0];
+                v[u] = ok ? x : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+                if (i0 + u * per < n) s_g[i0 + u * per] = v[u];
         }
     }
     __syncthreads();
@@ -205,9 +331,34 @@ bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool
     if (g.s != 1 || g.Ci > 4 || g.k != 3 || (kernel_variants() & MNB_VAR_NO_FIRST_CONV)) return false;
     if (M <= 0) return true;
     const FirstTile t = first_tile(g.Hi, g.Wi);
-    const size_t lds = (size_t)t.RB * FCO * (t.TH + 2) * (t.TW + 3) * sizeof(float);
     const long blocks = (long)cdiv(M, t.RB) * t.tiles_x * t.tiles_y;
     MNB_CHECK(blocks < (1L << 31), MNB_EDEVICE, "first-layer transposed convolution: grid too large");
+    {
+        // direct staging where a row block is whole wavefronts
+        constexpr int FCD = 4, NPX = 12;
+        const int per = t.TW / 2 * t.TH, WX = t.TW + 3, WY = t.TH + 2, RP = per / WX;
+        const int NP = RP > 0 ? cdiv(FCD * WY, RP) : 0;
+        if (per % 64 == 0 && RP > 0 && NP <= NPX && g.Co % FCD == 0 &&
+            (long)g.Co * g.Ho * g.Wo < (1L << 31)) {
+            const int RWP = std::max((NP - 1) * RP * WX + per, FCD * WY * WX);
+            const size_t lds = (size_t)2 * t.RB * RWP * sizeof(float);
+            if (lds <= 64 * 1024) {
+#define MNB_CTD(CI_)                                                                                                \
+    hipLaunchKernelGGL((k_convT_first_dma<CI_, 3, FCD, NPX>), dim3((unsigned)blocks), dim3(FT), lds, st, A, C, g.W, M, \
+                       g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, RWP)
+                switch (g.Ci) {
+                    case 1: MNB_CTD(1); break;
+                    case 2: MNB_CTD(2); break;
+                    case 3: MNB_CTD(3); break;
+                    default: MNB_CTD(4); break;
+                }
+#undef MNB_CTD
+                MNB_HIP(hipGetLastError());
+                return true;
+            }
+        }
+    }
+    const size_t lds = (size_t)t.RB * FCO * (t.TH + 2) * (t.TW + 3) * sizeof(float);
 #define MNB_CTF(CI_)                                                                                              \
     hipLaunchKernelGGL((k_convT_first<CI_, 3>), dim3((unsigned)blocks), dim3(FT), lds, st, A, C, g.W, M, g.Hi, g.Wi, \
                        g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t)

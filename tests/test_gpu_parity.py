@@ -45,6 +45,8 @@ CONV_GEOMS = [  # (Ci, H, Co, k, s, p)
     # first layers of receptive-field windows (padding 0) and forward cones (padding 2)
     (3, 16, 32, 3, 1, 0), (3, 16, 32, 3, 1, 2), (3, 10, 32, 3, 1, 2), (3, 6, 32, 3, 1, 0),
     (1, 12, 8, 3, 1, 1), (4, 7, 24, 3, 1, 1), (2, 40, 8, 3, 1, 1),
+    # channel counts that leave a partial last stage (direct-staged and register-staged tiles)
+    (3, 16, 6, 3, 1, 1), (2, 20, 10, 3, 1, 0),
     # forward cones of ConvBig's second and third convolutions (padding 2)
     (32, 18, 32, 4, 2, 2), (32, 10, 64, 3, 1, 2),
 ]
