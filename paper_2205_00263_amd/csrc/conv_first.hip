@@ -171,71 +171,68 @@ __global__ __launch_bounds__(FT) void k_convT_first(const float* __restrict__ A,
 // past the batch) load from here.
 __device__ float g_first_zero[64] = {};
 
-// The same transposed convolution for tiles whose row blocks fill whole wavefronts (per a
-// multiple of 64): the window is staged by direct global-to-LDS loads (no registers hold the data
-// in flight, so a stage's loads all issue at once), FC channels per stage, double-buffered: the
-// next stage's loads are in flight while this stage's products run.  Thread pix stages window
-// column scol of rows srow, srow + RP, ...; a wavefront's lanes then write consecutive LDS words,
-// which is the direct load's layout.  Lanes with srow >= RP write rows that a lower lane writes
-// again one pass later, with the same value; rows past the stage read the zero source and land
-// past the window (the buffer holds RWP >= every pass's slots).  A pass's source offset within
-// the stage's channels is the same for every stage, so it is computed once (NP <= NPX passes, Co
-// a multiple of FC: both checked by the launch).  Sums in the order above.
+// The same transposed convolution with the window staged by direct global-to-LDS loads: no
+// registers hold the data in flight, so a stage's loads all issue at once; FC channels per stage,
+// double-buffered, the next stage's loads in flight while this stage's products run.  The block's
+// RB windows of FC channel planes lie in LDS as in the kernel above; thread t stages elements t,
+// t + FT, ... of that range, so a wavefront's lanes write consecutive words (the direct load's
+// layout).  An element's source offset within the stage's channels is the same for every stage
+// and is computed once (NPE <= NPX passes, Co a multiple of FC: both checked by the launch);
+// window positions outside the layer output, rows past the batch and the slots past the windows
+// read the zero source.  Sums in the order above.
 template <int CI, int K, int FC, int NPX>
 __global__ __launch_bounds__(FT) void k_convT_first_dma(const float* __restrict__ A, float* __restrict__ C,
                                                         const float* __restrict__ W, int M, int Hi, int Wi, int Co,
-                                                        int Ho, int Wo, int p, int acc, FirstTile t, int RWP) {
+                                                        int Ho, int Wo, int p, int acc, FirstTile t, int NPE) {
     extern __shared__ float sm[];
     const int WY = t.TH + K - 1, WX = t.TW + K, win = WY * WX;
     const int per = t.TW / 2 * t.TH;
     const int rb = threadIdx.x / per, pix = threadIdx.x - rb * per;
     const int tile = blockIdx.x % (t.tiles_x * t.tiles_y);
-    const long r = (long)(blockIdx.x / (t.tiles_x * t.tiles_y)) * t.RB + rb;
+    const long rf = (long)(blockIdx.x / (t.tiles_x * t.tiles_y)) * t.RB;   // the block's first row (< M)
+    const long r = rf + rb;
     const int ty0 = (tile / t.tiles_x) * t.TH, tx0 = (tile % t.tiles_x) * t.TW;
     const int dy0 = pix / (t.TW / 2), dx0 = 2 * (pix % (t.TW / 2));
     const int Y = ty0 + dy0, X = tx0 + dx0;
-    const bool live = rb < t.RB;   // uniform per wavefront
+    const bool live = rb < t.RB;
     const bool act = live && r < M;
     const int y0 = ty0 + p - (K - 1), x0 = tx0 + p - (K - 1);
-    float* s_a = sm + (live ? rb : 0) * RWP;   // buffer 0 of this row; buffer 1 t.RB * RWP further
-    const int bstride = t.RB * RWP;
-    const float* Ar = A + (act ? r : 0) * (long)Co * Ho * Wo;
-    const int HoWo = Ho * Wo;
-    const float rWX = 1.f / (float)WX, rWY = 1.f / (float)WY;
-    const int RP = per / WX;   // >= 1 (checked by the launch)
-    const int srow = fdivs(pix, rWX), scol = pix - srow * WX;
-    const int sx = x0 + scol;
-    const bool sxok = r < M && sx >= 0 && sx < Wo;
-    const int nrr = FC * WY, NP = (nrr + RP - 1) / RP;
-    const int wbase = __builtin_amdgcn_readfirstlane(pix & ~63);
+    const int HoWo = Ho * Wo, CHW = Co * HoWo;
+    const float* Ab = A + rf * (long)CHW;
+    const float rwin = 1.f / (float)win, rWX = 1.f / (float)WX;
     const float* zero = g_first_zero + (threadIdx.x & 63);
-    int poff[NPX];   // offset of pass u's element from the stage's first channel plane, or -1
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63);
+    int poff[NPX];   // element threadIdx.x + u FT: offset from the stage's first channel plane, or -1
 #pragma unroll
     for (int u = 0; u < NPX; ++u) {
-        const int rr = srow + u * RP;
-        const int co = fdivs(rr, rWY), wy = rr - co * WY;
-        const int y = y0 + wy;
-        poff[u] = sxok && rr < nrr && y >= 0 && y < Ho ? co * HoWo + y * Wo + sx : -1;
+        const int e = threadIdx.x + u * FT;
+        const int pl = fdivs(e, rwin), w = e - pl * win;   // plane rb' FC + co, position in it
+        const int wy = fdivs(w, rWX), wx = w - wy * WX;
+        const int eb = pl / FC, co = pl - eb * FC;
+        const int y = y0 + wy, x = x0 + wx;
+        poff[u] = eb < t.RB && rf + eb < M && y >= 0 && y < Ho && x >= 0 && x < Wo
+                      ? eb * CHW + co * HoWo + y * Wo + x
+                      : -1;
     }
+    const int bstride = NPE * FT;   // floats per buffer
     auto stage = [&](int c0, float* buf) {
-        if (!live) return;
-        const float* base = Ar + (long)c0 * HoWo;
+        const float* base = Ab + (long)c0 * HoWo;
 #pragma unroll
         for (int u = 0; u < NPX; ++u)
-            if (u < NP)
-                __builtin_amdgcn_global_load_lds(poff[u] >= 0 ? base + poff[u] : zero, buf + wbase + u * RP * WX, 4,
-                                                 0, 0);
+            if (u < NPE)
+                __builtin_amdgcn_global_load_lds(poff[u] >= 0 ? base + poff[u] : zero, buf + wave + u * FT, 4, 0, 0);
     };
     float o0[CI], o1[CI];
 #pragma unroll
     for (int c = 0; c < CI; ++c) o0[c] = o1[c] = 0.f;
-    stage(0, s_a);
+    const float* ap = sm + (live ? rb : 0) * FC * win + dy0 * WX + dx0;
+    stage(0, sm);
     int cur = 0;
     for (int c0 = 0; c0 < Co; c0 += FC) {
         vmem_drain();      // this thread's loads of the stage have reached LDS
         __syncthreads();   // everyone's; and the other buffer's products are done
-        if (c0 + FC < Co) stage(c0 + FC, s_a + (cur ^ 1) * bstride);
-        if (live) convT_first_taps<CI, K>(s_a + cur * bstride + dy0 * WX + dx0, win, WX, W, c0, FC, o0, o1);
+        if (c0 + FC < Co) stage(c0 + FC, sm + (cur ^ 1) * bstride);
+        if (live) convT_first_taps<CI, K>(ap + cur * bstride, win, WX, W, c0, FC, o0, o1);
         cur ^= 1;
     }
     if (!act || Y >= Hi) return;
@@ -334,28 +331,23 @@ bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool
     const long blocks = (long)cdiv(M, t.RB) * t.tiles_x * t.tiles_y;
     MNB_CHECK(blocks < (1L << 31), MNB_EDEVICE, "first-layer transposed convolution: grid too large");
     {
-        // direct staging where a row block is whole wavefronts
-        constexpr int FCD = 4, NPX = 12;
-        const int per = t.TW / 2 * t.TH, WX = t.TW + 3, WY = t.TH + 2, RP = per / WX;
-        const int NP = RP > 0 ? cdiv(FCD * WY, RP) : 0;
-        if (per % 64 == 0 && RP > 0 && NP <= NPX && g.Co % FCD == 0 &&
-            (long)g.Co * g.Ho * g.Wo < (1L << 31)) {
-            const int RWP = std::max((NP - 1) * RP * WX + per, FCD * WY * WX);
-            const size_t lds = (size_t)2 * t.RB * RWP * sizeof(float);
-            if (lds <= 64 * 1024) {
+        // direct staging (the register-staged kernel below serves the remaining shapes)
+        constexpr int FCD = 4, NPX = 16;
+        const int NPE = cdiv(t.RB * FCD * (t.TH + 2) * (t.TW + 3), FT);
+        if (NPE <= NPX && g.Co % FCD == 0 && (long)t.RB * g.Co * g.Ho * g.Wo < (1L << 31)) {
+            const size_t lds = (size_t)2 * NPE * FT * sizeof(float);
 #define MNB_CTD(CI_)                                                                                                \
     hipLaunchKernelGGL((k_convT_first_dma<CI_, 3, FCD, NPX>), dim3((unsigned)blocks), dim3(FT), lds, st, A, C, g.W, M, \
-                       g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, RWP)
-                switch (g.Ci) {
-                    case 1: MNB_CTD(1); break;
-                    case 2: MNB_CTD(2); break;
-                    case 3: MNB_CTD(3); break;
-                    default: MNB_CTD(4); break;
-                }
-#undef MNB_CTD
-                MNB_HIP(hipGetLastError());
-                return true;
+                       g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, NPE)
+            switch (g.Ci) {
+                case 1: MNB_CTD(1); break;
+                case 2: MNB_CTD(2); break;
+                case 3: MNB_CTD(3); break;
+                default: MNB_CTD(4); break;
             }
+#undef MNB_CTD
+            MNB_HIP(hipGetLastError());
+            return true;
         }
     }
     const size_t lds = (size_t)t.RB * FCO * (t.TH + 2) * (t.TW + 3) * sizeof(float);
