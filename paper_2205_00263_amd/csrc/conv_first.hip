@@ -18,6 +18,7 @@ namespace mnb {
 constexpr int FT = 256;     // threads per workgroup
 constexpr int FCO = 8;      // transposed: layer output channels staged per step
 constexpr int SB = 8;       // staging loads in flight per thread
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 // Output tile of one row: TW x TH positions, each thread two horizontally adjacent ones
 // (TW even, TW / 2 * TH <= FT); RB rows per workgroup.
@@ -245,7 +246,7 @@ template <int CI, int K>
 __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, float* __restrict__ C,
                                                    const float* __restrict__ W, const float* __restrict__ bias, int M,
                                                    int Hi, int Wi, int Co, int Ho, int Wo, int p, int acc,
-                                                   FirstTile t, ConeClip clip) {
+                                                   FirstTile t, ConeClip clip, int st2) {
     extern __shared__ float sm[];
     const int WY = t.TH + K - 1, WX = t.TW + K, win = WY * WX;
     const int per = t.TW / 2 * t.TH;
@@ -319,8 +320,20 @@ __global__ __launch_bounds__(FT) void k_conv_first(const float* __restrict__ G, 
         float* o = Cr + (long)co * Ho * Wo;
         if (z0) s0 = 0.f;
         if (z1) s1 = 0.f;
-        if (x < Wo) o[0] = acc ? o[0] + s0 : s0;
-        if (two) o[1] = acc ? o[1] + s1 : s1;
+        if (st2) {
+            // even plane width, 8-byte aligned output: the pair is one aligned 8-byte word
+            if (x < Wo) {
+                f2 v = {s0, s1};
+                if (acc) {
+                    const f2 pv = *reinterpret_cast<const f2*>(o);
+                    v = f2{pv.x + s0, pv.y + s1};
+                }
+                *reinterpret_cast<f2*>(o) = v;
+            }
+        } else {
+            if (x < Wo) o[0] = acc ? o[0] + s0 : s0;
+            if (two) o[1] = acc ? o[1] + s1 : s1;
+        }
     }
 }
 
@@ -371,11 +384,12 @@ bool launch_conv_first(const ConvGeom& g, const float* G, float* C, int M, bool 
     if (M <= 0) return true;
     const FirstTile t = first_tile(g.Ho, g.Wo);
     const size_t lds = (size_t)t.RB * g.Ci * (t.TH + 2) * (t.TW + 3) * sizeof(float);
+    const int st2 = g.Wo % 2 == 0 && ((uintptr_t)C & 7) == 0;   // pairs as 8-byte stores
     const long blocks = (long)cdiv(M, t.RB) * t.tiles_x * t.tiles_y;
     MNB_CHECK(blocks < (1L << 31), MNB_EDEVICE, "first-layer convolution: grid too large");
 #define MNB_CF1(CI_)                                                                                              \
     hipLaunchKernelGGL((k_conv_first<CI_, 3>), dim3((unsigned)blocks), dim3(FT), lds, st, G, C, g.W, g.b, M, g.Hi,   \
-                       g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, clip ? *clip : ConeClip{})
+                       g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, clip ? *clip : ConeClip{}, st2)
     switch (g.Ci) {
         case 1: MNB_CF1(1); break;
         case 2: MNB_CF1(2); break;
