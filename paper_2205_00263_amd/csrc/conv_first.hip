@@ -180,12 +180,17 @@ __device__ float g_first_zero[64] = {};
 // layout).  An element's source offset within the stage's channels is the same for every stage
 // and is computed once (NPE <= NPX passes, Co a multiple of FC: both checked by the launch);
 // window positions outside the layer output, rows past the batch and the slots past the windows
-// read the zero source.  Sums in the order above.
-template <int CI, int K, int FC, int NPX>
+// read the zero source.  TWC > 0: the tile is TWC x THC (strides known to the compiler, whose
+// LDS reads then take them as immediate offsets).  Sums in the order above.
+template <int CI, int K, int FC, int NPX, int TWC, int THC>
 __global__ __launch_bounds__(FT) void k_convT_first_dma(const float* __restrict__ A, float* __restrict__ C,
                                                         const float* __restrict__ W, int M, int Hi, int Wi, int Co,
                                                         int Ho, int Wo, int p, int acc, FirstTile t, int NPE) {
     extern __shared__ float sm[];
+    if constexpr (TWC > 0) {
+        t.TW = TWC;
+        t.TH = THC;
+    }
     const int WY = t.TH + K - 1, WX = t.TW + K, win = WY * WX;
     const int per = t.TW / 2 * t.TH;
     const int rb = threadIdx.x / per, pix = threadIdx.x - rb * per;
@@ -206,6 +211,8 @@ __global__ __launch_bounds__(FT) void k_convT_first_dma(const float* __restrict_
     int poff[NPX];   // element threadIdx.x + u FT: offset from the stage's first channel plane, or -1
 #pragma unroll
     for (int u = 0; u < NPX; ++u) {
+        poff[u] = -1;
+        if (u >= NPE) continue;   // uniform
         const int e = threadIdx.x + u * FT;
         const int pl = fdivs(e, rwin), w = e - pl * win;   // plane rb' FC + co, position in it
         const int wy = fdivs(w, rWX), wx = w - wy * WX;
@@ -349,9 +356,15 @@ bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool
         const int NPE = cdiv(t.RB * FCD * (t.TH + 2) * (t.TW + 3), FT);
         if (NPE <= NPX && g.Co % FCD == 0 && (long)t.RB * g.Co * g.Ho * g.Wo < (1L << 31)) {
             const size_t lds = (size_t)2 * NPE * FT * sizeof(float);
-#define MNB_CTD(CI_)                                                                                                \
-    hipLaunchKernelGGL((k_convT_first_dma<CI_, 3, FCD, NPX>), dim3((unsigned)blocks), dim3(FT), lds, st, A, C, g.W, M, \
-                       g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, NPE)
+#define MNB_CTD_(CI_, TW_, TH_)                                                                          \
+    hipLaunchKernelGGL((k_convT_first_dma<CI_, 3, FCD, NPX, TW_, TH_>), dim3((unsigned)blocks), dim3(FT), lds, st, A, \
+                       C, g.W, M, g.Hi, g.Wi, g.Co, g.Ho, g.Wo, g.p, (int)accumulate, t, NPE)
+#define MNB_CTD(CI_)                                                                        \
+    if (t.TW == 32 && t.TH == 16) MNB_CTD_(CI_, 32, 16); /* whole 32-wide planes */            \
+    else if (t.TW == 16 && t.TH == 16) MNB_CTD_(CI_, 16, 16); /* windows of 16, 10 and 6 */    \
+    else if (t.TW == 10 && t.TH == 10) MNB_CTD_(CI_, 10, 10);                                 \
+    else if (t.TW == 6 && t.TH == 6) MNB_CTD_(CI_, 6, 6);                                     \
+    else MNB_CTD_(CI_, 0, 0)
             switch (g.Ci) {
                 case 1: MNB_CTD(1); break;
                 case 2: MNB_CTD(2); break;
@@ -359,6 +372,7 @@ bool launch_convT_first(const ConvGeom& g, const float* A, float* C, int M, bool
                 default: MNB_CTD(4); break;
             }
 #undef MNB_CTD
+#undef MNB_CTD_
             MNB_HIP(hipGetLastError());
             return true;
         }
