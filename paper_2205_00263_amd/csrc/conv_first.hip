@@ -35,8 +35,9 @@ static FirstTile first_tile(int H, int W) {
     return t;
 }
 
-// i / d for 0 <= i < 2^16, 0 < d <= 2^10 through a float reciprocal: (i + 0.5) / d lies at least
-// 0.5 / d from an integer, far above the rounding of the product.
+// i / d for 0 <= i < 2^16, d > 0 through a float reciprocal: (i + 0.5) / d lies at least 0.5 / d
+// from an integer, while the rounding of the reciprocal and of the product moves it by at most
+// about 2^-23 (i + 0.5) / d, below that for every i < 2^22.
 __device__ __forceinline__ int fdivs(int i, float rd) { return (int)(((float)i + 0.5f) * rd); }
 
 // The transposed convolution's products for one thread's output pair over nco staged channels:
