@@ -47,6 +47,8 @@ CONV_GEOMS = [  # (Ci, H, Co, k, s, p)
     (1, 12, 8, 3, 1, 1), (4, 7, 24, 3, 1, 1), (2, 40, 8, 3, 1, 1),
     # channel counts that leave a partial last stage (direct-staged and register-staged tiles)
     (3, 16, 6, 3, 1, 1), (2, 20, 10, 3, 1, 0),
+    # planes so small that a workgroup's windows need more staging passes than the direct form holds
+    (2, 4, 8, 3, 1, 1), (1, 3, 4, 3, 1, 1),
     # forward cones of ConvBig's second and third convolutions (padding 2)
     (32, 18, 32, 4, 2, 2), (32, 10, 64, 3, 1, 2),
 ]
