@@ -60,13 +60,17 @@ template <int BN> struct WinB { static constexpr int BNP = BN + 16; };   // filt
 template <int K, int S, int BM, int BN, int VEC, int NPH, int NSPLIT>
 __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
     constexpr int KK = K * K;
-    // NPH == 1: the four wavefronts split the tile's positions and channels (NSPLIT: channels
-    // only, each wavefront taking every position of the tile); NPH == 4: wavefront f computes the
-    // whole tile of stride phase f
-    constexpr int WAVES_N = NSPLIT ? 4 : NPH == 1 ? BN / 32 : 1;
+    // NPH == 1: the four wavefronts split the tile's positions and channels (NSPLIT 1: channels
+    // only, each wavefront taking every position of the tile; NSPLIT 2: two channel halves and the
+    // taps, wavefronts f and f + 2 taking every position of half f for the even and the odd taps,
+    // their partial tiles then summed in LDS); NPH == 4: wavefront f computes the whole tile of
+    // stride phase f
+    constexpr bool TSPLIT = NSPLIT == 2;
+    constexpr int WAVES_N = NSPLIT == 1 ? 4 : TSPLIT ? 2 : NPH == 1 ? BN / 32 : 1;
     constexpr int WAVES_M = NSPLIT ? 1 : NPH == 1 ? 4 / WAVES_N : 1;
-    constexpr int FN = NSPLIT ? BN / 64 : NPH == 1 ? 2 : BN / 16, FM = BM / (16 * WAVES_M);
-    static_assert(!NSPLIT || (NPH == 1 && FN >= 1 && FN * 64 == BN), "channel split");
+    constexpr int FN = NSPLIT == 1 ? BN / 64 : TSPLIT ? BN / 32 : NPH == 1 ? 2 : BN / 16, FM = BM / (16 * WAVES_M);
+    static_assert(NSPLIT != 1 || (NPH == 1 && FN >= 1 && FN * 64 == BN), "channel split");
+    static_assert(!TSPLIT || (NPH == 1 && FN * 32 == BN), "tap split");
     static_assert(FM >= 1 && FM * 16 * WAVES_M == BM, "tile");
     static_assert(NPH == 1 || (NPH == 4 && S == 1), "phases");
     constexpr int NLD = VEC == 4 ? NLD4 : NLD1;
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // wavefront's position and channel block (NPH == 4: the whole tile, for phase `wave`)
-    const int wm = NPH == 1 ? wave % WAVES_M : 0, wn = NPH == 1 ? wave / WAVES_M : 0;
+    const int wm = NPH == 1 ? wave % WAVES_M : 0, wn = TSPLIT ? (wave & 1) : NPH == 1 ? wave / WAVES_M : 0;
     constexpr int WNC = FN * 16;   // channels per wavefront
     const int r = blockIdx.x / a.mtiles, mt = blockIdx.x - r * a.mtiles;
     const int n0 = blockIdx.y * BN;
@@ -197,8 +201,9 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
         if (g + 1 < ng) MNB_WIN_LOAD(g + 1)
         // taps as a loop (not unrolled): unrolled, the compiler keeps every tap's LDS addresses in
         // registers across the stages, which halves the wavefronts a SIMD can hold
+        const int t_first = TSPLIT ? __builtin_amdgcn_readfirstlane(wave >> 1) : 0;
 #pragma unroll 1
-        for (int t = 0; t < KK; ++t) {
+        for (int t = t_first; t < KK; t += TSPLIT ? 2 : 1) {
             const int ky = t / K, kx = t - ky * K;
             const int tc = kx + c0p;
             const int toff = (ky + row_off) * a.RS + (tc % S) * a.WS + tc / S;
@@ -223,6 +228,31 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
             MNB_WIN_STORE()
             __syncthreads();
         }
+    }
+
+    if constexpr (TSPLIT) {
+        // the odd taps' partial tile added to the even taps' one (wavefront f + 2 to f) through LDS
+        // (the stages' space), lane-major so that consecutive lanes write consecutive words;
+        // wavefronts 0 and 1 store their channel halves
+        constexpr int TILE = FN * FM * 4 * 64;
+        __syncthreads();   // the last stage is consumed
+        float* red = sm + (wave & 1) * TILE;
+        if (wave >= 2) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) red[((j * FM + i) * 4 + v) * 64 + lane] = acc[j][i][v];
+        }
+        __syncthreads();
+        if (wave >= 2) return;
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[j][i][v] += red[((j * FM + i) * 4 + v) * 64 + lane];
     }
 
     // result lanes: channel n0 + wn*32 + 16 j + 4 (lane / 16) + v, position m0 + ... + lane % 16
@@ -328,9 +358,14 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     // wavefront, no idle tile), its filters staged once per row
     const bool grid = nph == 1 && BN == 64 && ks31 && P > 128 && P <= 144;
     if (w.only_grid && !grid) return false;
+    // stride-2 grids of 81 to 112 positions into 32 channels (ConvBig's 9x9 and 10x10 forward cones):
+    // one tile of 96 or 112 positions per row, held whole by every wavefront, the taps split
+    // across the wavefronts (a 128-position tile would leave 22-37% of its lanes idle)
+    const bool tsplit = nph == 1 && BN == 32 && ks42 && P > 80 && P <= 112;
     // otherwise positions per workgroup: 128, unless 64 wastes fewer lanes on the last tile (or a
     // wavefront holding a whole tile of 64 channels would need more accumulators)
-    const int BM = grid ? 144 : cdiv(P, 64) * 64 < cdiv(P, 128) * 128 || (nph == 4 && BN == 64) ? 64 : 128;
+    const int BM = grid ? 144 : tsplit ? (P <= 96 ? 96 : 112)
+                 : cdiv(P, 64) * 64 < cdiv(P, 128) * 128 || (nph == 4 && BN == 64) ? 64 : 128;
     // phases in one workgroup: the window spans every phase's rows and columns
     int py = w.py, px = w.px, extra = 0;
     if (nph == 4) {
@@ -381,7 +416,8 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     }
     a.PL = best;
     const int BNP = BN + 16;
-    const size_t lds = ((size_t)nph * K * K * CG * BNP + (size_t)CG * a.PL) * sizeof(float);
+    size_t lds = ((size_t)nph * K * K * CG * BNP + (size_t)CG * a.PL) * sizeof(float);
+    if (tsplit) lds = std::max(lds, (size_t)2 * (BN / 32) * (BM / 16) * 4 * 64 * sizeof(float));   // partial tiles
     if (lds > WIN_LDS_MAX) return false;
     // window loads per thread and stage
     const int Q = vec ? w.Wi / 4 : w.Wi;
@@ -394,6 +430,14 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     if (grid) {
         if (vec) hipLaunchKernelGGL((k_conv_win<3, 1, 144, 64, 4, 1, 1>), dgrid, blk, lds, st, a);
         else hipLaunchKernelGGL((k_conv_win<3, 1, 144, 64, 1, 1, 1>), dgrid, blk, lds, st, a);
+        MNB_HIP(hipGetLastError());
+        return true;
+    }
+    if (tsplit) {
+        if (BM == 112) { if (vec) hipLaunchKernelGGL((k_conv_win<4, 2, 112, 32, 4, 1, 2>), dgrid, blk, lds, st, a);
+                         else hipLaunchKernelGGL((k_conv_win<4, 2, 112, 32, 1, 1, 2>), dgrid, blk, lds, st, a); }
+        else { if (vec) hipLaunchKernelGGL((k_conv_win<4, 2, 96, 32, 4, 1, 2>), dgrid, blk, lds, st, a);
+               else hipLaunchKernelGGL((k_conv_win<4, 2, 96, 32, 1, 1, 2>), dgrid, blk, lds, st, a); }
         MNB_HIP(hipGetLastError());
         return true;
     }

@@ -93,7 +93,7 @@ def test_conv_kernels_match_oracle(geom):
 
 WIN_GEOMS = [  # (Ci, H, Co, k, s, p): input-window kernels, whole tiles and ragged ones
     (32, 32, 32, 4, 2, 1), (32, 16, 64, 3, 1, 1), (64, 16, 64, 4, 2, 1),     # ConvBig, float4 staging
-    (32, 18, 32, 4, 2, 2), (32, 10, 64, 3, 1, 2),                           # its forward cones
+    (32, 18, 32, 4, 2, 2), (32, 16, 32, 4, 2, 2), (32, 10, 64, 3, 1, 2),    # its forward cones
     (16, 13, 32, 4, 2, 0), (8, 20, 96, 3, 1, 1), (8, 24, 128, 3, 1, 0),      # ragged tiles, channel tiles
     (16, 12, 32, 4, 2, 3), (16, 16, 32, 3, 2, 1), (16, 14, 32, 3, 1, 1),      # rows of 2 mod 4 floats
     (64, 32, 32, 4, 2, 1), (32, 40, 64, 4, 2, 1), (32, 16, 32, 3, 1, 1),     # transposed: 2x2 and 3x3 phases
