@@ -358,13 +358,15 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
     // wavefront, no idle tile), its filters staged once per row
     const bool grid = nph == 1 && BN == 64 && ks31 && P > 128 && P <= 144;
     if (w.only_grid && !grid) return false;
-    // stride-2 grids of 81 to 112 positions into 32 channels (ConvBig's 9x9 and 10x10 forward cones):
-    // one tile of 96 or 112 positions per row, held whole by every wavefront, the taps split
-    // across the wavefronts (a 128-position tile would leave 22-37% of its lanes idle)
-    const bool tsplit = nph == 1 && BN == 32 && ks42 && P > 80 && P <= 112;
+    // stride-2 grids of 81 to 112 positions and 3x3 / 1 grids of at most 48 into 32 channels
+    // (ConvBig's 10x10 forward cones, its 6x6 transposed windows): one tile of 16 P / 16 positions
+    // per row (96 or 112 for the stride-2 ones), each wavefront pair holding every position of its
+    // channel half, the taps split between the pair (a 64- or 128-position tile would leave 22-75%
+    // of its lanes idle)
+    const bool tsplit = nph == 1 && BN == 32 && ((ks42 && P > 80 && P <= 112) || (ks31 && P <= 48));
     // otherwise positions per workgroup: 128, unless 64 wastes fewer lanes on the last tile (or a
     // wavefront holding a whole tile of 64 channels would need more accumulators)
-    const int BM = grid ? 144 : tsplit ? (P <= 96 ? 96 : 112)
+    const int BM = grid ? 144 : tsplit ? (ks42 ? (P <= 96 ? 96 : 112) : cdiv(P, 16) * 16)
                  : cdiv(P, 64) * 64 < cdiv(P, 128) * 128 || (nph == 4 && BN == 64) ? 64 : 128;
     // phases in one workgroup: the window spans every phase's rows and columns
     int py = w.py, px = w.px, extra = 0;
@@ -434,10 +436,14 @@ bool launch_win(const WinConv& w, int M, bool accumulate, hipStream_t st, bool c
         return true;
     }
     if (tsplit) {
-        if (BM == 112) { if (vec) hipLaunchKernelGGL((k_conv_win<4, 2, 112, 32, 4, 1, 2>), dgrid, blk, lds, st, a);
-                         else hipLaunchKernelGGL((k_conv_win<4, 2, 112, 32, 1, 1, 2>), dgrid, blk, lds, st, a); }
-        else { if (vec) hipLaunchKernelGGL((k_conv_win<4, 2, 96, 32, 4, 1, 2>), dgrid, blk, lds, st, a);
-               else hipLaunchKernelGGL((k_conv_win<4, 2, 96, 32, 1, 1, 2>), dgrid, blk, lds, st, a); }
+#define MNB_WINT(K_, S_, BM_) \
+    if (vec) hipLaunchKernelGGL((k_conv_win<K_, S_, BM_, 32, 4, 1, 2>), dgrid, blk, lds, st, a); \
+    else hipLaunchKernelGGL((k_conv_win<K_, S_, BM_, 32, 1, 1, 2>), dgrid, blk, lds, st, a)
+        if (ks42) { if (BM == 112) { MNB_WINT(4, 2, 112); } else { MNB_WINT(4, 2, 96); } }
+        else if (BM == 16) { MNB_WINT(3, 1, 16); }
+        else if (BM == 32) { MNB_WINT(3, 1, 32); }
+        else { MNB_WINT(3, 1, 48); }
+#undef MNB_WINT
         MNB_HIP(hipGetLastError());
         return true;
     }

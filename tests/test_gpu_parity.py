@@ -97,6 +97,8 @@ WIN_GEOMS = [  # (Ci, H, Co, k, s, p): input-window kernels, whole tiles and rag
     (16, 13, 32, 4, 2, 0), (8, 20, 96, 3, 1, 1), (8, 24, 128, 3, 1, 0),      # ragged tiles, channel tiles
     (16, 12, 32, 4, 2, 3), (16, 16, 32, 3, 2, 1), (16, 14, 32, 3, 1, 1),      # rows of 2 mod 4 floats
     (64, 32, 32, 4, 2, 1), (32, 40, 64, 4, 2, 1), (32, 16, 32, 3, 1, 1),     # transposed: 2x2 and 3x3 phases
+    (32, 6, 64, 3, 1, 1), (32, 6, 96, 3, 1, 1), (32, 5, 96, 3, 1, 1),        # transposed: 3x3 grids of 36, 25
+    (32, 4, 96, 3, 1, 1),                                                     # and 16 positions into 32 channels
 ]
 
 
