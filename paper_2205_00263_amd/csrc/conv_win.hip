@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_conv_win(ConvWinArgs a) {
                 for (int v = 0; v < 4; ++v) acc[j][i][v] += red[((j * FM + i) * 4 + v) * 64 + lane];
     }
 
-    // result lanes: channel n0 + wn*32 + 16 j + 4 (lane / 16) + v, position m0 + ... + lane % 16
+    // result lanes: channel n0 + wn WNC + 16 j + 4 (lane / 16) + v, position m0 + ... + lane % 16
 #undef MNB_WIN_LOAD
 #undef MNB_WIN_STORE
     float bias[FN][4];
