@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_relu_relax(RelaxArgs a) {
     NeuronRelax nr = neuron_relax(a.l[so], a.u[so], s, a.alpha[po]);
     float da = 0.f, sh = 0.f, sg = 0.f;
     // rows in groups of RR with all of a group's loads in flight together; sums in row order
-    constexpr int RR = 8;
+    constexpr int RR = 16;
     for (int r0 = in.r0; r0 < in.r1; r0 += RR) {
         float ghv[RR], apv[RR];
 #pragma unroll
